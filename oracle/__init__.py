@@ -1,0 +1,195 @@
+"""FP64 CPU oracle for SpAMM (Challacombe & Bock, section 2, Eqs. 1 and 4).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU
+baseline of the benchmark may import this package; the product path (the HIP
+library and its Python binding) never does and shares no code with it.
+
+The heavy loops live in ``spamm_oracle.c`` (plain C, FP64, built with gcc and
+-ffp-contract=off); this module marshals numpy arrays to it.  The TC2
+purification driver and the tau-model pieces are in ``sp2.py`` and
+``tau_model.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "spamm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_CFLAGS = ["-O3", "-mavx2", "-mfma", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+           "-std=c11", "-Wall"]
+
+_lib = None
+_DP = ctypes.POINTER(ctypes.c_double)
+_U64P = ctypes.POINTER(ctypes.c_uint64)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (always when force, else only if missing)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *_CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.orc_tile_sqnorms.argtypes = [_DP, i64, i64, i32, _DP]
+    lib.orc_tile_sqnorms.restype = ctypes.c_int
+    lib.orc_norm_parent.argtypes = [_DP, i64, _DP]
+    lib.orc_norm_parent.restype = None
+    lib.orc_num_levels.argtypes = [i64]
+    lib.orc_num_levels.restype = i32
+    lib.orc_spamm_recursive.argtypes = [_DP, _DP, i64, i32, dbl, _DP, _U64P, i64, _I64P]
+    lib.orc_spamm_recursive.restype = i64
+    lib.orc_spamm_flat.argtypes = [_DP, _DP, i64, i32, dbl, i64, i64, _DP]
+    lib.orc_spamm_flat.restype = i64
+    lib.orc_tasks_flat.argtypes = [_DP, _DP, i64, dbl, _U64P, i64, _DP]
+    lib.orc_tasks_flat.restype = i64
+    lib.orc_count_hierarchical.argtypes = [_DP, _DP, i64, dbl, _I64P]
+    lib.orc_count_hierarchical.restype = i64
+    lib.orc_dense_matmul.argtypes = [_DP, _DP, i64, _DP]
+    lib.orc_dense_matmul.restype = None
+    lib.orc_num_threads.argtypes = []
+    lib.orc_num_threads.restype = i32
+    _lib = lib
+    return lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a, t=_DP):
+    return a.ctypes.data_as(t)
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def num_levels(nb: int) -> int:
+    """Tiers above the leaves: m_0 = nb, m_{l+1} = ceil(m_l / 2), m_L = 1."""
+    return int(_load().orc_num_levels(nb))
+
+
+def tile_sqnorms(a, b: int) -> np.ndarray:
+    """Canonical FP64 squared Frobenius norms of the b x b leaves, shape (nb, nb)."""
+    a = _f64(a)
+    n = a.shape[0]
+    nb = -(-n // b)
+    out = np.empty((nb, nb), dtype=np.float64)
+    rc = _load().orc_tile_sqnorms(_p(a), n, a.shape[1], b, _p(out))
+    if rc:
+        raise ValueError(f"orc_tile_sqnorms failed ({rc})")
+    return out
+
+
+def norm_parent(S) -> np.ndarray:
+    S = _f64(S)
+    m = S.shape[0]
+    mp = -(-m // 2)
+    out = np.empty((mp, mp), dtype=np.float64)
+    _load().orc_norm_parent(_p(S), m, _p(out))
+    return out
+
+
+def norm_pyramid(a, b: int) -> list[np.ndarray]:
+    """[S_0 (leaves), S_1, ..., S_L (root, 1x1)] of the quadtree (Eq. 1)."""
+    levels = [tile_sqnorms(a, b)]
+    while levels[-1].shape[0] > 1:
+        levels.append(norm_parent(levels[-1]))
+    return levels
+
+
+def spamm_recursive(a, bm, b: int, tau: float, want_keys: bool = False):
+    """Eq. (4) literally.  Returns (C, T, keys-or-None, kept-per-tier)."""
+    a, bm = _f64(a), _f64(bm)
+    n = a.shape[0]
+    nb = -(-n // b)
+    L = num_levels(nb)
+    c = np.empty((n, n), dtype=np.float64)
+    kept = np.zeros(L + 1, dtype=np.int64)
+    cap = nb ** 3 if want_keys else 0
+    keys = np.empty(max(cap, 1), dtype=np.uint64)
+    t = _load().orc_spamm_recursive(_p(a), _p(bm), n, b, float(tau), _p(c),
+                                    _p(keys, _U64P) if want_keys else None, cap, _p(kept, _I64P))
+    if t < 0:
+        raise ValueError(f"orc_spamm_recursive failed ({t})")
+    return c, int(t), (keys[:t].copy() if want_keys else None), kept
+
+
+def spamm_flat(a, bm, b: int, tau: float, rows: tuple[int, int] | None = None):
+    """Flat enumeration of kept leaf triples; returns (C, T).
+
+    rows = (I0, I1) restricts the work to C tile rows [I0, I1); the other rows
+    of the returned C are zero."""
+    a, bm = _f64(a), _f64(bm)
+    n = a.shape[0]
+    nb = -(-n // b)
+    I0, I1 = rows if rows is not None else (0, nb)
+    c = np.zeros((n, n), dtype=np.float64)
+    t = _load().orc_spamm_flat(_p(a), _p(bm), n, b, float(tau), I0, I1, _p(c))
+    if t < 0:
+        raise ValueError(f"orc_spamm_flat failed ({t})")
+    return c, int(t)
+
+
+def tasks_flat(SA, SB, tau: float, want_keys: bool = True):
+    """Brute-force kept triples from leaf norms.  Returns (keys sorted, bound)."""
+    SA, SB = _f64(SA), _f64(SB)
+    nb = SA.shape[0]
+    cap = nb ** 3 if want_keys else 0
+    keys = np.empty(max(cap, 1), dtype=np.uint64)
+    bound = ctypes.c_double(0.0)
+    t = _load().orc_tasks_flat(_p(SA), _p(SB), nb, float(tau),
+                               _p(keys, _U64P) if want_keys else None, cap, ctypes.byref(bound))
+    return (keys[:t].copy() if want_keys else int(t)), float(bound.value)
+
+
+def count_hierarchical(SA, SB, tau: float):
+    """Kept octree nodes per tier (tier 0 = leaf triples) from leaf norms."""
+    SA, SB = _f64(SA), _f64(SB)
+    nb = SA.shape[0]
+    kept = np.zeros(num_levels(nb) + 1, dtype=np.int64)
+    t = _load().orc_count_hierarchical(_p(SA), _p(SB), nb, float(tau), _p(kept, _I64P))
+    return int(t), kept
+
+
+def dense_matmul(a, bm) -> np.ndarray:
+    a, bm = _f64(a), _f64(bm)
+    n = a.shape[0]
+    c = np.empty((n, n), dtype=np.float64)
+    _load().orc_dense_matmul(_p(a), _p(bm), n, _p(c))
+    return c
+
+
+def unpack_keys(keys):
+    keys = np.asarray(keys, dtype=np.uint64)
+    m21 = np.uint64((1 << 21) - 1)
+    return ((keys >> np.uint64(42)) & m21).astype(np.int64), \
+        ((keys >> np.uint64(21)) & m21).astype(np.int64), (keys & m21).astype(np.int64)
+
+
+def pack_keys(I, J, K):
+    I, J, K = (np.asarray(x, dtype=np.uint64) for x in (I, J, K))
+    return (I << np.uint64(42)) | (J << np.uint64(21)) | K
+
+
+def rel_err(c_approx, c_exact) -> float:
+    """||C~ - C||_F / ||C||_F in FP64."""
+    d = np.asarray(c_approx, dtype=np.float64) - np.asarray(c_exact, dtype=np.float64)
+    den = np.linalg.norm(np.asarray(c_exact, dtype=np.float64))
+    return float(np.linalg.norm(d) / den) if den > 0 else float(np.linalg.norm(d))
