@@ -1,0 +1,228 @@
+/*
+ * spamm.h -- C ABI of the MI355X (gfx950) Sparse Approximate Matrix Multiply.
+ *
+ * Method: Challacombe & Bock, "Fast Multiplication of Matrices with Decay"
+ * (arXiv:1011.3534).  A matrix is held as a quadtree (section 2, Eq. 1):
+ * 2x2 recursive blocking down to dense b x b leaves, with the Frobenius norm
+ * (section 3) carried at every node.  The product C = A B is formed by the
+ * SpAMM recursion of Eq. (4): a block product is dropped when
+ * ||A^k|| ||B^k|| < tau, taken densely at the leaves, and otherwise assembled
+ * from its 8 sub-products.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  - All functions return spamm_status; SPAMM_OK (0) on success.  Nothing is
+ *    thrown or aborted across the ABI.  On a non-OK status
+ *    spamm_last_error() returns a thread-local message.
+ *  - Arguments are validated on the host before anything is enqueued; a
+ *    SPAMM_EINVAL return leaves every output untouched.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it in order; calls do not synchronise the device
+ *    except where stated (non-NULL stats/log pointers, the host read-back
+ *    helpers).
+ *  - Device pointers are caller-owned, are read in stream order and may be
+ *    released once the stream has passed the call.  spamm_matrix handles are
+ *    library-owned and released with spamm_free().
+ *  - Norms are FP64 squared Frobenius norms S; the cull test is
+ *    fl(S_A * S_B) < fl(tau * tau) (ties kept), so no square root decides a
+ *    product.  A leaf's S is summed in a fixed order: per column, over rows
+ *    in ascending order with fused multiply-add; then over columns by the
+ *    pairwise tree s_c += s_{c+h}, h = b/2 .. 1.  A parent's S is
+ *    (S_00 + S_01) + (S_10 + S_11), absent children counting +0.
+ *  - The kept leaf triples (I, J, K) are therefore fixed by the stored input
+ *    values, the leaf size and tau alone -- not by leaf precision, schedule or
+ *    padding -- and equal the flat rule keep <=> !(S_A[I,K] S_B[K,J] < tau^2)
+ *    (the tier tests are monotone because parent norms dominate children).
+ */
+#ifndef SPAMM_H
+#define SPAMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spamm_matrix spamm_matrix;
+
+typedef enum {
+    SPAMM_OK = 0,
+    SPAMM_EINVAL = 1,       /* invalid argument (nothing enqueued)                  */
+    SPAMM_ENOMEM = 2,       /* device allocation failed                             */
+    SPAMM_EHIP = 3,         /* a HIP runtime call failed (message names it)         */
+    SPAMM_ECAPACITY = 4,    /* a device-side buffer would overflow                  */
+    SPAMM_ENONFINITE = 5,   /* a non-finite norm was met (inf/nan in an operand)    */
+    SPAMM_ENOCONV = 6,      /* SP2 did not meet its stopping rule within max_iter   */
+    SPAMM_EUNSUPPORTED = 7  /* valid request this build does not implement          */
+} spamm_status;
+
+/* Element type of the caller's dense matrix and of the stored tiles. */
+typedef enum { SPAMM_F64 = 0, SPAMM_F32 = 1 } spamm_dtype;
+
+/* Arithmetic of the dense leaf products (section 3 uses single precision
+ * 4x4 products; the MFMA variants here accumulate in FP32, FP64 in FP64).
+ *   F64    : FP64 inputs, FP64 MFMA, FP64 result (also the exact judge)
+ *   F32    : FP32 MFMA, FP32 result
+ *   BF16   : operands rounded to bfloat16 (RNE), FP32 accumulation
+ *   BF16X3 : x = hi + lo with hi = bf16(x), lo = bf16(x - hi); the product
+ *            hi*hi + hi*lo + lo*hi on bf16 MFMA (lo*lo dropped)
+ *   F16    : operands scaled per tile by a power of two, rounded to fp16
+ *   F16X3  : as BF16X3 with fp16 halves of the per-tile power-of-two scaled
+ *            operand; the scale is undone exactly after each leaf product.
+ * The result of every precision other than F64 is stored as FP32. */
+typedef enum {
+    SPAMM_LEAF_F64 = 0,
+    SPAMM_LEAF_F32 = 1,
+    SPAMM_LEAF_BF16 = 2,
+    SPAMM_LEAF_BF16X3 = 3,
+    SPAMM_LEAF_F16 = 4,
+    SPAMM_LEAF_F16X3 = 5
+} spamm_leaf_prec;
+
+#define SPAMM_MAX_LEVELS 24
+
+/* Statistics of one product (filled by a syncing call). */
+typedef struct {
+    int64_t n;                                /* matrix dimension                              */
+    int32_t leaf;                             /* leaf size b                                   */
+    int32_t levels;                           /* tiers above the leaves, L = ceil(log2 nb)     */
+    int64_t nb;                               /* leaves per dimension, ceil(n / b)             */
+    int64_t survivors[SPAMM_MAX_LEVELS];      /* kept octree nodes per tier (0 = leaf triples) */
+    int64_t tasks;                            /* leaf products T (= survivors[0])              */
+    int64_t nonempty_tiles;                   /* C tiles with at least one kept product        */
+    double flops;                             /* algorithmic leaf flops 2 b^3 T                */
+    double culled_bound;                      /* sum over culled octree nodes of
+                                                 ||A^k||_F ||B^k||_F (Eq. 3 bound on ||dC||_F) */
+} spamm_stats;
+
+/* Per-iteration record of spamm_sp2. */
+#define SPAMM_SP2_MAX_ITER 256
+typedef struct {
+    int32_t iterations;                       /* steps executed                                */
+    int32_t converged;                        /* 1: ||X^2-X||_F <= idem_tol was met            */
+    int32_t stagnated;                        /* 1: stopped by the stagnation rule             */
+    int32_t result_step;                      /* P = X_{result_step}                           */
+    double trace[SPAMM_SP2_MAX_ITER];         /* tr(X_m), FP64                                 */
+    double idem[SPAMM_SP2_MAX_ITER];          /* ||X_m^2 - X_m||_F, FP64                       */
+    int32_t branch[SPAMM_SP2_MAX_ITER];       /* 0: X <- X^2, 1: X <- 2X - X^2                 */
+    int64_t tasks[SPAMM_SP2_MAX_ITER];        /* leaf products of step m                       */
+    double final_trace;                       /* tr(P)                                         */
+    double energy;                            /* tr(P H), FP64                                 */
+    double eps_min, eps_max;                  /* Gershgorin bounds of H                        */
+} spamm_sp2_log;
+
+/* ------------------------------------------------------------------ build */
+
+/* Quadtree representation of a dense matrix (section 2, Eq. 1).
+ *   dev_a : device pointer, n x n row-major, leading dimension lda (elements)
+ *   dt    : element type of dev_a; the tiles are stored in the same type
+ *   leaf  : b in {32, 64, 128}
+ *   out   : receives a new handle: zero-padded tile-major storage (b x b
+ *           tiles, row-major inside, tiles in (I, K) row-major order) and the
+ *           FP64 squared-norm pyramid of all tiers.
+ * One pass over dev_a computes the packed tiles and the leaf norms; the
+ * upper tiers follow.  Errors: EINVAL (n < 1, lda < n, bad leaf/dtype, null
+ * pointers), ENOMEM, EHIP. */
+spamm_status spamm_build(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf,
+                         void* stream, spamm_matrix** out);
+
+/* ------------------------------------------------------------------ multiply */
+
+/* C ~= A B by Eq. (4) with absolute threshold tau.
+ *   A, B  : handles with equal n and leaf (dtypes may differ; F64 leaves
+ *           promote FP32 tiles exactly)
+ *   tau   : finite, tau == 0 (dense product) or tau >= 1e-150
+ *   prec  : leaf arithmetic (spamm_leaf_prec)
+ *   C     : in/out.  If *C is NULL a new handle is allocated.  If *C is a
+ *           handle of the same n, leaf and result type it is overwritten in
+ *           place, reusing its product scratch (no allocation).  C may not
+ *           alias A or B.
+ *   st    : optional; when non-NULL the call synchronises the stream and
+ *           fills the statistics.
+ * The result carries its own norm pyramid, so it can be an operand of the
+ * next product.  Every C tile with no kept product is exactly zero.
+ * Errors: EINVAL, ENOMEM, EHIP, ENONFINITE (reported through st). */
+spamm_status spamm_multiply(const spamm_matrix* A, const spamm_matrix* B, double tau,
+                            spamm_leaf_prec prec, void* stream, spamm_matrix** C,
+                            spamm_stats* st);
+
+/* count independent products C_m ~= A_m B_m in one pass: one cull over every
+ * root and ONE persistent leaf-product launch over the union of all C tiles
+ * (largest work first).  All operands share the leaf size and leaf
+ * precision; n may differ between products.
+ *   tau[m]       : per-product threshold (host array of count doubles)
+ *   C[m]         : in/out as for spamm_multiply
+ *   st           : optional host array of count spamm_stats (syncs)
+ * Errors: EINVAL (count < 1 or > 128, mismatched pairs), ENOMEM, EHIP. */
+spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
+                                    const spamm_matrix* const* B, const double* tau,
+                                    spamm_leaf_prec prec, void* stream, spamm_matrix** C,
+                                    spamm_stats* st);
+
+/* ------------------------------------------------------------------ SP2 / TC2 */
+
+/* Density matrix P = theta[mu I - H] with n_occ occupied states by TC2
+ * purification (section 3; Niklasson 2002), every squaring a SpAMM at tau:
+ *   X_0 = (eps_max I - H)/(eps_max - eps_min) from Gershgorin bounds (FP64);
+ *   step m: Y = SpAMM(X_m, X_m); X_{m+1} = Y if tr(X_m) > n_occ else 2X_m - Y;
+ *           e_m = ||Y - X_m||_F; traces and e_m in FP64 on the device;
+ *   stop after the step with e_m <= idem_tol (P = X_{m+1}), or when
+ *   e_m >= e_{m-2} while e_{m-2} < 0.1 (stagnation; P = X_m), or after
+ *   max_iter steps.
+ * All max_iter steps are captured in one hipGraph; steps after the stop are
+ * no-ops decided on the device, so the host synchronises once.
+ *   H       : symmetric operand (FP32 or FP64 tiles)
+ *   prec    : leaf arithmetic of the squarings (not F64 unless H is FP64)
+ *   P       : receives a new handle
+ *   log     : optional per-step record
+ * Errors: EINVAL (n_occ outside [0, n], max_iter outside [1, 256]), ENOMEM,
+ * EHIP, ENOCONV (no stop rule met; P then holds X_max_iter). */
+spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t max_iter,
+                       double idem_tol, spamm_leaf_prec prec, void* stream, spamm_matrix** P,
+                       spamm_sp2_log* log);
+
+/* ------------------------------------------------------------------ helpers */
+
+/* Dense row-major copy of M (n x n, leading dimension ldo, M's element type)
+ * into caller-owned device memory. */
+spamm_status spamm_to_dense(const spamm_matrix* M, void* dev_out, int64_t ldo, void* stream);
+
+/* Shape queries. */
+spamm_status spamm_info(const spamm_matrix* M, int64_t* n, int32_t* leaf, spamm_dtype* dt,
+                        int32_t* levels);
+
+/* Squared norms of tier `level` (0 = leaves) copied to host_out
+ * (m_l x m_l row-major, m_l = ceil(nb / 2^level)); cap in elements.
+ * Synchronises the stream. */
+spamm_status spamm_norms(const spamm_matrix* M, int32_t level, double* host_out, int64_t cap,
+                         void* stream);
+
+/* The kept leaf triples of the product that last wrote C, as keys
+ * I << 42 | J << 21 | K, sorted ascending, copied to host (up to cap);
+ * *count receives T.  Synchronises the stream. */
+spamm_status spamm_task_list(const spamm_matrix* C, uint64_t* host_keys, int64_t cap,
+                             int64_t* count, void* stream);
+
+/* ||X - Y||_F^2 and ||Y||_F^2 in FP64 over two handles of equal n (any
+ * element types), e.g. X = SpAMM result, Y = exact product.  Synchronises. */
+spamm_status spamm_diff_norms(const spamm_matrix* X, const spamm_matrix* Y, double* diff2,
+                              double* ref2, void* stream);
+
+/* Device allocation hook.  alloc(bytes, ctx) returns device memory or NULL;
+ * dealloc(ptr, ctx) releases it.  NULL functions restore hipMalloc/hipFree.
+ * Handles keep the pair they were allocated with. */
+typedef void* (*spamm_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*spamm_dealloc_fn)(void* ptr, void* ctx);
+spamm_status spamm_set_allocator(spamm_alloc_fn alloc, spamm_dealloc_fn dealloc, void* ctx);
+
+/* Release a handle (NULL is a no-op).  Synchronises the handle's last stream. */
+void spamm_free(spamm_matrix* M);
+
+/* Thread-local description of the last non-OK status. */
+const char* spamm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPAMM_H */

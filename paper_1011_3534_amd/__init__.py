@@ -1,0 +1,276 @@
+"""Python binding of libspamm: the MI355X SpAMM (Challacombe & Bock, section 2).
+
+Argument marshalling only: every step of the multiply runs in the HIP
+library; PyTorch provides device memory (its caching allocator backs the
+library's allocations) and the stream.  The binding refuses to work without
+the built library -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspamm.so")
+
+LEAF = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3, "f16": 4, "f16x3": 5}
+LEAF_NAMES = {v: k for k, v in LEAF.items()}
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ECAPACITY", 5: "ENONFINITE",
+          6: "ENOCONV", 7: "EUNSUPPORTED"}
+MAX_LEVELS = 24
+SP2_MAX_ITER = 256
+
+
+class SpammError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("leaf", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("nb", ctypes.c_int64), ("survivors", ctypes.c_int64 * MAX_LEVELS),
+                ("tasks", ctypes.c_int64), ("nonempty_tiles", ctypes.c_int64),
+                ("flops", ctypes.c_double), ("culled_bound", ctypes.c_double)]
+
+    def to_dict(self):
+        return {"n": self.n, "leaf": self.leaf, "levels": self.levels, "nb": self.nb,
+                "survivors": [int(self.survivors[i]) for i in range(self.levels + 1)],
+                "tasks": int(self.tasks), "nonempty_tiles": int(self.nonempty_tiles),
+                "flops": float(self.flops), "culled_bound": float(self.culled_bound)}
+
+
+class Sp2Log(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("stagnated", ctypes.c_int32), ("result_step", ctypes.c_int32),
+                ("trace", ctypes.c_double * SP2_MAX_ITER), ("idem", ctypes.c_double * SP2_MAX_ITER),
+                ("branch", ctypes.c_int32 * SP2_MAX_ITER), ("tasks", ctypes.c_int64 * SP2_MAX_ITER),
+                ("final_trace", ctypes.c_double), ("energy", ctypes.c_double),
+                ("eps_min", ctypes.c_double), ("eps_max", ctypes.c_double)]
+
+    def to_dict(self):
+        k = self.iterations
+        return {"iterations": k, "converged": bool(self.converged), "stagnated": bool(self.stagnated),
+                "result_step": int(self.result_step),
+                "trace": [self.trace[i] for i in range(k)], "idem": [self.idem[i] for i in range(k)],
+                "branch": [int(self.branch[i]) for i in range(k)],
+                "tasks": [int(self.tasks[i]) for i in range(k)],
+                "final_trace": self.final_trace, "energy": self.energy,
+                "eps_min": self.eps_min, "eps_max": self.eps_max}
+
+
+_lib = None
+_alloc_cb = None
+_dealloc_cb = None
+_VP = ctypes.c_void_p
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_DEALLOC_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def lib():
+    """Load libspamm.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1011_3534_amd.hipbuild`")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    PP = ctypes.POINTER(_VP)
+    sig = {
+        "spamm_build": ([_VP, i64, i64, i32, i32, _VP, PP], i32),
+        "spamm_multiply": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Stats)], i32),
+        "spamm_multiply_batched": ([i32, PP, PP, ctypes.POINTER(dbl), i32, _VP, PP, ctypes.POINTER(Stats)], i32),
+        "spamm_sp2": ([_VP, i64, dbl, i32, dbl, i32, _VP, PP, ctypes.POINTER(Sp2Log)], i32),
+        "spamm_to_dense": ([_VP, _VP, i64, _VP], i32),
+        "spamm_info": ([_VP, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                        ctypes.POINTER(i32)], i32),
+        "spamm_norms": ([_VP, i32, ctypes.POINTER(dbl), i64, _VP], i32),
+        "spamm_task_list": ([_VP, ctypes.POINTER(ctypes.c_uint64), i64, ctypes.POINTER(i64), _VP], i32),
+        "spamm_diff_norms": ([_VP, _VP, ctypes.POINTER(dbl), ctypes.POINTER(dbl), _VP], i32),
+        "spamm_set_allocator": ([_ALLOC_FN, _DEALLOC_FN, _VP], i32),
+        "spamm_free": ([_VP], None),
+        "spamm_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def declared_symbols() -> list[str]:
+    """Function names declared in include/*.h (the ABI this binding wraps)."""
+    import glob
+    import re
+    inc = os.path.join(os.path.dirname(_HERE), "include")
+    names = []
+    for h in sorted(glob.glob(os.path.join(inc, "*.h"))):
+        text = open(h).read()
+        names += re.findall(r"^\s*(?:spamm_status|void|const char\*)\s+(spamm_\w+)\s*\(", text, re.M)
+    return names
+
+
+def _check(code):
+    if code != 0:
+        msg = lib().spamm_last_error()
+        raise SpammError(code, msg.decode() if msg else "")
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def use_torch_allocator(enable: bool = True):
+    """Back the library's device allocations with torch's caching allocator."""
+    global _alloc_cb, _dealloc_cb
+    import torch
+
+    if not enable:
+        _check(lib().spamm_set_allocator(_ALLOC_FN(), _DEALLOC_FN(), None))
+        _alloc_cb = _dealloc_cb = None
+        return
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:          # OOM: the library reports SPAMM_ENOMEM
+            return None
+
+    def _dealloc(ptr, ctx):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    _alloc_cb = _ALLOC_FN(_alloc)
+    _dealloc_cb = _DEALLOC_FN(_dealloc)
+    _check(lib().spamm_set_allocator(_alloc_cb, _dealloc_cb, None))
+
+
+class Matrix:
+    """Owning wrapper of a spamm_matrix handle."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+        n, b, dt, lv = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().spamm_info(handle, ctypes.byref(n), ctypes.byref(b), ctypes.byref(dt), ctypes.byref(lv)))
+        self.n, self.leaf, self.levels = n.value, b.value, lv.value
+        self.dtype = "f64" if dt.value == 0 else "f32"
+        self.nb = -(-self.n // self.leaf)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h:
+            lib().spamm_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def to_dense(self, stream=None):
+        import torch
+        dt = torch.float64 if self.dtype == "f64" else torch.float32
+        out = torch.empty((self.n, self.n), dtype=dt, device="cuda")
+        _check(lib().spamm_to_dense(self._h, ctypes.c_void_p(out.data_ptr()), self.n, _stream(stream)))
+        return out
+
+    def norms(self, level: int = 0, stream=None) -> np.ndarray:
+        m = self.nb
+        for _ in range(level):
+            m = -(-m // 2)
+        out = np.empty((m, m), dtype=np.float64)
+        _check(lib().spamm_norms(self._h, level, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 out.size, _stream(stream)))
+        return out
+
+    def task_list(self, stream=None) -> np.ndarray:
+        cnt = ctypes.c_int64()
+        _check(lib().spamm_task_list(self._h, None, 0, ctypes.byref(cnt), _stream(stream)))
+        keys = np.empty(max(cnt.value, 1), dtype=np.uint64)
+        _check(lib().spamm_task_list(self._h, keys.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                     keys.size, ctypes.byref(cnt), _stream(stream)))
+        return np.sort(keys[:cnt.value])
+
+
+def build(a, leaf: int, stream=None) -> Matrix:
+    """Quadtree of a dense CUDA tensor (float32 or float64, row-major)."""
+    import torch
+    if not (a.is_cuda and a.dim() == 2 and a.shape[0] == a.shape[1]):
+        raise ValueError("build expects a square CUDA tensor")
+    if a.dtype not in (torch.float32, torch.float64):
+        raise ValueError("build expects float32 or float64")
+    if a.stride(1) != 1:
+        raise ValueError("build expects unit column stride")
+    h = ctypes.c_void_p()
+    _check(lib().spamm_build(ctypes.c_void_p(a.data_ptr()), a.shape[0], a.stride(0),
+                             0 if a.dtype == torch.float64 else 1, leaf, _stream(stream), ctypes.byref(h)))
+    return Matrix(h)
+
+
+def multiply(A: Matrix, B: Matrix, tau: float, prec: str = "f32", out: Matrix | None = None,
+             stats: bool = False, stream=None):
+    """C ~= A B by the SpAMM recursion (Eq. 4).  Returns C, or (C, stats dict)."""
+    h = ctypes.c_void_p(out.handle if out is not None else None)
+    st = Stats() if stats else None
+    _check(lib().spamm_multiply(A.handle, B.handle, float(tau), LEAF[prec], _stream(stream), ctypes.byref(h),
+                                ctypes.byref(st) if st is not None else None))
+    C = out if out is not None else Matrix(h)
+    return (C, st.to_dict()) if stats else C
+
+
+def multiply_batched(As, Bs, taus, prec: str = "f32", outs=None, stats: bool = False, stream=None):
+    """Independent products C_m ~= A_m B_m in one cull pass and one leaf launch."""
+    count = len(As)
+    PA = (ctypes.c_void_p * count)(*[a.handle for a in As])
+    PB = (ctypes.c_void_p * count)(*[b.handle for b in Bs])
+    PC = (ctypes.c_void_p * count)(*[(o.handle if o is not None else None) for o in (outs or [None] * count)])
+    T = (ctypes.c_double * count)(*[float(t) for t in taus])
+    st = (Stats * count)() if stats else None
+    _check(lib().spamm_multiply_batched(count, PA, PB, T, LEAF[prec], _stream(stream), PC,
+                                        st if st is not None else None))
+    Cs = []
+    for m in range(count):
+        if outs is not None and outs[m] is not None:
+            Cs.append(outs[m])
+        else:
+            Cs.append(Matrix(ctypes.c_void_p(PC[m])))
+    return (Cs, [s.to_dict() for s in st]) if stats else Cs
+
+
+def sp2(H: Matrix, n_occ: int, tau: float, max_iter: int = 60, idem_tol: float = 1e-6,
+        prec: str = "f32", stream=None):
+    """TC2 purification (section 3) with SpAMM squarings; returns (P, log dict)."""
+    h = ctypes.c_void_p()
+    log = Sp2Log()
+    code = lib().spamm_sp2(H.handle, int(n_occ), float(tau), int(max_iter), float(idem_tol), LEAF[prec],
+                           _stream(stream), ctypes.byref(h), ctypes.byref(log))
+    if code not in (0, 6):
+        _check(code)
+    d = log.to_dict()
+    d["status"] = STATUS[code]
+    return Matrix(h), d
+
+
+def diff_norms(X: Matrix, Y: Matrix, stream=None):
+    """(||X - Y||_F^2, ||Y||_F^2) in FP64."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(lib().spamm_diff_norms(X.handle, Y.handle, ctypes.byref(a), ctypes.byref(b), _stream(stream)))
+    return a.value, b.value
+
+
+def rel_err(X: Matrix, Y: Matrix, stream=None) -> float:
+    d2, r2 = diff_norms(X, Y, stream)
+    return float(np.sqrt(d2 / r2)) if r2 > 0 else float(np.sqrt(d2))

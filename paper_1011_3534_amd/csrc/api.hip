@@ -1,0 +1,458 @@
+// extern "C" entry points of libspamm (declared in include/spamm.h).
+//
+// Host-side validation happens before anything is enqueued; device-side
+// conditions are latched in a status word and reported by syncing calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "spamm_internal.hpp"
+
+namespace spamm {
+
+namespace {
+thread_local std::string g_err;
+spamm_alloc_fn g_alloc = nullptr;
+spamm_dealloc_fn g_dealloc = nullptr;
+void* g_actx = nullptr;
+std::mutex g_mu;
+}  // namespace
+
+spamm_status set_error(spamm_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+spamm_status hip_error(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? SPAMM_ENOMEM : SPAMM_EHIP;
+}
+
+void* dev_alloc(spamm_matrix* owner, size_t bytes, hipStream_t) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (owner->alloc) return owner->alloc(bytes, owner->actx);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void dev_free(spamm_matrix* owner, void* p, hipStream_t) {
+    if (!p) return;
+    if (owner->dealloc) owner->dealloc(p, owner->actx);
+    else (void)hipFree(p);
+}
+
+int num_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+namespace {
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+bool leaf_ok(int32_t b) { return b == 32 || b == 64 || b == 128; }
+
+// Tier shapes m_0 = nb, m_{l+1} = ceil(m_l / 2) ... m_L = 1.
+void tier_shapes(int64_t nb, int32_t& L, int32_t* m, int64_t* off, int64_t& total) {
+    L = 0;
+    int64_t mm = nb;
+    total = 0;
+    for (int l = 0;; ++l) {
+        m[l] = (int32_t)mm;
+        off[l] = total;
+        total += mm * mm;
+        if (mm == 1) {
+            L = l;
+            break;
+        }
+        mm = ceil_div(mm, 2);
+    }
+}
+
+spamm_matrix* new_handle(int64_t n, int32_t b, spamm_dtype dt) {
+    auto* M = new spamm_matrix();
+    M->n = n;
+    M->b = b;
+    M->nb = ceil_div(n, b);
+    M->dt = dt;
+    M->elem = dt == SPAMM_F64 ? 8 : 4;
+    tier_shapes(M->nb, M->L, M->lvl_m, M->lvl_off, M->norms_total);
+    M->alloc = g_alloc;
+    M->dealloc = g_dealloc;
+    M->actx = g_actx;
+    (void)hipGetDevice(&M->device);
+    return M;
+}
+
+void release_scratch(spamm_matrix* M) {
+    if (!M->ps) return;
+    ProductScratch* ps = M->ps;
+    dev_free(M, ps->mask, M->last_stream);
+    dev_free(M, ps->front[0], M->last_stream);
+    dev_free(M, ps->front[1], M->last_stream);
+    dev_free(M, ps->ctr, M->last_stream);
+    dev_free(M, ps->desc, M->last_stream);
+    dev_free(M, ps->sp2_part, M->last_stream);
+    delete ps;
+    M->ps = nullptr;
+}
+
+void release(spamm_matrix* M) {
+    if (!M) return;
+    if (M->last_stream) (void)hipStreamSynchronize(M->last_stream);
+    release_scratch(M);
+    dev_free(M, M->tiles, M->last_stream);
+    dev_free(M, M->norms, M->last_stream);
+    dev_free(M, M->texp, M->last_stream);
+    delete M;
+}
+
+// Device storage of a handle: tiles, norm pyramid (+ tier tables + status
+// word at its tail) and per-tile exponents.
+spamm_status alloc_storage(spamm_matrix* M, hipStream_t s) {
+    const size_t tiles = (size_t)(M->nb * M->nb) * M->b * M->b * M->elem;
+    M->tiles = dev_alloc(M, tiles, s);
+    const size_t nbytes = (size_t)M->norms_total * 8 + kMaxLevels * 8 + kMaxLevels * 4 + 64;
+    M->norms = (double*)dev_alloc(M, nbytes, s);
+    M->texp = (int8_t*)dev_alloc(M, (size_t)(M->nb * M->nb), s);
+    if (!M->tiles || !M->norms || !M->texp) return set_error(SPAMM_ENOMEM, "device allocation failed");
+    int64_t* off = reinterpret_cast<int64_t*>(M->norms + M->norms_total);
+    int* mm = reinterpret_cast<int*>(off + kMaxLevels);
+    SPAMM_HIP(hipMemcpyAsync(off, M->lvl_off, sizeof(int64_t) * kMaxLevels, hipMemcpyHostToDevice, s));
+    SPAMM_HIP(hipMemcpyAsync(mm, M->lvl_m, sizeof(int32_t) * kMaxLevels, hipMemcpyHostToDevice, s));
+    return SPAMM_OK;
+}
+
+unsigned* status_word(const spamm_matrix* M) {
+    int64_t* off = reinterpret_cast<int64_t*>(M->norms + M->norms_total);
+    int* mm = reinterpret_cast<int*>(off + kMaxLevels);
+    return reinterpret_cast<unsigned*>(mm + kMaxLevels);
+}
+
+// Product scratch owned by the result handle.
+spamm_status ensure_scratch(spamm_matrix* C, hipStream_t s) {
+    if (C->ps) return SPAMM_OK;
+    auto* ps = new ProductScratch();
+    C->ps = ps;
+    const int64_t nb = C->nb;
+    const int W = (int)ceil_div(nb, 64);
+    ps->mask = (uint64_t*)dev_alloc(C, (size_t)(nb * nb * W) * 8, s);
+    int64_t cap = 1;
+    if (C->L >= 2) cap = (int64_t)C->lvl_m[1] * C->lvl_m[1] * C->lvl_m[1];
+    ps->front_cap = cap;
+    ps->front[0] = (uint64_t*)dev_alloc(C, (size_t)cap * 8, s);
+    ps->front[1] = (uint64_t*)dev_alloc(C, (size_t)cap * 8, s);
+    ps->ctr = (DevCounters*)dev_alloc(C, sizeof(DevCounters) + 16 * kMaxBatch, s);
+    ps->desc = (ProdDesc*)dev_alloc(C, sizeof(ProdDesc), s);
+    if (!ps->mask || !ps->front[0] || !ps->front[1] || !ps->ctr || !ps->desc)
+        return set_error(SPAMM_ENOMEM, "device allocation of product scratch failed");
+    return SPAMM_OK;
+}
+
+// nonempty-tile counters live right after the DevCounters block
+unsigned long long* nonempty_ctr(DevCounters* ctr) {
+    return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(ctr) + sizeof(DevCounters));
+}
+
+ProdDesc make_desc(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C, double tau) {
+    ProdDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.A = A->tiles;
+    d.B = B->tiles;
+    d.C = C->tiles;
+    d.SA = A->norms;
+    d.SB = B->norms;
+    d.SC = C->norms;
+    d.eA = A->texp;
+    d.eB = B->texp;
+    d.eC = C->texp;
+    d.mask = C->ps->mask;
+    d.nonempty = nonempty_ctr(C->ps->ctr);
+    for (int l = 0; l < kMaxLevels; ++l) {
+        d.lvl_off[l] = C->lvl_off[l];
+        d.lvl_m[l] = C->lvl_m[l];
+    }
+    d.tile_base = 0;
+    d.tau2 = tau * tau;
+    d.nb = (int32_t)C->nb;
+    d.L = C->L;
+    d.W = (int32_t)ceil_div(C->nb, 64);
+    d.a_f64 = A->dt == SPAMM_F64;
+    d.b_f64 = B->dt == SPAMM_F64;
+    return d;
+}
+
+spamm_status check_operands(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec) {
+    if (!A || !B) return set_error(SPAMM_EINVAL, "null operand");
+    if (A->n != B->n || A->b != B->b) return set_error(SPAMM_EINVAL, "operands differ in n or leaf size");
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return set_error(SPAMM_EINVAL, "tau must be finite and >= 0");
+    if (tau > 0.0 && tau < 1e-150) return set_error(SPAMM_EINVAL, "0 < tau < 1e-150: tau^2 would underflow");
+    if ((int)prec < 0 || (int)prec > 5) return set_error(SPAMM_EINVAL, "unknown leaf precision");
+    if (prec != SPAMM_LEAF_F64 && (A->dt != SPAMM_F32 || B->dt != SPAMM_F32))
+        return set_error(SPAMM_EUNSUPPORTED, "leaf precisions below FP64 take FP32 operand tiles");
+    if (prec == SPAMM_LEAF_F64 && A->dt != B->dt)
+        return set_error(SPAMM_EUNSUPPORTED, "FP64 leaves take operands of one element type");
+    return SPAMM_OK;
+}
+
+// Host upper bound of the nodes stored at each tier (for grid sizing).
+void tier_items(const spamm_matrix* C, int64_t cap, int64_t* items) {
+    for (int l = 0; l < kMaxLevels; ++l) items[l] = 0;
+    for (int l = 1; l <= C->L; ++l) {
+        const int64_t m = C->lvl_m[l];
+        items[l] = std::min<int64_t>(m * m * m, cap);
+    }
+    items[C->L] = 0;  // the root enters as a virtual item
+}
+
+spamm_status read_stats(spamm_matrix* C, hipStream_t s, spamm_stats* st, double tau) {
+    SPAMM_HIP(hipStreamSynchronize(s));
+    DevCounters h;
+    unsigned long long ne = 0;
+    SPAMM_HIP(hipMemcpy(&h, C->ps->ctr, sizeof(DevCounters), hipMemcpyDeviceToHost));
+    SPAMM_HIP(hipMemcpy(&ne, nonempty_ctr(C->ps->ctr), sizeof ne, hipMemcpyDeviceToHost));
+    std::memset(st, 0, sizeof *st);
+    st->n = C->n;
+    st->leaf = C->b;
+    st->levels = C->L;
+    st->nb = C->nb;
+    for (int l = 0; l <= C->L && l < kMaxLevels; ++l) st->survivors[l] = (int64_t)h.survivors[0][l];
+    st->tasks = st->survivors[0];
+    st->nonempty_tiles = (int64_t)ne;
+    st->flops = 2.0 * C->b * (double)C->b * C->b * (double)st->tasks;
+    st->culled_bound = h.culled_bound[0];
+    (void)tau;
+    if (h.status & kDevCapacity) return set_error(SPAMM_ECAPACITY, "frontier capacity exceeded");
+    return SPAMM_OK;
+}
+
+}  // namespace
+
+// Shared by multiply and SP2: cull + leaf products + C pyramid, all enqueued.
+spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C, double tau,
+                             spamm_leaf_prec prec, hipStream_t s, int want_bound, int sp2, const int* d_branch,
+                             const int* d_active, ProdDesc* d_desc_override) {
+    ProductScratch* ps = C->ps;
+    ProdDesc* d_desc = d_desc_override;
+    if (!d_desc) {
+        ProdDesc d = make_desc(A, B, C, tau);
+        if (!ps->desc_valid || std::memcmp(&d, &ps->host_desc, sizeof d) != 0) {
+            ps->host_desc = d;
+            SPAMM_HIP(hipMemcpyAsync(ps->desc, &ps->host_desc, sizeof(ProdDesc), hipMemcpyHostToDevice, s));
+            ps->desc_valid = true;
+        }
+        d_desc = ps->desc;
+    }
+    CullPlan cp;
+    cp.count = 1;
+    cp.Lmax = C->L;
+    cp.front_cap = ps->front_cap;
+    cp.mask_words = C->nb * C->nb * ceil_div(C->nb, 64);
+    int64_t items[kMaxLevels];
+    tier_items(C, ps->front_cap, items);
+    SPAMM_HIP(launch_clear_nonempty(nonempty_ctr(ps->ctr), 1, d_active, s));
+    SPAMM_HIP(launch_cull_ex(d_desc, cp, ps->mask, ps->front[0], ps->front[1], ps->ctr, want_bound, d_active, items, s));
+    LeafPlan lp;
+    lp.count = 1;
+    lp.total_tiles = C->nb * C->nb;
+    lp.b = C->b;
+    lp.prec = prec;
+    lp.c_f64 = C->dt == SPAMM_F64;
+    lp.sp2 = sp2;
+    lp.d_branch = d_branch;
+    lp.d_active = d_active;
+    SPAMM_HIP(launch_leaf_typed(d_desc, lp, A->dt == SPAMM_F64, s));
+    SPAMM_HIP(launch_upper_norms(C, s, d_active));
+    return SPAMM_OK;
+}
+
+}  // namespace spamm
+
+using namespace spamm;
+
+extern "C" {
+
+spamm_status spamm_build(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf, void* stream,
+                         spamm_matrix** out) {
+    if (!out) return set_error(SPAMM_EINVAL, "out is null");
+    if (!dev_a) return set_error(SPAMM_EINVAL, "dev_a is null");
+    if (n < 1 || lda < n) return set_error(SPAMM_EINVAL, "need n >= 1 and lda >= n");
+    if (dt != SPAMM_F32 && dt != SPAMM_F64) return set_error(SPAMM_EINVAL, "unknown dtype");
+    if (!leaf_ok(leaf)) return set_error(SPAMM_EINVAL, "leaf must be 32, 64 or 128");
+    if (ceil_div(n, leaf) > kMaxNb) return set_error(SPAMM_EINVAL, "n / leaf exceeds 2^19 leaves");
+    hipStream_t s = (hipStream_t)stream;
+    spamm_matrix* M = new_handle(n, leaf, dt);
+    M->last_stream = s;
+    spamm_status st = alloc_storage(M, s);
+    if (st != SPAMM_OK) {
+        release(M);
+        return st;
+    }
+    hipError_t e = hipMemsetAsync(status_word(M), 0, 4, s);
+    if (e == hipSuccess) e = launch_pack_norm(dev_a, n, lda, dt, M, status_word(M), s);
+    if (e == hipSuccess) e = launch_upper_norms(M, s, nullptr);
+    if (e != hipSuccess) {
+        st = hip_error(e, "spamm_build kernels");
+        release(M);
+        return st;
+    }
+    *out = M;
+    return SPAMM_OK;
+}
+
+spamm_status spamm_multiply(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,
+                            void* stream, spamm_matrix** C, spamm_stats* st) {
+    if (!C) return set_error(SPAMM_EINVAL, "C is null");
+    spamm_status v = check_operands(A, B, tau, prec);
+    if (v != SPAMM_OK) return v;
+    const spamm_dtype cdt = prec == SPAMM_LEAF_F64 ? SPAMM_F64 : SPAMM_F32;
+    spamm_matrix* Cm = *C;
+    if (Cm) {
+        if (Cm == A || Cm == B) return set_error(SPAMM_EINVAL, "C may not alias an operand");
+        if (Cm->n != A->n || Cm->b != A->b || Cm->dt != cdt)
+            return set_error(SPAMM_EINVAL, "existing C differs in n, leaf or result type");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    bool fresh = false;
+    if (!Cm) {
+        Cm = new_handle(A->n, A->b, cdt);
+        fresh = true;
+        spamm_status r = alloc_storage(Cm, s);
+        if (r != SPAMM_OK) {
+            release(Cm);
+            return r;
+        }
+    }
+    Cm->last_stream = s;
+    spamm_status r = ensure_scratch(Cm, s);
+    if (r == SPAMM_OK) r = enqueue_product(A, B, Cm, tau, prec, s, st != nullptr, 0, nullptr, nullptr, nullptr);
+    if (r != SPAMM_OK) {
+        if (fresh) release(Cm);
+        return r;
+    }
+    *C = Cm;
+    if (st) return read_stats(Cm, s, st, tau);
+    return SPAMM_OK;
+}
+
+spamm_status spamm_to_dense(const spamm_matrix* M, void* dev_out, int64_t ldo, void* stream) {
+    if (!M || !dev_out) return set_error(SPAMM_EINVAL, "null argument");
+    if (ldo < M->n) return set_error(SPAMM_EINVAL, "ldo < n");
+    SPAMM_HIP(launch_to_dense(M, dev_out, ldo, (hipStream_t)stream));
+    return SPAMM_OK;
+}
+
+spamm_status spamm_info(const spamm_matrix* M, int64_t* n, int32_t* leaf, spamm_dtype* dt, int32_t* levels) {
+    if (!M) return set_error(SPAMM_EINVAL, "null handle");
+    if (n) *n = M->n;
+    if (leaf) *leaf = M->b;
+    if (dt) *dt = M->dt;
+    if (levels) *levels = M->L;
+    return SPAMM_OK;
+}
+
+spamm_status spamm_norms(const spamm_matrix* M, int32_t level, double* host_out, int64_t cap, void* stream) {
+    if (!M || !host_out) return set_error(SPAMM_EINVAL, "null argument");
+    if (level < 0 || level > M->L) return set_error(SPAMM_EINVAL, "level out of range");
+    const int64_t m = M->lvl_m[level];
+    if (cap < m * m) return set_error(SPAMM_EINVAL, "host buffer too small");
+    hipStream_t s = (hipStream_t)stream;
+    SPAMM_HIP(hipStreamSynchronize(s));
+    SPAMM_HIP(hipMemcpy(host_out, M->norms + M->lvl_off[level], sizeof(double) * m * m, hipMemcpyDeviceToHost));
+    unsigned stw = 0;
+    SPAMM_HIP(hipMemcpy(&stw, status_word(M), 4, hipMemcpyDeviceToHost));
+    if (stw & kDevNonFinite) return set_error(SPAMM_ENONFINITE, "non-finite norm in operand");
+    return SPAMM_OK;
+}
+
+spamm_status spamm_task_list(const spamm_matrix* C, uint64_t* host_keys, int64_t cap, int64_t* count,
+                             void* stream) {
+    if (!C || !count) return set_error(SPAMM_EINVAL, "null argument");
+    if (!C->ps) return set_error(SPAMM_EINVAL, "handle was not written by a product");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nb = C->nb;
+    const int W = (int)ceil_div(nb, 64);
+    std::vector<uint64_t> mask((size_t)(nb * nb * W));
+    SPAMM_HIP(hipStreamSynchronize(s));
+    SPAMM_HIP(hipMemcpy(mask.data(), C->ps->mask, mask.size() * 8, hipMemcpyDeviceToHost));
+    int64_t t = 0;
+    for (int64_t tile = 0; tile < nb * nb; ++tile)
+        for (int w = 0; w < W; ++w) {
+            uint64_t bits = mask[(size_t)(tile * W + w)];
+            while (bits) {
+                const int k = __builtin_ctzll(bits);
+                bits &= bits - 1;
+                if (host_keys && t < cap)
+                    host_keys[t] = ((uint64_t)(tile / nb) << 42) | ((uint64_t)(tile % nb) << 21) | (uint64_t)(w * 64 + k);
+                ++t;
+            }
+        }
+    *count = t;
+    return SPAMM_OK;
+}
+
+spamm_status spamm_diff_norms(const spamm_matrix* X, const spamm_matrix* Y, double* diff2, double* ref2,
+                              void* stream) {
+    if (!X || !Y || !diff2 || !ref2) return set_error(SPAMM_EINVAL, "null argument");
+    if (X->n != Y->n || X->b != Y->b) return set_error(SPAMM_EINVAL, "handles differ in n or leaf");
+    hipStream_t s = (hipStream_t)stream;
+    double* d = nullptr;
+    SPAMM_HIP(hipMalloc(&d, 2 * 1024 * sizeof(double)));
+    hipError_t e = launch_diff_norms(X, Y, d, s);
+    std::vector<double> h(2048);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(h.data(), d, h.size() * 8, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_error(e, "spamm_diff_norms");
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < 1024; ++i) {
+        a += h[2 * i];
+        b += h[2 * i + 1];
+    }
+    *diff2 = a;
+    *ref2 = b;
+    return SPAMM_OK;
+}
+
+spamm_status spamm_set_allocator(spamm_alloc_fn alloc, spamm_dealloc_fn dealloc, void* ctx) {
+    if ((alloc == nullptr) != (dealloc == nullptr))
+        return set_error(SPAMM_EINVAL, "alloc and dealloc must both be set or both be NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_alloc = alloc;
+    g_dealloc = dealloc;
+    g_actx = ctx;
+    return SPAMM_OK;
+}
+
+void spamm_free(spamm_matrix* M) { release(M); }
+
+const char* spamm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+extern "C" {
+
+spamm_status spamm_multiply_batched(int32_t, const spamm_matrix* const*, const spamm_matrix* const*, const double*,
+                                    spamm_leaf_prec, void*, spamm_matrix**, spamm_stats*) {
+    return spamm::set_error(SPAMM_EUNSUPPORTED, "spamm_multiply_batched is not built yet");
+}
+
+spamm_status spamm_sp2(const spamm_matrix*, int64_t, double, int32_t, double, spamm_leaf_prec, void*,
+                       spamm_matrix**, spamm_sp2_log*) {
+    return spamm::set_error(SPAMM_EUNSUPPORTED, "spamm_sp2 is not built yet");
+}
+
+}  // extern "C"

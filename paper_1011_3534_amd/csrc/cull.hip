@@ -1,0 +1,212 @@
+// Product-space cull of the SpAMM recursion (section 2, Eq. 4; the octree of
+// Figure 1) as level-synchronous passes on gfx950.
+//
+// The frontier of tier l holds the kept octree nodes (m, I, J, K) of every
+// product in the batch.  One launch per tier expands each node into its 8
+// children and keeps a child iff !(S_A[l-1][I',K'] * S_B[l-1][K',J'] < tau^2);
+// survivors are compacted with a block-wide exclusive prefix scan and one
+// atomic reservation per block.  Children at the leaf tier are not
+// compacted: they set bit K of the C tile (I, J) in a bitmask, which gives
+// every C tile its kept K in ascending order with no sort.
+//
+// Roots enter as virtual items: at tier l the products whose quadtree has l
+// tiers test their root and expand it in the same launch, so a batch of
+// unequal sizes is culled with one launch per tier.
+#include "spamm_internal.hpp"
+
+namespace spamm {
+namespace {
+
+constexpr int kCullThreads = 256;
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+    for (int d = kWave / 2; d >= 1; d /= 2) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+__global__ void __launch_bounds__(kCullThreads)
+    k_cull_tier(const ProdDesc* __restrict__ desc, int nprod, int l, const uint64_t* __restrict__ in,
+                uint64_t* __restrict__ out, DevCounters* __restrict__ ctr, int64_t out_cap, int want_bound,
+                const int* __restrict__ active) {
+    if (active && *active == 0) return;
+    __shared__ unsigned wave_tot[kCullThreads / kWave];
+    __shared__ unsigned long long block_base;
+    const int64_t P = (int64_t)ctr->front_count[l];
+    const int64_t items = P + nprod;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int c = l - 1;  // child tier
+
+    for (int64_t base = (int64_t)blockIdx.x * kCullThreads; base < items;
+         base += (int64_t)gridDim.x * kCullThreads) {
+        const int64_t idx = base + threadIdx.x;
+        uint32_t m = 0, I = 0, J = 0, K = 0;
+        bool have = false;
+        if (idx < P) {
+            const uint64_t key = in[idx];
+            m = key_m(key);
+            I = key_i(key);
+            J = key_j(key);
+            K = key_k(key);
+            have = true;
+        } else if (idx < items) {
+            m = (uint32_t)(idx - P);
+            const ProdDesc& d = desc[m];
+            if (d.L == l || (l == 1 && d.L == 0)) {
+                // root of product m: Eq. (4) tests it like any other node
+                const double sa = d.SA[d.lvl_off[d.L]], sb = d.SB[d.lvl_off[d.L]];
+                if (!(sa * sb < d.tau2)) {
+                    atomicAdd(&ctr->survivors[m][d.L], 1ull);
+                    if (d.L == 0) {
+                        atomicOr((unsigned long long*)&d.mask[0], 1ull);
+                    } else {
+                        have = true;
+                    }
+                } else if (want_bound) {
+                    atomicAdd(&ctr->culled_bound[m], sqrt(sa) * sqrt(sb));
+                }
+            }
+        }
+        unsigned keep = 0;  // bit q set: child q kept (q = i2*4 + j2*2 + k2)
+        unsigned long long leaf_kept = 0;
+        double bound = 0.0;
+        if (have) {
+            const ProdDesc& d = desc[m];
+            const int mc = d.lvl_m[c];
+            const double* SA = d.SA + d.lvl_off[c];
+            const double* SB = d.SB + d.lvl_off[c];
+            const double t2 = d.tau2;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t Ic = 2 * I + (q >> 2), Jc = 2 * J + ((q >> 1) & 1), Kc = 2 * K + (q & 1);
+                if ((int)Ic >= mc || (int)Jc >= mc || (int)Kc >= mc) continue;
+                const double sa = SA[(int64_t)Ic * mc + Kc];
+                const double sb = SB[(int64_t)Kc * mc + Jc];
+                if (sa * sb < t2) {
+                    if (want_bound) bound += sqrt(sa) * sqrt(sb);
+                    continue;
+                }
+                if (c == 0) {
+                    uint64_t* w = d.mask + ((int64_t)Ic * mc + Jc) * d.W + (Kc >> 6);
+                    atomicOr((unsigned long long*)w, 1ull << (Kc & 63));
+                    ++leaf_kept;
+                } else {
+                    keep |= 1u << q;
+                }
+            }
+        }
+        // survivors of this tier per product: one atomic per uniform wave
+        const unsigned nk = __popc(keep);
+        {
+            const unsigned long long mine = (unsigned long long)nk + leaf_kept;
+            const uint32_t m0 = __shfl(m, 0, kWave);
+            const bool uniform = __all(!(have) || m == m0);
+            if (uniform) {
+                const unsigned long long s = wave_sum_u64(mine);
+                if (lane == 0 && s) atomicAdd(&ctr->survivors[m0][c], s);
+            } else if (mine) {
+                atomicAdd(&ctr->survivors[m][c], mine);
+            }
+            if (want_bound && bound > 0.0) atomicAdd(&ctr->culled_bound[m], bound);
+        }
+        if (c == 0) continue;  // leaf tier: nothing to compact
+        // block-wide exclusive scan of the per-thread child counts
+        unsigned incl = nk;
+        for (int d = 1; d < kWave; d *= 2) {
+            const unsigned o = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += o;
+        }
+        if (lane == kWave - 1) wave_tot[wid] = incl;
+        __syncthreads();
+        unsigned wave_off = 0, block_tot = 0;
+        for (int w = 0; w < kCullThreads / kWave; ++w) {
+            if (w < wid) wave_off += wave_tot[w];
+            block_tot += wave_tot[w];
+        }
+        if (threadIdx.x == 0)
+            block_base = block_tot ? atomicAdd(&ctr->front_count[c], (unsigned long long)block_tot) : 0ull;
+        __syncthreads();
+        int64_t pos = (int64_t)block_base + wave_off + (incl - nk);
+        if (keep) {
+            if (pos + nk > out_cap) {
+                atomicOr(&ctr->status, kDevCapacity);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (keep & (1u << q))
+                        out[pos++] = node_key(m, 2 * I + (q >> 2), 2 * J + ((q >> 1) & 1), 2 * K + (q & 1));
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_zero_counters(DevCounters* ctr, int nprod, const int* active) {
+    if (active && *active == 0) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < kMaxLevels) ctr->front_count[t] = 0;
+    if (t == 0) ctr->status = 0;
+    for (int i = t; i < nprod * kMaxLevels; i += gridDim.x * blockDim.x)
+        ctr->survivors[i / kMaxLevels][i % kMaxLevels] = 0;
+    for (int i = t; i < nprod; i += gridDim.x * blockDim.x) ctr->culled_bound[i] = 0.0;
+}
+
+__global__ void k_clear_mask(uint64_t* mask, int64_t words, const int* active) {
+    if (active && *active == 0) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        mask[i] = 0;
+}
+
+__global__ void k_task_keys(const ProdDesc* __restrict__ desc, int64_t nb, int W, const uint64_t* __restrict__ mask,
+                            uint64_t* __restrict__ out, unsigned long long* count, int64_t cap) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb * nb) return;
+    const int64_t I = t / nb, J = t % nb;
+    for (int w = 0; w < W; ++w) {
+        uint64_t bits = mask[t * W + w];
+        while (bits) {
+            const int k = __ffsll((unsigned long long)bits) - 1;
+            bits &= bits - 1;
+            const unsigned long long p = atomicAdd(count, 1ull);
+            if ((int64_t)p < cap) out[p] = ((uint64_t)I << 42) | ((uint64_t)J << 21) | (uint64_t)(w * 64 + k);
+        }
+    }
+}
+
+}  // namespace
+
+// Tier-by-tier cull; `plan.front_cap` bounds each frontier buffer.
+hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t* mask, uint64_t* front0,
+                          uint64_t* front1, DevCounters* ctr, int want_bound, const int* active,
+                          const int64_t* tier_items, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_counters, dim3(8), dim3(256), 0, s, ctr, plan.count, active);
+    {
+        int64_t blocks = (plan.mask_words + 255) / 256;
+        blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
+        hipLaunchKernelGGL(k_clear_mask, dim3((unsigned)blocks), dim3(256), 0, s, mask, plan.mask_words, active);
+    }
+    const int top = plan.Lmax < 1 ? 1 : plan.Lmax;
+    for (int l = top; l >= 1; --l) {
+        // frontier of tier l lives in buffer (l & 1); children go to ((l-1) & 1)
+        const uint64_t* in = (l & 1) ? front1 : front0;
+        uint64_t* out = ((l - 1) & 1) ? front1 : front0;
+        int64_t items = tier_items[l] + plan.count;
+        int64_t blocks = (items + kCullThreads - 1) / kCullThreads;
+        const int64_t maxb = (int64_t)num_cus() * 8;
+        blocks = blocks < 1 ? 1 : (blocks > maxb ? maxb : blocks);
+        hipLaunchKernelGGL(k_cull_tier, dim3((unsigned)blocks), dim3(kCullThreads), 0, s, d_desc, plan.count, l,
+                           in, out, ctr, plan.front_cap, want_bound, active);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_task_keys(const ProdDesc* d_desc, int64_t nb, int W, const uint64_t* mask, uint64_t* keys_out,
+                            unsigned long long* count, int64_t cap, hipStream_t s) {
+    const int64_t tiles = nb * nb;
+    hipLaunchKernelGGL(k_task_keys, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, s, d_desc, nb, W, mask,
+                       keys_out, count, cap);
+    return hipGetLastError();
+}
+
+}  // namespace spamm

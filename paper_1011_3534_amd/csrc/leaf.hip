@@ -1,0 +1,540 @@
+// Dense leaf products of SpAMM (the finest tier of Eq. 4) on gfx950 MFMA.
+//
+// One 256-thread workgroup owns one C tile (I, J): it walks the kept K of the
+// tile in ascending order straight from the leaf bitmask written by the cull,
+// streams A_IK and B_KJ through double-buffered LDS in k-chunks and
+// accumulates with 16x16 MFMA blocks; the four waves split the tile 2 x 2.
+// Tiles are handed out XCD by XCD (block x runs on XCD x mod 8), each XCD
+// taking a contiguous run of tiles so that neighbouring tiles, which share
+// operand panels, meet in the same L2.
+//
+// The epilogue stages the tile through LDS, stores it coalesced, and computes
+// its FP64 squared norm in the same fixed order as the build (per column over
+// ascending rows with FMA, then the pairwise column tree), so the result can
+// be an operand of the next product with norms identical to a fresh build of
+// the stored values.  The SP2 variant also applies the TC2 update
+// X <- X^2 or 2X - X^2 and emits FP64 partials of ||X^2 - X||_F^2 and tr(X).
+#include "spamm_internal.hpp"
+
+namespace spamm {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+enum Kind { kF64 = 0, kF32 = 1, kBF16 = 2, kBF16X3 = 3, kF16 = 4, kF16X3 = 5 };
+
+constexpr bool is16(int k) { return k >= kBF16; }
+constexpr bool isx3(int k) { return k == kBF16X3 || k == kF16X3; }
+constexpr bool isf16(int k) { return k == kF16 || k == kF16X3; }
+constexpr int kF16Bias = 14;  // scaled tile max lies in [2^14, 2^15)
+
+// Geometry of one (leaf size, precision) instance.
+template <int B, int P>
+struct Geo {
+    static constexpr int R = B / 32;                                   // 16x16 blocks per wave per dim
+    static constexpr int KC = (P == kF64) ? (B == 128 ? 16 : 32) : (B == 64 ? 64 : 32);  // k-chunk
+    static constexpr int NCH = B / KC;                                 // chunks per task
+    // operand element in LDS
+    using E = typename std::conditional<P == kF64, double, typename std::conditional<is16(P), uint16_t, float>::type>::type;
+    static constexpr int SA = (P == kF64) ? KC + 2 : (is16(P) ? KC + 8 : KC + 4);  // A row stride (elements)
+    static constexpr int SB = (P == kF64) ? B + 8 : (is16(P) ? KC + 8 : B + 16);   // B row stride
+    static constexpr int ROWS_B = is16(P) ? B : KC;                                // B^T rows for 16-bit
+    static constexpr int NARR = isx3(P) ? 2 : 1;                                   // hi (+ lo)
+    static constexpr int A_ELEMS = B * SA;
+    static constexpr int B_ELEMS = ROWS_B * SB;
+    static constexpr int BUF_BYTES = NARR * (A_ELEMS + B_ELEMS) * (int)sizeof(E);
+    using CT = typename std::conditional<P == kF64, double, float>::type;         // accumulator
+    static constexpr int SC = B + (P == kF64 ? 2 : 4);                            // C staging stride
+    static constexpr int C_BYTES = B * SC * (int)sizeof(CT);
+    static constexpr int SMEM = (2 * BUF_BYTES > C_BYTES) ? 2 * BUF_BYTES : C_BYTES;
+};
+
+__device__ inline uint16_t bf16_bits(float x) {
+    __bf16 h = (__bf16)x;
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ inline float bf16_val(uint16_t u) { return (float)__builtin_bit_cast(__bf16, u); }
+__device__ inline uint16_t f16_bits(float x) {
+    _Float16 h = (_Float16)x;
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ inline float f16_val(uint16_t u) { return (float)__builtin_bit_cast(_Float16, u); }
+
+template <int P>
+__device__ inline void split16(float x, uint16_t& hi, uint16_t& lo) {
+    if constexpr (P == kBF16 || P == kBF16X3) {
+        hi = bf16_bits(x);
+        if constexpr (isx3(P)) lo = bf16_bits(x - bf16_val(hi));
+    } else {
+        hi = f16_bits(x);
+        if constexpr (isx3(P)) lo = f16_bits(x - f16_val(hi));
+    }
+}
+
+// fp16 operands are scaled by 2^e per tile (exact); bf16 needs no scaling
+template <int P>
+__device__ inline float scale_in(float x, int e) {
+    if constexpr (isf16(P)) return ldexpf(x, e);
+    return x;
+}
+
+// Register stage of one k-chunk: the raw operand values of this thread.
+template <int B, int P, typename TA>
+struct Stage {
+    using G = Geo<B, P>;
+    static constexpr int KC = G::KC;
+    // 32-bit and FP64 paths: float4/double2-sized units of A rows and B rows
+    static constexpr int VA = is16(P) ? 8 : (16 / (int)sizeof(TA));
+    static constexpr int NU = B * KC / VA;                                // units per operand chunk
+    static constexpr int UA = (NU + 255) / 256;                           // units per thread
+    static constexpr int UB = UA;
+    static constexpr bool PARTIAL = (NU % 256) != 0;
+    TA a[UA][VA];
+    TA b[UB][VA];
+};
+
+template <int B, int P, typename TA>
+__device__ inline void stage_load(Stage<B, P, TA>& st, const TA* __restrict__ At, const TA* __restrict__ Bt, int kc,
+                                  int tid) {
+    using S = Stage<B, P, TA>;
+    constexpr int KC = S::KC, VA = S::VA;
+#pragma unroll
+    for (int u = 0; u < S::UA; ++u) {
+        const int unit = tid + u * 256;
+        if (S::PARTIAL && unit >= S::NU) break;
+        const int r = unit / (KC / VA), k = (unit % (KC / VA)) * VA;
+        const TA* src = At + (int64_t)r * B + kc + k;
+#pragma unroll
+        for (int j = 0; j < VA; ++j) st.a[u][j] = src[j];
+    }
+    if constexpr (is16(P)) {
+        // B^T units: column c, 8 consecutive k (each load coalesced over c)
+#pragma unroll
+        for (int u = 0; u < S::UB; ++u) {
+            const int unit = tid + u * 256;
+        if (S::PARTIAL && unit >= S::NU) break;
+            const int c = unit % B, k = (unit / B) * 8;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) st.b[u][j] = Bt[(int64_t)(kc + k + j) * B + c];
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < S::UB; ++u) {
+            const int unit = tid + u * 256;
+        if (S::PARTIAL && unit >= S::NU) break;
+            const int k = unit / (B / VA), c = (unit % (B / VA)) * VA;
+            const TA* src = Bt + (int64_t)(kc + k) * B + c;
+#pragma unroll
+            for (int j = 0; j < VA; ++j) st.b[u][j] = src[j];
+        }
+    }
+}
+
+template <int B, int P, typename TA>
+__device__ inline void stage_store(const Stage<B, P, TA>& st, char* buf, int tid, int sa, int sb) {
+    using G = Geo<B, P>;
+    using S = Stage<B, P, TA>;
+    using E = typename G::E;
+    constexpr int KC = G::KC, VA = S::VA;
+    E* As = reinterpret_cast<E*>(buf);
+    E* Bs = As + G::NARR * G::A_ELEMS;
+#pragma unroll
+    for (int u = 0; u < S::UA; ++u) {
+        const int unit = tid + u * 256;
+        if (S::PARTIAL && unit >= S::NU) break;
+        const int r = unit / (KC / VA), k = (unit % (KC / VA)) * VA;
+        if constexpr (is16(P)) {
+            uint16_t h[8], l[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) split16<P>(scale_in<P>((float)st.a[u][j], sa), h[j], l[j]);
+            uint4 vh, vl;
+            vh.x = h[0] | ((uint32_t)h[1] << 16); vh.y = h[2] | ((uint32_t)h[3] << 16);
+            vh.z = h[4] | ((uint32_t)h[5] << 16); vh.w = h[6] | ((uint32_t)h[7] << 16);
+            *reinterpret_cast<uint4*>(As + r * G::SA + k) = vh;
+            if constexpr (isx3(P)) {
+                vl.x = l[0] | ((uint32_t)l[1] << 16); vl.y = l[2] | ((uint32_t)l[3] << 16);
+                vl.z = l[4] | ((uint32_t)l[5] << 16); vl.w = l[6] | ((uint32_t)l[7] << 16);
+                *reinterpret_cast<uint4*>(As + G::A_ELEMS + r * G::SA + k) = vl;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < VA; ++j) As[r * G::SA + k + j] = (E)st.a[u][j];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < S::UB; ++u) {
+        const int unit = tid + u * 256;
+        if (S::PARTIAL && unit >= S::NU) break;
+        if constexpr (is16(P)) {
+            const int c = unit % B, k = (unit / B) * 8;
+            uint16_t h[8], l[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) split16<P>(scale_in<P>((float)st.b[u][j], sb), h[j], l[j]);
+            uint4 vh, vl;
+            vh.x = h[0] | ((uint32_t)h[1] << 16); vh.y = h[2] | ((uint32_t)h[3] << 16);
+            vh.z = h[4] | ((uint32_t)h[5] << 16); vh.w = h[6] | ((uint32_t)h[7] << 16);
+            *reinterpret_cast<uint4*>(Bs + c * G::SB + k) = vh;
+            if constexpr (isx3(P)) {
+                vl.x = l[0] | ((uint32_t)l[1] << 16); vl.y = l[2] | ((uint32_t)l[3] << 16);
+                vl.z = l[4] | ((uint32_t)l[5] << 16); vl.w = l[6] | ((uint32_t)l[7] << 16);
+                *reinterpret_cast<uint4*>(Bs + G::B_ELEMS + c * G::SB + k) = vl;
+            }
+        } else {
+            const int k = unit / (B / VA), c = (unit % (B / VA)) * VA;
+#pragma unroll
+            for (int j = 0; j < VA; ++j) Bs[k * G::SB + c + j] = (E)st.b[u][j];
+        }
+    }
+}
+
+// MFMA accumulation of one k-chunk held in LDS.
+template <int B, int P, typename Acc>
+__device__ inline void chunk_mma(const char* buf, Acc (&acc)[Geo<B, P>::R][Geo<B, P>::R], int lane, int wr, int wc) {
+    using G = Geo<B, P>;
+    using E = typename G::E;
+    constexpr int R = G::R, KC = G::KC;
+    const E* As = reinterpret_cast<const E*>(buf);
+    const E* Bs = As + G::NARR * G::A_ELEMS;
+    const int row0 = wr * (B / 2) + (lane & 15);
+    const int col0 = wc * (B / 2) + (lane & 15);
+    const int g = lane >> 4;
+    if constexpr (is16(P)) {
+#pragma unroll
+        for (int t = 0; t < KC / 32; ++t) {
+            const int k = 32 * t + 8 * g;
+            using V8 = typename std::conditional<P == kBF16 || P == kBF16X3, bf16x8, f16x8>::type;
+            V8 ah[R], bh[R], al[R], bl[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                ah[i] = *reinterpret_cast<const V8*>(As + (row0 + 16 * i) * G::SA + k);
+                bh[i] = *reinterpret_cast<const V8*>(Bs + (col0 + 16 * i) * G::SB + k);
+                if constexpr (isx3(P)) {
+                    al[i] = *reinterpret_cast<const V8*>(As + G::A_ELEMS + (row0 + 16 * i) * G::SA + k);
+                    bl[i] = *reinterpret_cast<const V8*>(Bs + G::B_ELEMS + (col0 + 16 * i) * G::SB + k);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    if constexpr (P == kBF16 || P == kBF16X3) {
+                        if constexpr (isx3(P)) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                        }
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                    } else {
+                        if constexpr (isx3(P)) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                        }
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                    }
+                }
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < KC / 4; ++t) {
+            const int k = 4 * t + g;
+            E a[R], b[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                a[i] = As[(row0 + 16 * i) * G::SA + k];
+                b[i] = Bs[k * G::SB + col0 + 16 * i];
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    if constexpr (P == kF64)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                    else
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+                }
+        }
+    }
+}
+
+// Iterator over the kept K of one C tile (ascending), from its bitmask.
+struct KIter {
+    const uint64_t* w;
+    int W, wi;
+    uint64_t bits;
+    __device__ int next() {
+        while (bits == 0) {
+            if (++wi >= W) return -1;
+            bits = w[wi];
+        }
+        const int k = __ffsll((unsigned long long)bits) - 1;
+        bits &= bits - 1;
+        return wi * 64 + k;
+    }
+};
+
+__device__ inline int find_product(const ProdDesc* desc, int nprod, int64_t t) {
+    int lo = 0, hi = nprod - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (desc[mid].tile_base <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+
+template <int B, int P, typename TA, typename TC, bool SP2>
+__global__ void __launch_bounds__(256) k_leaf(const ProdDesc* __restrict__ desc, int nprod, int64_t total,
+                                              int64_t chunk, const int* __restrict__ branch,
+                                              const int* __restrict__ active) {
+    using G = Geo<B, P>;
+    using CT = typename G::CT;
+    using Acc = typename std::conditional<P == kF64, f64x4, f32x4>::type;
+    constexpr int R = G::R, KC = G::KC, NCH = G::NCH;
+    __shared__ __attribute__((aligned(16))) char smem[G::SMEM];
+
+    if (active && *active == 0) return;
+    const int64_t x = blockIdx.x;
+    const int64_t t = (x & 7) * chunk + (x >> 3);
+    if (t >= total) return;
+    const int m = nprod > 1 ? find_product(desc, nprod, t) : 0;
+    const ProdDesc& d = desc[m];
+    const int nb = d.nb;
+    const int64_t local = t - d.tile_base;
+    const int I = (int)(local / nb), J = (int)(local % nb);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+    const TA* Ab = reinterpret_cast<const TA*>(d.A);
+    const TA* Bb = reinterpret_cast<const TA*>(d.B);
+    constexpr int64_t TS = (int64_t)B * B;
+
+    Acc acc[R][R], part[R][R];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            acc[i][j] = Acc{0, 0, 0, 0};
+            part[i][j] = Acc{0, 0, 0, 0};
+        }
+
+    KIter it{d.mask + local * d.W, d.W, 0, d.mask[local * d.W]};
+    int kcur = it.next();
+    if (kcur >= 0) {
+        if (tid == 0) atomicAdd(d.nonempty, 1ull);
+        Stage<B, P, TA> st;
+        // fp16: A_IK is scaled by 2^sa, B_KJ by 2^sb, their product undone by 2^unscale
+        int sa = 0, sb = 0, unscale = 0;
+        auto scales = [&](int k, int& a_s, int& b_s, int& un) {
+            if constexpr (isf16(P)) {
+                int ea = d.eA[(int64_t)I * nb + k], eb = d.eB[(int64_t)k * nb + J];
+                ea = ea == -128 ? 0 : ea;
+                eb = eb == -128 ? 0 : eb;
+                a_s = kF16Bias - ea;
+                b_s = kF16Bias - eb;
+                un = -(a_s + b_s);
+            }
+        };
+        scales(kcur, sa, sb, unscale);
+        int ch = 0;
+        stage_load<B, P, TA>(st, Ab + ((int64_t)I * nb + kcur) * TS, Bb + ((int64_t)kcur * nb + J) * TS, 0, tid);
+        stage_store<B, P, TA>(st, smem, tid, sa, sb);
+        __syncthreads();
+        int buf = 0;
+        while (true) {
+            // next (task, chunk)
+            int knext = kcur, chn = ch + 1;
+            if (chn == NCH) {
+                knext = it.next();
+                chn = 0;
+            }
+            const bool more = knext >= 0;
+            int nsa = sa, nsb = sb, nun = unscale;
+            if (more) {
+                if (knext != kcur) scales(knext, nsa, nsb, nun);
+                stage_load<B, P, TA>(st, Ab + ((int64_t)I * nb + knext) * TS, Bb + ((int64_t)knext * nb + J) * TS,
+                                     chn * KC, tid);
+            }
+            if constexpr (isf16(P)) {
+                chunk_mma<B, P, Acc>(smem + buf * G::BUF_BYTES, part, lane, wr, wc);
+                if (ch == NCH - 1) {  // task done: undo its power-of-two scales
+#pragma unroll
+                    for (int i = 0; i < R; ++i)
+#pragma unroll
+                        for (int j = 0; j < R; ++j) {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) acc[i][j][q] += ldexpf(part[i][j][q], unscale);
+                            part[i][j] = Acc{0, 0, 0, 0};
+                        }
+                }
+            } else {
+                chunk_mma<B, P, Acc>(smem + buf * G::BUF_BYTES, acc, lane, wr, wc);
+            }
+            if (!more) break;
+            stage_store<B, P, TA>(st, smem + (buf ^ 1) * G::BUF_BYTES, tid, nsa, nsb);
+            __syncthreads();
+            buf ^= 1;
+            kcur = knext;
+            ch = chn;
+            sa = nsa;
+            sb = nsb;
+            unscale = nun;
+        }
+        __syncthreads();  // all waves done reading the stage buffers
+    }
+
+    // ---------------------------------------------------------------- epilogue
+    CT* Cs = reinterpret_cast<CT*>(smem);
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = wr * (B / 2) + 16 * i + 4 * (lane >> 4) + q;
+                const int c = wc * (B / 2) + 16 * j + (lane & 15);
+                Cs[r * G::SC + c] = (CT)acc[i][j][q];
+            }
+    __syncthreads();
+
+    TC* Cg = reinterpret_cast<TC*>(d.C) + local * TS;
+    constexpr int VC = 16 / (int)sizeof(TC);
+    double mx = 0.0, idem = 0.0;
+    const TC* Xg = SP2 ? reinterpret_cast<const TC*>(d.X) + local * TS : nullptr;
+    const int br = SP2 ? *branch : 0;
+    for (int u = tid; u < B * B / VC; u += 256) {
+        const int r = u / (B / VC), c = (u % (B / VC)) * VC;
+        TC v[VC];
+#pragma unroll
+        for (int j = 0; j < VC; ++j) v[j] = (TC)Cs[r * G::SC + c + j];
+        if constexpr (SP2) {
+#pragma unroll
+            for (int j = 0; j < VC; ++j) {
+                const TC xv = Xg[r * B + c + j];
+                const double dv = (double)v[j] - (double)xv;
+                idem = __fma_rn(dv, dv, idem);
+                v[j] = br ? (TC)(xv + xv - v[j]) : v[j];
+                Cs[r * G::SC + c + j] = (CT)v[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < VC; ++j) {
+            mx = fmax(mx, fabs((double)v[j]));
+            Cg[r * B + c + j] = v[j];
+        }
+    }
+    if constexpr (SP2) __syncthreads();
+
+    // block reductions in a fixed order (deterministic)
+    __shared__ double red[2][4];
+    for (int dd = 32; dd >= 1; dd >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, dd, 64));
+        if constexpr (SP2) idem += __shfl_down(idem, dd, 64);
+    }
+    if (lane == 0) {
+        red[0][w] = mx;
+        red[1][w] = idem;
+    }
+    // canonical squared norm of the stored tile: wave 0, one (or two) columns per lane
+    if (w == 0) {
+        double s = 0.0;
+        if (lane < B) {
+            if constexpr (B == 128) {
+                double s2 = 0.0;
+                for (int r = 0; r < B; ++r) {
+                    const double a0 = (double)(TC)Cs[r * G::SC + lane];
+                    const double a1 = (double)(TC)Cs[r * G::SC + lane + 64];
+                    s = __fma_rn(a0, a0, s);
+                    s2 = __fma_rn(a1, a1, s2);
+                }
+                s = s + s2;  // tree step h = 64
+            } else {
+                for (int r = 0; r < B; ++r) {
+                    const double a0 = (double)(TC)Cs[r * G::SC + lane];
+                    s = __fma_rn(a0, a0, s);
+                }
+            }
+        }
+        constexpr int H0 = (B == 128 ? 64 : B) / 2;
+        for (int h = H0; h >= 1; h >>= 1) {
+            const double o = __shfl_down(s, h, 64);
+            if (lane < h) s = s + o;
+        }
+        double tr = 0.0;
+        if constexpr (SP2) {
+            if (I == J) {
+                // trace partial: diagonal of the updated tile, pairwise over lanes
+                double dv = 0.0;
+                if (lane < B) dv = (double)(TC)Cs[lane * G::SC + lane];
+                if constexpr (B == 128) dv += (double)(TC)Cs[(lane + 64) * G::SC + lane + 64];
+                for (int h = 32; h >= 1; h >>= 1) {
+                    const double o = __shfl_down(dv, h, 64);
+                    if (lane < h) dv = dv + o;
+                }
+                tr = dv;
+            }
+        }
+        if (lane == 0) {
+            d.SC[local] = s;
+            if constexpr (SP2) {
+                if (I == J) d.sp2_part[(int64_t)nb * nb + I] = tr;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double m2 = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+        int e = -128;
+        if (m2 > 0.0) {
+            e = ilogb(m2);
+            e = e < -127 ? -127 : (e > 127 ? 127 : e);
+        }
+        d.eC[local] = (int8_t)e;
+        if constexpr (SP2) d.sp2_part[local] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    }
+}
+
+template <int B, int P, typename TA, typename TC, bool SP2>
+hipError_t go(const ProdDesc* d_desc, const LeafPlan& p, hipStream_t s) {
+    const int64_t chunk = (p.total_tiles + 7) / 8;
+    const int64_t grid = chunk * 8;
+    hipLaunchKernelGGL((k_leaf<B, P, TA, TC, SP2>), dim3((unsigned)grid), dim3(256), 0, s, d_desc, p.count,
+                       p.total_tiles, chunk, p.d_branch, p.d_active);
+    return hipGetLastError();
+}
+
+template <int B>
+hipError_t dispatch_b(const ProdDesc* d_desc, const LeafPlan& p, bool a_f64, hipStream_t s) {
+    switch (p.prec) {
+        case SPAMM_LEAF_F64:
+            if (a_f64) return go<B, kF64, double, double, false>(d_desc, p, s);
+            return go<B, kF64, float, double, false>(d_desc, p, s);
+        case SPAMM_LEAF_F32:
+            return p.sp2 ? go<B, kF32, float, float, true>(d_desc, p, s) : go<B, kF32, float, float, false>(d_desc, p, s);
+        case SPAMM_LEAF_BF16:
+            return p.sp2 ? go<B, kBF16, float, float, true>(d_desc, p, s) : go<B, kBF16, float, float, false>(d_desc, p, s);
+        case SPAMM_LEAF_BF16X3:
+            return p.sp2 ? go<B, kBF16X3, float, float, true>(d_desc, p, s)
+                         : go<B, kBF16X3, float, float, false>(d_desc, p, s);
+        case SPAMM_LEAF_F16:
+            return p.sp2 ? go<B, kF16, float, float, true>(d_desc, p, s) : go<B, kF16, float, float, false>(d_desc, p, s);
+        case SPAMM_LEAF_F16X3:
+            return p.sp2 ? go<B, kF16X3, float, float, true>(d_desc, p, s)
+                         : go<B, kF16X3, float, float, false>(d_desc, p, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+// a_f64 is carried in the plan via the descriptor of product 0 (all products of
+// one launch share operand types).
+hipError_t launch_leaf_typed(const ProdDesc* d_desc, const LeafPlan& p, bool a_f64, hipStream_t s) {
+    switch (p.b) {
+        case 32: return dispatch_b<32>(d_desc, p, a_f64, s);
+        case 64: return dispatch_b<64>(d_desc, p, a_f64, s);
+        case 128: return dispatch_b<128>(d_desc, p, a_f64, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace spamm

@@ -1,0 +1,313 @@
+// Quadtree construction on gfx950: packing into b x b tiles, the FP64 leaf
+// norms in their fixed summation order, and the upper tiers (section 2,
+// Eq. 1; Frobenius norm as in section 3).
+//
+// One wavefront owns a strip of b rows by 64*V columns (V elements of 16
+// bytes per lane), so each row of the strip is one 1 KiB coalesced load and
+// each lane streams its V columns down all b rows, accumulating x*x with a
+// fused multiply-add in FP64 (exact for FP32 inputs).  The column sums of a
+// tile are then combined by the pairwise tree s_c += s_{c+h}, h = b/2 .. 1,
+// across lanes (shuffles) and finally inside a lane.
+#include "spamm_internal.hpp"
+
+namespace spamm {
+namespace {
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using type = float4;
+    static constexpr int V = 4;
+};
+template <>
+struct Vec16<double> {
+    using type = double2;
+    static constexpr int V = 2;
+};
+
+__device__ inline double shfl_down_d(double v, int d) { return __shfl_down(v, d, kWave); }
+__device__ inline float shfl_xor_f(float v, int d) { return __shfl_xor(v, d, kWave); }
+
+// Exponent e with max|x| in [2^e, 2^(e+1)); -128 for an all-zero tile.
+__device__ inline int8_t tile_exponent(double mx) {
+    if (!(mx > 0.0)) return (int8_t)-128;
+    int e = ilogb(mx);
+    e = e < -127 ? -127 : (e > 127 ? 127 : e);
+    return (int8_t)e;
+}
+
+template <typename T, int B>
+__global__ void __launch_bounds__(256) k_pack_norm(const T* __restrict__ a, int64_t n, int64_t lda,
+                                                   int64_t nb, int64_t nstrips, T* __restrict__ tiles,
+                                                   double* __restrict__ S0, int8_t* __restrict__ texp,
+                                                   unsigned* status, int vec) {
+    constexpr int V = Vec16<T>::V;
+    constexpr int LPT = B / V;  // lanes per tile
+    using VT = typename Vec16<T>::type;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (gw >= nb * nstrips) return;
+    const int64_t I = gw / nstrips;
+    const int64_t s = gw % nstrips;
+    const int64_t col = s * (int64_t)(kWave * V) + (int64_t)lane * V;
+    const int64_t K = col / B;
+    const int cin = (int)(col % B);
+    const bool live = K < nb;
+
+    double acc[V];
+    double mx = 0.0;
+#pragma unroll
+    for (int j = 0; j < V; ++j) acc[j] = 0.0;
+
+    T* tdst = tiles + ((I * nb + (live ? K : 0)) * B) * (int64_t)B + cin;
+#pragma unroll 8
+    for (int r = 0; r < B; ++r) {
+        const int64_t row = I * B + r;
+        T x[V];
+        if (vec) {
+            if (row < n && col < n) {
+                VT v = *reinterpret_cast<const VT*>(a + row * lda + col);
+                const T* pv = reinterpret_cast<const T*>(&v);
+#pragma unroll
+                for (int j = 0; j < V; ++j) x[j] = pv[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < V; ++j) x[j] = (T)0;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) x[j] = (row < n && col + j < n) ? a[row * lda + col + j] : (T)0;
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            double xd = (double)x[j];
+            acc[j] = __fma_rn(xd, xd, acc[j]);
+            mx = fmax(mx, fabs(xd));
+        }
+        if (live) {
+            VT v;
+            T* pv = reinterpret_cast<T*>(&v);
+#pragma unroll
+            for (int j = 0; j < V; ++j) pv[j] = x[j];
+            *reinterpret_cast<VT*>(tdst + (int64_t)r * B) = v;
+        }
+    }
+    // pairwise tree over the b columns of the tile: first across lanes ...
+    const int tl = lane % LPT;
+#pragma unroll
+    for (int h = B / 2; h >= V; h /= 2) {
+        const int d = h / V;
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            double o = shfl_down_d(acc[j], d);
+            if (tl < d) acc[j] = acc[j] + o;
+        }
+    }
+    // ... then inside the lane
+#pragma unroll
+    for (int h = V / 2; h >= 1; h /= 2)
+#pragma unroll
+        for (int c = 0; c < h; ++c) acc[c] = acc[c] + acc[c + h];
+    // tile max |x| for the power-of-two scaling of 16-bit leaves
+#pragma unroll
+    for (int d = 1; d < LPT; d *= 2) mx = fmax(mx, (double)__shfl_xor(mx, d, kWave));
+    if (live && tl == 0) {
+        S0[I * nb + K] = acc[0];
+        texp[I * nb + K] = tile_exponent(mx);
+        if (!isfinite(acc[0])) atomicOr(status, kDevNonFinite);
+    }
+}
+
+// One tier up: P[I,K] = (S[2I,2K] + S[2I,2K+1]) + (S[2I+1,2K] + S[2I+1,2K+1]).
+__global__ void k_norm_parent(const double* __restrict__ S, int m, double* __restrict__ P, int mp,
+                              const int* active) {
+    if (active && *active == 0) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)mp * mp) return;
+    const int I = (int)(t / mp), K = (int)(t % mp);
+    double c[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = 2 * I + (q >> 1), k = 2 * K + (q & 1);
+        c[q] = (i < m && k < m) ? S[(int64_t)i * m + k] : 0.0;
+    }
+    P[t] = (c[0] + c[1]) + (c[2] + c[3]);
+}
+
+// The small upper tiers in one block, tier by tier.
+__global__ void __launch_bounds__(1024) k_norm_small_tiers(double* __restrict__ norms, const int64_t* off,
+                                                           const int* mm, int l0, int L, const int* active) {
+    if (active && *active == 0) return;
+    for (int l = l0; l <= L; ++l) {
+        const double* S = norms + off[l - 1];
+        double* P = norms + off[l];
+        const int m = mm[l - 1], mp = mm[l];
+        for (int t = threadIdx.x; t < mp * mp; t += blockDim.x) {
+            const int I = t / mp, K = t % mp;
+            double c[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 2 * I + (q >> 1), k = 2 * K + (q & 1);
+                c[q] = (i < m && k < m) ? S[(int64_t)i * m + k] : 0.0;
+            }
+            P[t] = (c[0] + c[1]) + (c[2] + c[3]);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void k_to_dense(const T* __restrict__ tiles, int64_t n, int b, int64_t nb, T* __restrict__ out,
+                           int64_t ldo) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t row = t / n, col = t % n;
+    if (row >= n) return;
+    const int64_t I = row / b, K = col / b;
+    out[row * ldo + col] = tiles[((I * nb + K) * b + (row % b)) * b + (col % b)];
+}
+
+template <typename TX, typename TY>
+__global__ void __launch_bounds__(256) k_diff_norms(const TX* __restrict__ x, const TY* __restrict__ y,
+                                                    int64_t count, double* __restrict__ out) {
+    double d2 = 0.0, r2 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double yv = (double)y[i];
+        const double dv = (double)x[i] - yv;
+        d2 = __fma_rn(dv, dv, d2);
+        r2 = __fma_rn(yv, yv, r2);
+    }
+    for (int d = kWave / 2; d >= 1; d /= 2) {
+        d2 += __shfl_down(d2, d, kWave);
+        r2 += __shfl_down(r2, d, kWave);
+    }
+    __shared__ double sd[4], sr[4];
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        sd[w] = d2;
+        sr[w] = r2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b2 = 0.0;
+        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
+            a += sd[i];
+            b2 += sr[i];
+        }
+        out[2 * blockIdx.x] = a;
+        out[2 * blockIdx.x + 1] = b2;
+    }
+}
+
+__global__ void k_clear_u64(unsigned long long* p, int count, const int* active) {
+    if (active && *active == 0) return;
+    if ((int)threadIdx.x < count) p[threadIdx.x] = 0ull;
+}
+
+__global__ void k_fill_u64(uint64_t* p, int64_t count, uint64_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <typename T, int B>
+hipError_t pack_t(const void* a, int64_t n, int64_t lda, spamm_matrix* M, unsigned* status, hipStream_t s) {
+    constexpr int V = Vec16<T>::V;
+    const int64_t nb = M->nb;
+    const int64_t nstrips = (nb * B + kWave * V - 1) / (kWave * V);
+    const int64_t waves = nb * nstrips;
+    const int64_t blocks = (waves + 3) / 4;
+    const int vec = ((uintptr_t)a % 16 == 0) && (lda % V == 0) && (n % V == 0);
+    hipLaunchKernelGGL((k_pack_norm<T, B>), dim3((unsigned)blocks), dim3(256), 0, s, (const T*)a, n, lda, nb,
+                       nstrips, (T*)M->tiles, M->norms, M->texp, status, vec);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_pack_norm(const void* a, int64_t n, int64_t lda, spamm_dtype dt, spamm_matrix* M,
+                            unsigned* status, hipStream_t s) {
+    if (dt == SPAMM_F32) {
+        switch (M->b) {
+            case 32: return pack_t<float, 32>(a, n, lda, M, status, s);
+            case 64: return pack_t<float, 64>(a, n, lda, M, status, s);
+            case 128: return pack_t<float, 128>(a, n, lda, M, status, s);
+        }
+    } else {
+        switch (M->b) {
+            case 32: return pack_t<double, 32>(a, n, lda, M, status, s);
+            case 64: return pack_t<double, 64>(a, n, lda, M, status, s);
+            case 128: return pack_t<double, 128>(a, n, lda, M, status, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+// Upper tiers: one launch per large tier, then the small ones in one block.
+hipError_t launch_upper_norms(spamm_matrix* M, hipStream_t s, const int* active) {
+    constexpr int kSmall = 64;  // tiers with m_l <= kSmall go to the single-block kernel
+    int l = 1;
+    for (; l <= M->L && M->lvl_m[l] > kSmall; ++l) {
+        const int m = M->lvl_m[l - 1], mp = M->lvl_m[l];
+        const int64_t cnt = (int64_t)mp * mp;
+        hipLaunchKernelGGL(k_norm_parent, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
+                           M->norms + M->lvl_off[l - 1], m, M->norms + M->lvl_off[l], mp, active);
+    }
+    if (l <= M->L) {
+        // tier offsets/sizes travel as kernel arguments through a small device table
+        // kept at the end of the pyramid allocation
+        int64_t* off = reinterpret_cast<int64_t*>(M->norms + M->norms_total);
+        int* mm = reinterpret_cast<int*>(off + kMaxLevels);
+        hipLaunchKernelGGL(k_norm_small_tiers, dim3(1), dim3(1024), 0, s, M->norms, off, mm, l, M->L, active);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_to_dense(const spamm_matrix* M, void* out, int64_t ldo, hipStream_t s) {
+    const int64_t cnt = M->n * M->n;
+    const unsigned blocks = (unsigned)((cnt + 255) / 256);
+    if (M->dt == SPAMM_F32)
+        hipLaunchKernelGGL(k_to_dense<float>, dim3(blocks), dim3(256), 0, s, (const float*)M->tiles, M->n, M->b,
+                           M->nb, (float*)out, ldo);
+    else
+        hipLaunchKernelGGL(k_to_dense<double>, dim3(blocks), dim3(256), 0, s, (const double*)M->tiles, M->n,
+                           M->b, M->nb, (double*)out, ldo);
+    return hipGetLastError();
+}
+
+// Padding is zero in both handles, so the padded tile storage can be
+// compared element by element.
+hipError_t launch_diff_norms(const spamm_matrix* X, const spamm_matrix* Y, double* d_out, hipStream_t s) {
+    const int64_t count = X->nb * X->nb * (int64_t)X->b * X->b;
+    const unsigned blocks = 1024;
+    const bool xf = X->dt == SPAMM_F32, yf = Y->dt == SPAMM_F32;
+    if (xf && yf)
+        hipLaunchKernelGGL((k_diff_norms<float, float>), dim3(blocks), dim3(256), 0, s, (const float*)X->tiles,
+                           (const float*)Y->tiles, count, d_out);
+    else if (xf)
+        hipLaunchKernelGGL((k_diff_norms<float, double>), dim3(blocks), dim3(256), 0, s, (const float*)X->tiles,
+                           (const double*)Y->tiles, count, d_out);
+    else if (yf)
+        hipLaunchKernelGGL((k_diff_norms<double, float>), dim3(blocks), dim3(256), 0, s, (const double*)X->tiles,
+                           (const float*)Y->tiles, count, d_out);
+    else
+        hipLaunchKernelGGL((k_diff_norms<double, double>), dim3(blocks), dim3(256), 0, s,
+                           (const double*)X->tiles, (const double*)Y->tiles, count, d_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_nonempty(unsigned long long* p, int count, const int* active, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(256), 0, s, p, count, active);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, count, v);
+    return hipGetLastError();
+}
+
+}  // namespace spamm

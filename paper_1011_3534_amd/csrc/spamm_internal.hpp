@@ -1,0 +1,157 @@
+// Internal declarations of the gfx950 SpAMM library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/spamm.h"
+
+namespace spamm {
+
+constexpr int kMaxLevels = SPAMM_MAX_LEVELS;
+constexpr int kMaxBatch = 128;
+constexpr int kWave = 64;
+
+// Status bits latched on the device, surfaced by the next syncing call.
+constexpr unsigned kDevNonFinite = 1u;
+constexpr unsigned kDevCapacity = 2u;
+
+// Frontier key of an octree node: product index m (7 bits) | I | J | K (19 bits each).
+__host__ __device__ inline uint64_t node_key(uint32_t m, uint32_t I, uint32_t J, uint32_t K) {
+    return ((uint64_t)m << 57) | ((uint64_t)I << 38) | ((uint64_t)J << 19) | (uint64_t)K;
+}
+__host__ __device__ inline uint32_t key_m(uint64_t k) { return (uint32_t)(k >> 57); }
+__host__ __device__ inline uint32_t key_i(uint64_t k) { return (uint32_t)((k >> 38) & 0x7FFFF); }
+__host__ __device__ inline uint32_t key_j(uint64_t k) { return (uint32_t)((k >> 19) & 0x7FFFF); }
+__host__ __device__ inline uint32_t key_k(uint64_t k) { return (uint32_t)(k & 0x7FFFF); }
+constexpr int64_t kMaxNb = (int64_t)1 << 19;
+
+// Per-product descriptor read by the cull and leaf kernels.  Operand and
+// result pyramids share the same tier shapes (equal n and leaf).
+struct ProdDesc {
+    const void* A;            // tile-major operand tiles
+    const void* B;
+    void* C;                  // tile-major result tiles
+    const double* SA;         // norm pyramids (tier l at lvl_off[l])
+    const double* SB;
+    double* SC;
+    const int8_t* eA;         // per-tile max exponent (fp16 scaling)
+    const int8_t* eB;
+    int8_t* eC;
+    uint64_t* mask;           // leaf bitmask, W words per C tile
+    double* sp2_part;         // SP2: per-tile FP64 partials (idempotency, trace)
+    const void* X;            // SP2: the operand tiles X_m (== A == B)
+    unsigned long long* nonempty;  // count of C tiles with at least one kept product
+    int64_t lvl_off[kMaxLevels];
+    int32_t lvl_m[kMaxLevels];
+    int64_t tile_base;        // first global C-tile index of this product
+    double tau2;
+    int32_t nb, L, W;
+    int32_t a_f64, b_f64;     // operand tile element types (1 = FP64)
+    int32_t pad_;
+};
+
+// Device-side counters of one product launch sequence.
+struct DevCounters {
+    unsigned long long front_count[kMaxLevels];  // kept nodes stored per tier (frontier sizes)
+    unsigned long long survivors[kMaxBatch][kMaxLevels];
+    double culled_bound[kMaxBatch];
+    unsigned status;
+    unsigned pad_;
+};
+
+// Scratch a result handle owns for the product that writes it.
+struct ProductScratch {
+    uint64_t* mask = nullptr;          // nb*nb*W words
+    uint64_t* front[2] = {nullptr, nullptr};
+    int64_t front_cap = 0;
+    DevCounters* ctr = nullptr;
+    ProdDesc* desc = nullptr;          // device copy of the descriptor
+    ProdDesc host_desc{};              // last uploaded copy
+    bool desc_valid = false;
+    double* sp2_part = nullptr;        // SP2 partial sums (nb*nb + nb)
+};
+
+}  // namespace spamm
+
+struct spamm_matrix {
+    int64_t n = 0;
+    int32_t b = 0;
+    int64_t nb = 0;
+    int32_t L = 0;
+    spamm_dtype dt = SPAMM_F32;
+    size_t elem = 4;
+    void* tiles = nullptr;
+    double* norms = nullptr;
+    int8_t* texp = nullptr;
+    int64_t lvl_off[spamm::kMaxLevels] = {};
+    int32_t lvl_m[spamm::kMaxLevels] = {};
+    int64_t norms_total = 0;
+    spamm::ProductScratch* ps = nullptr;
+    spamm_alloc_fn alloc = nullptr;
+    spamm_dealloc_fn dealloc = nullptr;
+    void* actx = nullptr;
+    hipStream_t last_stream = nullptr;
+    int device = 0;
+};
+
+namespace spamm {
+
+// error plumbing -------------------------------------------------------------
+spamm_status set_error(spamm_status s, const std::string& msg);
+spamm_status hip_error(hipError_t e, const char* what);
+
+#define SPAMM_HIP(call)                                          \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return ::spamm::hip_error(e_, #call); \
+    } while (0)
+
+// allocation ------------------------------------------------------------------
+void* dev_alloc(spamm_matrix* owner, size_t bytes, hipStream_t s);
+void dev_free(spamm_matrix* owner, void* p, hipStream_t s);
+int num_cus();
+
+// launchers (norms.hip) ---------------------------------------------------------
+hipError_t launch_pack_norm(const void* a, int64_t n, int64_t lda, spamm_dtype dt, spamm_matrix* M,
+                            unsigned* status, hipStream_t s);
+hipError_t launch_upper_norms(spamm_matrix* M, hipStream_t s, const int* active);
+hipError_t launch_clear_nonempty(unsigned long long* p, int count, const int* active, hipStream_t s);
+hipError_t launch_to_dense(const spamm_matrix* M, void* out, int64_t ldo, hipStream_t s);
+hipError_t launch_diff_norms(const spamm_matrix* X, const spamm_matrix* Y, double* d_out, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s);
+
+// launchers (cull.hip) ----------------------------------------------------------
+struct CullPlan {
+    int count;              // products in the batch
+    int Lmax;               // highest tier among the products
+    int64_t front_cap;      // capacity of each frontier buffer (keys)
+    int64_t mask_words;     // total leaf-bitmask words
+};
+hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t* mask, uint64_t* front0,
+                          uint64_t* front1, DevCounters* ctr, int want_bound, const int* active,
+                          const int64_t* tier_items, hipStream_t s);
+hipError_t launch_task_keys(const ProdDesc* d_desc, int64_t nb, int W, const uint64_t* mask,
+                            uint64_t* keys_out, unsigned long long* count, int64_t cap, hipStream_t s);
+
+// launchers (leaf.hip) ----------------------------------------------------------
+struct LeafPlan {
+    int count;
+    int64_t total_tiles;    // sum over products of nb^2
+    int b;
+    spamm_leaf_prec prec;
+    bool c_f64;
+    int sp2;                // 1: fuse the TC2 update into the epilogue
+    const int* d_branch;    // SP2: device branch flag (0: X^2, 1: 2X - X^2)
+    const int* d_active;    // SP2: device flag, 0 = skip (converged)
+};
+hipError_t launch_leaf_typed(const ProdDesc* d_desc, const LeafPlan& plan, bool a_f64, hipStream_t s);
+
+// api.hip: cull + leaf products + result pyramid of one product, enqueued
+spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C, double tau,
+                             spamm_leaf_prec prec, hipStream_t s, int want_bound, int sp2, const int* d_branch,
+                             const int* d_active, ProdDesc* d_desc_override);
+
+}  // namespace spamm

@@ -1,0 +1,42 @@
+"""Helpers of the GPU parity tests: upload, oracle comparisons, tolerances."""
+import numpy as np
+
+import oracle
+
+U32 = 2.0 ** -24
+
+# Per-term relative error of one leaf product term a*b, beyond FP32 accumulation
+# (operands are the stored FP32 values; see the leaf-precision definitions):
+#   f32    : exact operands
+#   bf16   : a, b rounded to 8 significant bits (unit roundoff 2^-8) each
+#   bf16x3 : hi/lo split leaves |a - hi - lo| <= 2^-16|a|; lo*lo dropped -> 3 * 2^-16
+#   f16    : 11 significant bits -> 2 * 2^-11 (+ square)
+#   f16x3  : 3 * 2^-22 (power-of-two tile scaling keeps both halves normal
+#            except for entries 2^-17 below their tile maximum, covered by
+#            the absolute slack)
+INPUT_REL = {"f64": 0.0, "f32": 0.0, "bf16": 2 * 2 ** -8 + 2 ** -16, "bf16x3": 3 * 2 ** -16 + 2 ** -24,
+             "f16": 2 * 2 ** -11 + 2 ** -22, "f16x3": 3 * 2 ** -22 + 2 ** -33}
+ACC_U = {"f64": 2.0 ** -53}
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gamma(k, u):
+    return k * u / (1 - k * u)
+
+
+def elementwise_bound(a64, b64, leaf, tau, prec):
+    """Bound on |C_gpu - C_oracle| for the same kept triples.
+
+    (|A||B|)_kept is the oracle SpAMM of |A|, |B| (same squares -> same norms
+    -> same kept set).  Terms: operand representation error, accumulation in
+    the leaf's accumulator over at most n terms, rounding of the stored result."""
+    n = a64.shape[0]
+    absprod, _ = oracle.spamm_flat(np.abs(a64), np.abs(b64), leaf, tau)
+    u = ACC_U.get(prec, U32)
+    rel = INPUT_REL[prec] * (1 + gamma(n, u)) + gamma(n + 2, u) + (U32 if prec != "f64" else 2 ** -53)
+    slack = 2.0 ** -36 * np.max(np.abs(a64)) * np.max(np.abs(b64)) * n if prec.startswith("f16") else 0.0
+    return rel * absprod + slack

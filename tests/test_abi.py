@@ -1,0 +1,71 @@
+"""The C ABI library loads and exports what include/*.h declares; host-side
+argument checks return SPAMM_EINVAL before any device work (no GPU needed)."""
+import ctypes
+import os
+
+import pytest
+
+import paper_1011_3534_amd as sp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib_or_skip():
+    if not os.path.exists(sp.LIB_PATH):
+        pytest.skip("libspamm.so not built (run paper_1011_3534_amd.build)")
+    return sp.lib()
+
+
+def test_every_declared_symbol_is_exported():
+    L = _lib_or_skip()
+    names = sp.declared_symbols()
+    assert {"spamm_build", "spamm_multiply", "spamm_sp2"} <= set(names)
+    for name in names:
+        assert hasattr(L, name), f"{name} declared in include/ but not exported"
+
+
+def test_build_rejects_bad_arguments():
+    L = _lib_or_skip()
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.spamm_build(None, 16, 16, 1, 64, None, ctypes.byref(h)) == 1          # null input
+    assert L.spamm_build(fake, 0, 16, 1, 64, None, ctypes.byref(h)) == 1           # n < 1
+    assert L.spamm_build(fake, 16, 8, 1, 64, None, ctypes.byref(h)) == 1           # lda < n
+    assert L.spamm_build(fake, 16, 16, 1, 48, None, ctypes.byref(h)) == 1          # bad leaf
+    assert L.spamm_build(fake, 16, 16, 1, 16, None, ctypes.byref(h)) == 1          # leaf 16 not built
+    assert L.spamm_build(fake, 16, 16, 9, 64, None, ctypes.byref(h)) == 1          # bad dtype
+    assert L.spamm_build(fake, 16, 16, 1, 64, None, None) == 1                     # null out
+    assert h.value is None
+    assert b"leaf" in L.spamm_last_error() or b"null" in L.spamm_last_error()
+
+
+def test_multiply_rejects_null_operands():
+    L = _lib_or_skip()
+    h = ctypes.c_void_p()
+    assert L.spamm_multiply(None, None, 1e-6, 1, None, ctypes.byref(h), None) == 1
+    assert L.spamm_multiply(None, None, 1e-6, 1, None, None, None) == 1
+    assert h.value is None
+
+
+def test_helpers_reject_null():
+    L = _lib_or_skip()
+    assert L.spamm_to_dense(None, None, 1, None) == 1
+    assert L.spamm_norms(None, 0, None, 0, None) == 1
+    cnt = ctypes.c_int64()
+    assert L.spamm_task_list(None, None, 0, ctypes.byref(cnt), None) == 1
+    assert L.spamm_info(None, None, None, None, None) == 1
+    L.spamm_free(None)                                                           # no-op
+
+
+def test_set_allocator_requires_both_functions():
+    L = _lib_or_skip()
+    alloc = sp._ALLOC_FN(lambda n, c: None)
+    assert L.spamm_set_allocator(alloc, sp._DEALLOC_FN(), None) == 1
+    assert L.spamm_set_allocator(sp._ALLOC_FN(), sp._DEALLOC_FN(), None) == 0
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(sp, "_lib", None)
+    monkeypatch.setattr(sp, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        sp.lib()
