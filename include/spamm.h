@@ -118,9 +118,11 @@ typedef struct {
  *   dev_a : device pointer, n x n row-major, leading dimension lda (elements)
  *   dt    : element type of dev_a; the tiles are stored in the same type
  *   leaf  : b in {32, 64, 128}
- *   out   : receives a new handle: zero-padded tile-major storage (b x b
- *           tiles, row-major inside, tiles in (I, K) row-major order) and the
- *           FP64 squared-norm pyramid of all tiers.
+ *   out   : in/out.  If *out is NULL it receives a new handle: zero-padded
+ *           tile-major storage (b x b tiles, row-major inside, tiles in
+ *           (I, K) row-major order) and the FP64 squared-norm pyramid of all
+ *           tiers.  If *out is a handle of the same n, leaf and dtype it is
+ *           rebuilt in place (no allocation).
  * One pass over dev_a computes the packed tiles and the leaf norms; the
  * upper tiers follow.  Errors: EINVAL (n < 1, lda < n, bad leaf/dtype, null
  * pointers), ENOMEM, EHIP. */
@@ -146,6 +148,21 @@ spamm_status spamm_build(const void* dev_a, int64_t n, int64_t lda, spamm_dtype 
 spamm_status spamm_multiply(const spamm_matrix* A, const spamm_matrix* B, double tau,
                             spamm_leaf_prec prec, void* stream, spamm_matrix** C,
                             spamm_stats* st);
+
+/* Phase durations of one product, from HIP events on the caller's stream. */
+typedef struct {
+    double ms_cull;    /* counter reset, mask clear and every cull tier      */
+    double ms_leaf;    /* the leaf-product launch (incl. its epilogue)       */
+    double ms_norms;   /* upper tiers of the result's norm pyramid           */
+    double ms_total;   /* first to last event                                */
+} spamm_timing;
+
+/* spamm_multiply with phase timing: same arguments and result; records HIP
+ * events between the phases on `stream`, synchronises, and fills *t.
+ * Errors: as spamm_multiply; EINVAL if t is NULL. */
+spamm_status spamm_multiply_timed(const spamm_matrix* A, const spamm_matrix* B, double tau,
+                                  spamm_leaf_prec prec, void* stream, spamm_matrix** C,
+                                  spamm_timing* t);
 
 /* count independent products C_m ~= A_m B_m in one pass: one cull over every
  * root and ONE persistent leaf-product launch over the union of all C tiles

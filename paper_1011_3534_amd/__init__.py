@@ -43,6 +43,14 @@ class Stats(ctypes.Structure):
                 "flops": float(self.flops), "culled_bound": float(self.culled_bound)}
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [("ms_cull", ctypes.c_double), ("ms_leaf", ctypes.c_double), ("ms_norms", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Sp2Log(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("stagnated", ctypes.c_int32), ("result_step", ctypes.c_int32),
@@ -83,6 +91,7 @@ def lib():
     sig = {
         "spamm_build": ([_VP, i64, i64, i32, i32, _VP, PP], i32),
         "spamm_multiply": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Stats)], i32),
+        "spamm_multiply_timed": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Timing)], i32),
         "spamm_multiply_batched": ([i32, PP, PP, ctypes.POINTER(dbl), i32, _VP, PP, ctypes.POINTER(Stats)], i32),
         "spamm_sp2": ([_VP, i64, dbl, i32, dbl, i32, _VP, PP, ctypes.POINTER(Sp2Log)], i32),
         "spamm_to_dense": ([_VP, _VP, i64, _VP], i32),
@@ -205,8 +214,10 @@ class Matrix:
         return np.sort(keys[:cnt.value])
 
 
-def build(a, leaf: int, stream=None) -> Matrix:
-    """Quadtree of a dense CUDA tensor (float32 or float64, row-major)."""
+def build(a, leaf: int, out: Matrix | None = None, stream=None) -> Matrix:
+    """Quadtree of a dense CUDA tensor (float32 or float64, row-major).
+
+    With out given (same n, leaf, dtype) the handle is rebuilt in place."""
     import torch
     if not (a.is_cuda and a.dim() == 2 and a.shape[0] == a.shape[1]):
         raise ValueError("build expects a square CUDA tensor")
@@ -214,16 +225,16 @@ def build(a, leaf: int, stream=None) -> Matrix:
         raise ValueError("build expects float32 or float64")
     if a.stride(1) != 1:
         raise ValueError("build expects unit column stride")
-    h = ctypes.c_void_p()
+    h = ctypes.c_void_p(out.handle.value if out is not None else None)
     _check(lib().spamm_build(ctypes.c_void_p(a.data_ptr()), a.shape[0], a.stride(0),
                              0 if a.dtype == torch.float64 else 1, leaf, _stream(stream), ctypes.byref(h)))
-    return Matrix(h)
+    return out if out is not None else Matrix(h)
 
 
 def multiply(A: Matrix, B: Matrix, tau: float, prec: str = "f32", out: Matrix | None = None,
              stats: bool = False, stream=None):
     """C ~= A B by the SpAMM recursion (Eq. 4).  Returns C, or (C, stats dict)."""
-    h = ctypes.c_void_p(out.handle if out is not None else None)
+    h = ctypes.c_void_p(out.handle.value if out is not None else None)
     st = Stats() if stats else None
     _check(lib().spamm_multiply(A.handle, B.handle, float(tau), LEAF[prec], _stream(stream), ctypes.byref(h),
                                 ctypes.byref(st) if st is not None else None))
@@ -231,12 +242,23 @@ def multiply(A: Matrix, B: Matrix, tau: float, prec: str = "f32", out: Matrix | 
     return (C, st.to_dict()) if stats else C
 
 
+def multiply_timed(A: Matrix, B: Matrix, tau: float, prec: str = "f32", out: Matrix | None = None,
+                   stream=None):
+    """multiply with HIP-event phase timing; returns (C, timing dict in ms)."""
+    h = ctypes.c_void_p(out.handle.value if out is not None else None)
+    t = Timing()
+    _check(lib().spamm_multiply_timed(A.handle, B.handle, float(tau), LEAF[prec], _stream(stream), ctypes.byref(h),
+                                      ctypes.byref(t)))
+    C = out if out is not None else Matrix(h)
+    return C, t.to_dict()
+
+
 def multiply_batched(As, Bs, taus, prec: str = "f32", outs=None, stats: bool = False, stream=None):
     """Independent products C_m ~= A_m B_m in one cull pass and one leaf launch."""
     count = len(As)
-    PA = (ctypes.c_void_p * count)(*[a.handle for a in As])
-    PB = (ctypes.c_void_p * count)(*[b.handle for b in Bs])
-    PC = (ctypes.c_void_p * count)(*[(o.handle if o is not None else None) for o in (outs or [None] * count)])
+    PA = (ctypes.c_void_p * count)(*[a.handle.value for a in As])
+    PB = (ctypes.c_void_p * count)(*[b.handle.value for b in Bs])
+    PC = (ctypes.c_void_p * count)(*[(o.handle.value if o is not None else None) for o in (outs or [None] * count)])
     T = (ctypes.c_double * count)(*[float(t) for t in taus])
     st = (Stats * count)() if stats else None
     _check(lib().spamm_multiply_batched(count, PA, PB, T, LEAF[prec], _stream(stream), PC,

@@ -21,6 +21,7 @@ spamm_alloc_fn g_alloc = nullptr;
 spamm_dealloc_fn g_dealloc = nullptr;
 void* g_actx = nullptr;
 std::mutex g_mu;
+thread_local hipEvent_t* t_phase = nullptr;  // set by spamm_multiply_timed
 }  // namespace
 
 spamm_status set_error(spamm_status s, const std::string& msg) {
@@ -133,6 +134,7 @@ spamm_status alloc_storage(spamm_matrix* M, hipStream_t s) {
     int* mm = reinterpret_cast<int*>(off + kMaxLevels);
     SPAMM_HIP(hipMemcpyAsync(off, M->lvl_off, sizeof(int64_t) * kMaxLevels, hipMemcpyHostToDevice, s));
     SPAMM_HIP(hipMemcpyAsync(mm, M->lvl_m, sizeof(int32_t) * kMaxLevels, hipMemcpyHostToDevice, s));
+    SPAMM_HIP(hipMemsetAsync(mm + kMaxLevels, 0, 64, s));  // status word
     return SPAMM_OK;
 }
 
@@ -263,6 +265,7 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
     cp.mask_words = C->nb * C->nb * ceil_div(C->nb, 64);
     int64_t items[kMaxLevels];
     tier_items(C, ps->front_cap, items);
+    if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[0], s));
     SPAMM_HIP(launch_clear_nonempty(nonempty_ctr(ps->ctr), 1, d_active, s));
     SPAMM_HIP(launch_cull_ex(d_desc, cp, ps->mask, ps->front[0], ps->front[1], ps->ctr, want_bound, d_active, items, s));
     LeafPlan lp;
@@ -274,8 +277,11 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
     lp.sp2 = sp2;
     lp.d_branch = d_branch;
     lp.d_active = d_active;
+    if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[1], s));
     SPAMM_HIP(launch_leaf_typed(d_desc, lp, A->dt == SPAMM_F64, s));
+    if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[2], s));
     SPAMM_HIP(launch_upper_norms(C, s, d_active));
+    if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[3], s));
     return SPAMM_OK;
 }
 
@@ -294,19 +300,26 @@ spamm_status spamm_build(const void* dev_a, int64_t n, int64_t lda, spamm_dtype 
     if (!leaf_ok(leaf)) return set_error(SPAMM_EINVAL, "leaf must be 32, 64 or 128");
     if (ceil_div(n, leaf) > kMaxNb) return set_error(SPAMM_EINVAL, "n / leaf exceeds 2^19 leaves");
     hipStream_t s = (hipStream_t)stream;
-    spamm_matrix* M = new_handle(n, leaf, dt);
-    M->last_stream = s;
-    spamm_status st = alloc_storage(M, s);
-    if (st != SPAMM_OK) {
-        release(M);
-        return st;
+    spamm_matrix* M = *out;
+    const bool fresh = M == nullptr;
+    spamm_status st = SPAMM_OK;
+    if (fresh) {
+        M = new_handle(n, leaf, dt);
+        st = alloc_storage(M, s);
+        if (st != SPAMM_OK) {
+            release(M);
+            return st;
+        }
+    } else if (M->n != n || M->b != leaf || M->dt != dt) {
+        return set_error(SPAMM_EINVAL, "existing handle differs in n, leaf or dtype");
     }
+    M->last_stream = s;
     hipError_t e = hipMemsetAsync(status_word(M), 0, 4, s);
     if (e == hipSuccess) e = launch_pack_norm(dev_a, n, lda, dt, M, status_word(M), s);
     if (e == hipSuccess) e = launch_upper_norms(M, s, nullptr);
     if (e != hipSuccess) {
         st = hip_error(e, "spamm_build kernels");
-        release(M);
+        if (fresh) release(M);
         return st;
     }
     *out = M;
@@ -345,6 +358,29 @@ spamm_status spamm_multiply(const spamm_matrix* A, const spamm_matrix* B, double
     }
     *C = Cm;
     if (st) return read_stats(Cm, s, st, tau);
+    return SPAMM_OK;
+}
+
+spamm_status spamm_multiply_timed(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,
+                                  void* stream, spamm_matrix** C, spamm_timing* t) {
+    if (!t) return set_error(SPAMM_EINVAL, "timing output is null");
+    static thread_local hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (!ev[0])
+        for (auto& e : ev) SPAMM_HIP(hipEventCreate(&e));
+    t_phase = ev;
+    spamm_status r = spamm_multiply(A, B, tau, prec, stream, C, nullptr);
+    t_phase = nullptr;
+    if (r != SPAMM_OK) return r;
+    SPAMM_HIP(hipEventSynchronize(ev[3]));
+    float a = 0, b = 0, c = 0, d = 0;
+    SPAMM_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
+    SPAMM_HIP(hipEventElapsedTime(&b, ev[1], ev[2]));
+    SPAMM_HIP(hipEventElapsedTime(&c, ev[2], ev[3]));
+    SPAMM_HIP(hipEventElapsedTime(&d, ev[0], ev[3]));
+    t->ms_cull = a;
+    t->ms_leaf = b;
+    t->ms_norms = c;
+    t->ms_total = d;
     return SPAMM_OK;
 }
 

@@ -390,7 +390,9 @@ __global__ void __launch_bounds__(256) k_leaf(const ProdDesc* __restrict__ desc,
         for (int j = 0; j < R; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = wr * (B / 2) + 16 * i + 4 * (lane >> 4) + q;
+                // result layout: f32 16x16x4 / 16x16x32 give row 4*(lane/16) + q,
+                // f64 16x16x4 gives row 4*q + lane/16 (column lane%16 in both)
+                const int r = wr * (B / 2) + 16 * i + (P == kF64 ? 4 * q + (lane >> 4) : 4 * (lane >> 4) + q);
                 const int c = wc * (B / 2) + 16 * j + (lane & 15);
                 Cs[r * G::SC + c] = (CT)acc[i][j][q];
             }
