@@ -486,9 +486,151 @@ spamm_status spamm_multiply_batched(int32_t, const spamm_matrix* const*, const s
     return spamm::set_error(SPAMM_EUNSUPPORTED, "spamm_multiply_batched is not built yet");
 }
 
-spamm_status spamm_sp2(const spamm_matrix*, int64_t, double, int32_t, double, spamm_leaf_prec, void*,
-                       spamm_matrix**, spamm_sp2_log*) {
-    return spamm::set_error(SPAMM_EUNSUPPORTED, "spamm_sp2 is not built yet");
+spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t max_iter, double idem_tol,
+                       spamm_leaf_prec prec, void* stream, spamm_matrix** P, spamm_sp2_log* log) {
+    using namespace spamm;
+    if (!H || !P) return set_error(SPAMM_EINVAL, "null argument");
+    if (n_occ < 0 || n_occ > H->n) return set_error(SPAMM_EINVAL, "n_occ outside [0, n]");
+    if (max_iter < 1 || max_iter > SPAMM_SP2_MAX_ITER) return set_error(SPAMM_EINVAL, "max_iter outside [1, 256]");
+    if (!(idem_tol >= 0.0) || !std::isfinite(idem_tol)) return set_error(SPAMM_EINVAL, "idem_tol must be >= 0");
+    spamm_status v = check_operands(H, H, tau, prec);
+    if (v != SPAMM_OK) return v;
+    if (prec == SPAMM_LEAF_F64 || H->dt != SPAMM_F32)
+        return set_error(SPAMM_EUNSUPPORTED, "SP2 runs on FP32 tiles with FP32 or split 16-bit leaves");
+    hipStream_t s = (hipStream_t)stream;
+    (void)num_cus();  // device query outside the capture
+    spamm_matrix* X[2] = {nullptr, nullptr};
+    spamm_matrix* owner = nullptr;  // allocator context of the scratch block
+    void* scratch = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cs = nullptr;
+    spamm_status r = SPAMM_OK;
+    const int64_t nb = H->nb;
+    const size_t part_bytes = (size_t)(nb * nb + nb) * 8;
+    const size_t off_part = 0, off_lo = (part_bytes + 255) & ~(size_t)255;
+    const size_t off_hi = off_lo + (((size_t)H->n * 8 + 255) & ~(size_t)255);
+    const size_t off_st = off_hi + (((size_t)H->n * 8 + 255) & ~(size_t)255);
+    const size_t off_e = off_st + ((sizeof(Sp2State) + 255) & ~(size_t)255);
+    const size_t total = off_e + (size_t)(nb * nb + 1) * 8;
+    auto cleanup = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cs) (void)hipStreamDestroy(cs);
+        if (scratch && owner) dev_free(owner, scratch, s);
+        scratch = nullptr;
+        for (auto* x : X)
+            if (x) release(x);
+    };
+    for (int i = 0; i < 2 && r == SPAMM_OK; ++i) {
+        X[i] = new_handle(H->n, H->b, SPAMM_F32);
+        X[i]->last_stream = s;
+        r = alloc_storage(X[i], s);
+        if (r == SPAMM_OK) r = ensure_scratch(X[i], s);
+    }
+    if (r == SPAMM_OK) {
+        owner = X[0];
+        scratch = dev_alloc(owner, total, s);
+        if (!scratch) r = set_error(SPAMM_ENOMEM, "SP2 scratch allocation failed");
+    }
+    if (r != SPAMM_OK) {
+        cleanup();
+        return r;
+    }
+    char* base = (char*)scratch;
+    double* part = (double*)(base + off_part);
+    double* glo = (double*)(base + off_lo);
+    double* ghi = (double*)(base + off_hi);
+    Sp2State* st = (Sp2State*)(base + off_st);
+    double* etile = (double*)(base + off_e);
+    double* eout = etile + nb * nb;
+    static thread_local Sp2State h;
+    std::memset(&h, 0, sizeof h);
+    h.n_occ = (double)n_occ;
+    h.tol = idem_tol;
+    h.max_iter = max_iter;
+    auto fail = [&](hipError_t e, const char* what) {
+        r = hip_error(e, what);
+        cleanup();
+        return r;
+    };
+    hipError_t e = hipMemcpyAsync(st, &h, sizeof h, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_gershgorin(H, glo, ghi, st, s);
+    if (e == hipSuccess) e = launch_sp2_init(H, X[0], part, st, s);
+    // descriptors of the two directions X0 -> X1 and X1 -> X0
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        spamm_matrix* src = X[i];
+        spamm_matrix* dst = X[1 - i];
+        ProdDesc d = make_desc(src, src, dst, tau);
+        d.sp2_part = part;
+        d.X = src->tiles;
+        dst->ps->host_desc = d;
+        dst->ps->desc_valid = false;  // differs from any plain product's descriptor
+        e = hipMemcpyAsync(dst->ps->desc, &dst->ps->host_desc, sizeof d, hipMemcpyHostToDevice, s);
+    }
+    if (e != hipSuccess) return fail(e, "spamm_sp2 setup");
+    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return fail(e, "hipStreamCreate");
+    if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return fail(e, "hipStreamBeginCapture");
+    const int* d_branch = &st->branch;
+    const int* d_active = &st->active;
+    for (int m = 0; m < max_iter && r == SPAMM_OK; ++m) {
+        spamm_matrix* src = X[m & 1];
+        spamm_matrix* dst = X[(m + 1) & 1];
+        r = enqueue_product(src, src, dst, tau, prec, cs, 0, 1, d_branch, d_active, dst->ps->desc);
+        if (r == SPAMM_OK) {
+            e = launch_sp2_finalize(part, nb, &dst->ps->ctr->survivors[0][0], st, m, cs);
+            if (e != hipSuccess) r = hip_error(e, "sp2 finalize launch");
+        }
+    }
+    hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (r != SPAMM_OK) {
+        cleanup();
+        return r;
+    }
+    if (ec != hipSuccess) return fail(ec, "hipStreamEndCapture");
+    if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess)
+        return fail(e, "hipGraphInstantiate");
+    if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return fail(e, "hipGraphLaunch");
+    if ((e = hipMemcpyAsync(&h, st, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess) return fail(e, "state copy");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "hipStreamSynchronize");
+    const int res = h.result_step & 1;
+    double energy = 0.0;
+    e = launch_energy(X[res], H, etile, eout, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&energy, eout, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(e, "spamm_sp2 energy");
+    if (log) {
+        std::memset(log, 0, sizeof *log);
+        log->iterations = h.iter;
+        log->converged = h.converged;
+        log->stagnated = h.stagnated;
+        log->result_step = h.result_step;
+        for (int m = 0; m < h.iter && m < SPAMM_SP2_MAX_ITER; ++m) {
+            log->trace[m] = h.trace[m];
+            log->idem[m] = h.idem[m];
+            log->branch[m] = h.br[m];
+            log->tasks[m] = (int64_t)h.tasks[m];
+        }
+        log->final_trace = h.result_step == h.iter ? h.cur_trace : h.trace[h.result_step];
+        log->energy = energy;
+        log->eps_min = h.eps_min;
+        log->eps_max = h.eps_max;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
+    exec = nullptr;
+    graph = nullptr;
+    cs = nullptr;
+    dev_free(owner, scratch, s);
+    scratch = nullptr;
+    *P = X[res];
+    X[res] = nullptr;
+    cleanup();
+    if (!h.converged && !h.stagnated)
+        return set_error(SPAMM_ENOCONV, "SP2 met no stopping rule within max_iter steps");
+    return SPAMM_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,264 @@
+// TC2 / SP2 density-matrix purification on gfx950 (section 3 of the paper;
+// the iteration of Niklasson, Phys. Rev. B 66, 155115, 2002).
+//
+// Device-side pieces: Gershgorin bounds of H, the initial X_0, tile norms of
+// X_0, the per-step finalize (FP64 reductions of the epilogue partials, the
+// branch for the next step and the stopping rules) and E = tr(P H).  Every
+// decision stays on the device so that all steps fit one static hipGraph;
+// steps after the stop see active == 0 and return at once.
+#include "spamm_internal.hpp"
+
+namespace spamm {
+namespace {
+
+constexpr double kStagBelow = 0.1;
+
+// Fixed-order FP64 sum of x[0..count) by one block of 1024 threads.
+__device__ double block_sum_fixed(const double* x, int64_t count, double* red) {
+    const int t = threadIdx.x;
+    const int64_t per = (count + blockDim.x - 1) / blockDim.x;
+    double s = 0.0;
+    for (int64_t i = t * per; i < (t + 1) * per && i < count; ++i) s += x[i];
+    red[t] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h >= 1; h >>= 1) {
+        if (t < h) red[t] = red[t] + red[t + h];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// One wave per row i: d_i = h_ii, r_i = sum_{j != i} |h_ij|  ->  lo = d - r, hi = d + r.
+__global__ void __launch_bounds__(256) k_gersh_rows(const float* __restrict__ H, int64_t n, int b, int64_t nb,
+                                                    double* __restrict__ lo, double* __restrict__ hi) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const int64_t I = i / b, r = i % b;
+    double acc = 0.0, d = 0.0;
+    for (int64_t c = lane; c < n; c += 64) {
+        const double v = (double)H[((I * nb + c / b) * b + r) * b + (c % b)];
+        if (c == i) d = v;
+        else acc += fabs(v);
+    }
+    for (int h = 32; h >= 1; h >>= 1) {
+        acc += __shfl_down(acc, h, 64);
+        d += __shfl_down(d, h, 64);
+    }
+    if (lane == 0) {
+        lo[i] = d - acc;
+        hi[i] = d + acc;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_gersh_reduce(const double* lo, const double* hi, int64_t n, Sp2State* st) {
+    __shared__ double smin[1024], smax[1024];
+    double mn = INFINITY, mx = -INFINITY;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        mn = fmin(mn, lo[i]);
+        mx = fmax(mx, hi[i]);
+    }
+    smin[threadIdx.x] = mn;
+    smax[threadIdx.x] = mx;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + h]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        st->eps_min = smin[0];
+        st->eps_max = smax[0];
+    }
+}
+
+// X_0 = (eps_max I - H) / (eps_max - eps_min) over the padded tile storage
+// (padding stays zero).
+__global__ void k_sp2_init_x(const float* __restrict__ H, float* __restrict__ X, int64_t n, int b, int64_t nb,
+                             const Sp2State* st) {
+    const int64_t total = nb * nb * (int64_t)b * b;
+    const double emax = st->eps_max, den = st->eps_max - st->eps_min;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t tile = e / ((int64_t)b * b), in = e % ((int64_t)b * b);
+        const int64_t row = (tile / nb) * b + in / b, col = (tile % nb) * b + in % b;
+        double x = 0.0;
+        if (row < n && col < n) x = ((row == col ? emax : 0.0) - (double)H[e]) / den;
+        X[e] = (float)x;
+    }
+}
+
+// One wave per tile: squared norm in the fixed order (per column over rows
+// with FMA, then the pairwise column tree), tile exponent, diagonal sum.
+template <int B>
+__global__ void __launch_bounds__(64) k_tile_stats(const float* __restrict__ T, int64_t nb, double* __restrict__ S,
+                                                   int8_t* __restrict__ texp, double* __restrict__ diag) {
+    const int64_t tile = blockIdx.x;
+    const int lane = threadIdx.x;
+    const float* t = T + tile * (int64_t)B * B;
+    double s = 0.0, mx = 0.0, dv = 0.0;
+    if (B == 128) {
+        double s2 = 0.0;
+        for (int r = 0; r < B; ++r) {
+            const double a0 = t[r * B + lane], a1 = t[r * B + lane + 64];
+            s = __fma_rn(a0, a0, s);
+            s2 = __fma_rn(a1, a1, s2);
+            mx = fmax(mx, fmax(fabs(a0), fabs(a1)));
+        }
+        s = s + s2;
+        dv = (double)t[lane * B + lane] + (double)t[(lane + 64) * B + lane + 64];
+    } else if (lane < B) {
+        for (int r = 0; r < B; ++r) {
+            const double a0 = t[r * B + lane];
+            s = __fma_rn(a0, a0, s);
+            mx = fmax(mx, fabs(a0));
+        }
+        dv = t[lane * B + lane];
+    }
+    constexpr int H0 = (B == 128 ? 64 : B) / 2;
+    for (int h = H0; h >= 1; h >>= 1) {
+        const double o = __shfl_down(s, h, 64);
+        if (lane < h) s = s + o;
+    }
+    for (int h = 32; h >= 1; h >>= 1) {
+        const double o = __shfl_down(dv, h, 64);
+        if (lane < h) dv = dv + o;
+        mx = fmax(mx, __shfl_xor(mx, h, 64));
+    }
+    if (lane == 0) {
+        S[tile] = s;
+        int e = -128;
+        if (mx > 0.0) {
+            e = ilogb(mx);
+            e = e < -127 ? -127 : (e > 127 ? 127 : e);
+        }
+        texp[tile] = (int8_t)e;
+        const int64_t I = tile / nb, K = tile % nb;
+        if (I == K) diag[nb * nb + I] = dv;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_sp2_start(const double* part, int64_t nb, Sp2State* st) {
+    __shared__ double red[1024];
+    const double tr = block_sum_fixed(part + nb * nb, nb, red);
+    if (threadIdx.x == 0) {
+        st->cur_trace = tr;
+        st->branch = tr > st->n_occ ? 0 : 1;
+        st->active = 1;
+        st->iter = 0;
+        st->converged = 0;
+        st->stagnated = 0;
+        st->result_step = 0;
+    }
+}
+
+// After step m: e_m from the per-tile partials, tr(X_{m+1}) from the diagonal
+// partials, the stop rules, and the branch of step m+1.
+__global__ void __launch_bounds__(1024) k_sp2_finalize(const double* part, int64_t nb,
+                                                       const unsigned long long* survivors0, Sp2State* st, int m) {
+    if (st->active == 0) return;
+    __shared__ double red[1024];
+    const double e2 = block_sum_fixed(part, nb * nb, red);
+    const double tr_next = block_sum_fixed(part + nb * nb, nb, red);
+    if (threadIdx.x != 0) return;
+    const double e = sqrt(e2);
+    st->trace[m] = st->cur_trace;
+    st->idem[m] = e;
+    st->br[m] = st->branch;
+    st->tasks[m] = *survivors0;
+    st->iter = m + 1;
+    if (e <= st->tol) {
+        st->converged = 1;
+        st->result_step = m + 1;
+        st->active = 0;
+        st->cur_trace = tr_next;
+        return;
+    }
+    if (m >= 2 && st->idem[m - 2] < kStagBelow && e >= st->idem[m - 2]) {
+        st->stagnated = 1;
+        st->result_step = m;
+        st->active = 0;
+        return;
+    }
+    st->cur_trace = tr_next;
+    st->branch = tr_next > st->n_occ ? 0 : 1;
+    st->result_step = m + 1;
+    if (m + 1 >= st->max_iter) st->active = 0;
+}
+
+// E = tr(P H) = sum over tiles (I,K) of <P_IK, (H_KI)^T>, one wave per tile.
+__global__ void __launch_bounds__(64) k_energy_tiles(const float* __restrict__ P, const float* __restrict__ H, int b,
+                                                     int64_t nb, double* __restrict__ out) {
+    const int64_t tile = blockIdx.x;
+    const int64_t I = tile / nb, K = tile % nb;
+    const float* p = P + tile * (int64_t)b * b;
+    const float* h = H + (K * nb + I) * (int64_t)b * b;
+    double s = 0.0;
+    for (int e = threadIdx.x; e < b * b; e += 64) {
+        const int r = e / b, c = e % b;
+        s += (double)p[r * b + c] * (double)h[c * b + r];
+    }
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_down(s, d, 64);
+    if (threadIdx.x == 0) out[tile] = s;
+}
+
+__global__ void __launch_bounds__(1024) k_sum_to(const double* x, int64_t count, double* out) {
+    __shared__ double red[1024];
+    const double s = block_sum_fixed(x, count, red);
+    if (threadIdx.x == 0) *out = s;
+}
+
+__global__ void k_trace_of(const double* part, int64_t nb, double* out) {
+    __shared__ double red[1024];
+    const double s = block_sum_fixed(part + nb * nb, nb, red);
+    if (threadIdx.x == 0) *out = s;
+}
+
+}  // namespace
+
+hipError_t launch_gershgorin(const spamm_matrix* H, double* lo, double* hi, Sp2State* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_gersh_rows, dim3((unsigned)((H->n + 3) / 4)), dim3(256), 0, s, (const float*)H->tiles, H->n,
+                       H->b, H->nb, lo, hi);
+    hipLaunchKernelGGL(k_gersh_reduce, dim3(1), dim3(1024), 0, s, lo, hi, H->n, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_sp2_init(const spamm_matrix* H, spamm_matrix* X, double* part, Sp2State* st, hipStream_t s) {
+    const int64_t total = H->nb * H->nb * (int64_t)H->b * H->b;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_sp2_init_x, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)H->tiles,
+                       (float*)X->tiles, H->n, H->b, H->nb, st);
+    const unsigned tiles = (unsigned)(X->nb * X->nb);
+    switch (X->b) {
+        case 32: hipLaunchKernelGGL(k_tile_stats<32>, dim3(tiles), dim3(64), 0, s, (const float*)X->tiles, X->nb, X->norms, X->texp, part); break;
+        case 64: hipLaunchKernelGGL(k_tile_stats<64>, dim3(tiles), dim3(64), 0, s, (const float*)X->tiles, X->nb, X->norms, X->texp, part); break;
+        case 128: hipLaunchKernelGGL(k_tile_stats<128>, dim3(tiles), dim3(64), 0, s, (const float*)X->tiles, X->nb, X->norms, X->texp, part); break;
+        default: return hipErrorInvalidValue;
+    }
+    hipError_t e = launch_upper_norms(X, s, nullptr);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sp2_start, dim3(1), dim3(1024), 0, s, part, X->nb, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_sp2_finalize(const double* part, int64_t nb, const unsigned long long* survivors0, Sp2State* st,
+                               int m, hipStream_t s) {
+    hipLaunchKernelGGL(k_sp2_finalize, dim3(1), dim3(1024), 0, s, part, nb, survivors0, st, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy(const spamm_matrix* P, const spamm_matrix* H, double* tile_part, double* out,
+                         hipStream_t s) {
+    const int64_t tiles = P->nb * P->nb;
+    hipLaunchKernelGGL(k_energy_tiles, dim3((unsigned)tiles), dim3(64), 0, s, (const float*)P->tiles,
+                       (const float*)H->tiles, P->b, P->nb, tile_part);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(1024), 0, s, tile_part, tiles, out);
+    return hipGetLastError();
+}
+
+}  // namespace spamm

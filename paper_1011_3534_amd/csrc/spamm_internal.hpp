@@ -149,6 +149,27 @@ struct LeafPlan {
 };
 hipError_t launch_leaf_typed(const ProdDesc* d_desc, const LeafPlan& plan, bool a_f64, hipStream_t s);
 
+// SP2 device state (sp2.hip): the branch/active flags read by the product
+// kernels, the per-step log and the stopping parameters.
+struct Sp2State {
+    int branch;          // 0: X <- X^2, 1: X <- 2X - X^2 (for the current step)
+    int active;          // 0 once a stop rule fired
+    int iter, converged, stagnated, result_step, max_iter, pad_;
+    double cur_trace;    // tr(X_iter)
+    double n_occ, tol;
+    double eps_min, eps_max;
+    double trace[SPAMM_SP2_MAX_ITER];
+    double idem[SPAMM_SP2_MAX_ITER];
+    int br[SPAMM_SP2_MAX_ITER];
+    unsigned long long tasks[SPAMM_SP2_MAX_ITER];
+};
+hipError_t launch_gershgorin(const spamm_matrix* H, double* lo, double* hi, Sp2State* st, hipStream_t s);
+hipError_t launch_sp2_init(const spamm_matrix* H, spamm_matrix* X, double* part, Sp2State* st, hipStream_t s);
+hipError_t launch_sp2_finalize(const double* part, int64_t nb, const unsigned long long* survivors0, Sp2State* st,
+                               int m, hipStream_t s);
+hipError_t launch_energy(const spamm_matrix* P, const spamm_matrix* H, double* tile_part, double* out,
+                         hipStream_t s);
+
 // api.hip: cull + leaf products + result pyramid of one product, enqueued
 spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C, double tau,
                              spamm_leaf_prec prec, hipStream_t s, int want_bound, int sp2, const int* d_branch,

@@ -1,0 +1,103 @@
+"""GPU TC2/SP2 purification (hipGraph) against the FP64 oracle and LAPACK."""
+import numpy as np
+import pytest
+
+import oracle
+import spamm_inputs as si
+from gpu_util import to_dev
+from oracle import sp2 as osp2
+
+pytestmark = pytest.mark.gpu
+sp = pytest.importorskip("paper_1011_3534_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _torch_alloc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sp.use_torch_allocator(True)
+    yield
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16x3"])
+def test_sp2_projector_matches_eigh(prec):
+    print(f"[case] sp2 vs eigh prec={prec}", flush=True)
+    n, b, n_occ = 512, 32, 256
+    h = si.sp2_hamiltonian(n, 0.85, 4, np.float32, gap=4.0)
+    H = sp.build(to_dev(h), b)
+    P, log = sp.sp2(H, n_occ, 0.0, max_iter=100, idem_tol=1e-6, prec=prec)
+    assert log["status"] == "OK" and (log["converged"] or log["stagnated"])
+    w, v = np.linalg.eigh(h.astype(np.float64))
+    pe = v[:, :n_occ] @ v[:, :n_occ].T
+    pd = P.to_dense().cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(pd - pe)) < 2e-5
+    assert abs(np.trace(pd) - n_occ) < 1e-3
+    assert abs(log["final_trace"] - np.trace(pd)) < 1e-6 * n
+    assert abs(log["energy"] - w[:n_occ].sum()) < 1e-5 * abs(w[:n_occ].sum())
+    assert abs(log["eps_min"] - osp2.gershgorin(h)[0]) < 1e-12
+    assert abs(log["eps_max"] - osp2.gershgorin(h)[1]) < 1e-12
+    assert 10 <= log["iterations"] <= 100
+
+
+def test_sp2_step_replay_matches_oracle():
+    # feed the GPU's stored X_k into one oracle step: same norms -> same kept
+    # triples (count), same branch; trace, idempotency and X_{k+1} agree
+    n, b, n_occ, tau = 384, 32, 192, 1e-5
+    h = si.sp2_hamiltonian(n, 0.85, 7, np.float32)
+    H = sp.build(to_dev(h), b)
+    for k in (1, 6, 15):
+        print(f"[case] sp2 replay k={k}", flush=True)
+        Pk, logk = sp.sp2(H, n_occ, tau, max_iter=k, idem_tol=0.0)
+        assert logk["status"] == "ENOCONV" and logk["result_step"] == k
+        xk = Pk.to_dense().cpu().numpy().astype(np.float64)
+        Pk1, logk1 = sp.sp2(H, n_occ, tau, max_iter=k + 1, idem_tol=0.0)
+        x_next, tr, idem, br, T = osp2.step(xk, n_occ, b, tau)
+        assert logk1["tasks"][k] == T
+        assert logk1["branch"][k] == br
+        assert abs(logk1["trace"][k] - tr) < 1e-9 * n
+        assert abs(logk1["idem"][k] - idem) < 1e-5 * max(idem, 1.0)
+        got = Pk1.to_dense().cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(got - x_next)) < 1e-5
+        # the k-step prefix of the log is reproduced exactly
+        assert logk1["tasks"][:k] == logk["tasks"][:k]
+        assert logk1["idem"][:k] == logk["idem"][:k]
+
+
+def test_sp2_first_step_from_gershgorin():
+    # step 0 from X_0 = (eps_max I - H)/(eps_max - eps_min), built by the oracle in FP64
+    n, b, n_occ, tau = 256, 32, 128, 1e-6
+    h = si.sp2_hamiltonian(n, 0.85, 9, np.float32)
+    H = sp.build(to_dev(h), b)
+    P1, log = sp.sp2(H, n_occ, tau, max_iter=1, idem_tol=0.0)
+    x0 = osp2.initial_x(h.astype(np.float64)).astype(np.float32).astype(np.float64)
+    x1, tr, idem, br, T = osp2.step(x0, n_occ, b, tau)
+    assert log["tasks"][0] == T and log["branch"][0] == br
+    assert abs(log["trace"][0] - tr) < 1e-9 * n
+    assert np.max(np.abs(P1.to_dense().cpu().numpy() - x1)) < 1e-5
+
+
+def test_sp2_invalid_arguments():
+    h = si.sp2_hamiltonian(128, 0.85, 4, np.float32)
+    H = sp.build(to_dev(h), 32)
+    for kw in ({"n_occ": 129}, {"n_occ": -1}, {"max_iter": 0}, {"max_iter": 257}):
+        args = {"n_occ": 64, "tau": 1e-6, "max_iter": 10}
+        args.update(kw)
+        with pytest.raises(sp.SpammError, match="EINVAL"):
+            sp.sp2(H, **args)
+    H64 = sp.build(to_dev(h.astype(np.float64)), 32)
+    with pytest.raises(sp.SpammError, match="EUNSUPPORTED"):
+        sp.sp2(H64, 64, 1e-6)
+
+
+def test_sp2_truncated_energy_close_to_exact():
+    # tau > 0 inside TC2: energy error small and leaf work well below tau = 0
+    n, b, n_occ = 1024, 64, 512
+    h = si.sp2_hamiltonian(n, 0.85, 4, np.float32)
+    H = sp.build(to_dev(h), b)
+    _, log0 = sp.sp2(H, n_occ, 0.0, max_iter=80, idem_tol=1e-6)
+    _, log1 = sp.sp2(H, n_occ, 1e-5, max_iter=80, idem_tol=1e-6)
+    rel = abs(log1["energy"] - log0["energy"]) / abs(log0["energy"])
+    print(f"[case] sp2 tau=1e-5 dE={rel:.2e} iters={log1['iterations']} vs {log0['iterations']}", flush=True)
+    assert rel < 1e-5
+    assert sum(log1["tasks"]) < 0.7 * sum(log0["tasks"])
