@@ -164,18 +164,37 @@ spamm_status spamm_multiply_timed(const spamm_matrix* A, const spamm_matrix* B, 
                                   spamm_leaf_prec prec, void* stream, spamm_matrix** C,
                                   spamm_timing* t);
 
+/* Leaf-product schedule. */
+typedef enum {
+    SPAMM_SCHED_STATIC = 0,  /* one block per C tile, tiles split into 8 contiguous
+                                ranges, one per XCD (the default of spamm_multiply) */
+    SPAMM_SCHED_LPT = 1      /* persistent blocks pull tiles from a device queue in
+                                order of decreasing kept-K count (largest first)     */
+} spamm_schedule;
+
+typedef struct {
+    int32_t leaf;            /* leaf size the operands were built with (autotuner output) */
+    int32_t schedule;        /* spamm_schedule                                           */
+    int32_t reserved[6];
+} spamm_tune;
+
 /* count independent products C_m ~= A_m B_m in one pass: one cull over every
- * root and ONE persistent leaf-product launch over the union of all C tiles
- * (largest work first).  All operands share the leaf size and leaf
+ * root (products enter at their own root tier) and ONE leaf-product launch
+ * over the union of all C tiles.  All operands share the leaf size and leaf
  * precision; n may differ between products.
  *   tau[m]       : per-product threshold (host array of count doubles)
+ *   tune         : schedule; NULL = SPAMM_SCHED_LPT (tune->leaf is ignored
+ *                  here: it must equal the operands' leaf if set)
  *   C[m]         : in/out as for spamm_multiply
  *   st           : optional host array of count spamm_stats (syncs)
- * Errors: EINVAL (count < 1 or > 128, mismatched pairs), ENOMEM, EHIP. */
+ * Batch scratch (frontiers, counters, schedule) is allocated for the call and
+ * released at its end.
+ * Errors: EINVAL (count < 1 or > 128, mismatched pairs, mixed leaf sizes),
+ * ENOMEM, EHIP. */
 spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
                                     const spamm_matrix* const* B, const double* tau,
-                                    spamm_leaf_prec prec, void* stream, spamm_matrix** C,
-                                    spamm_stats* st);
+                                    spamm_leaf_prec prec, const spamm_tune* tune, void* stream,
+                                    spamm_matrix** C, spamm_stats* st);
 
 /* ------------------------------------------------------------------ SP2 / TC2 */
 

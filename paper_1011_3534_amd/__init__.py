@@ -43,6 +43,13 @@ class Stats(ctypes.Structure):
                 "flops": float(self.flops), "culled_bound": float(self.culled_bound)}
 
 
+SCHEDULE = {"static": 0, "lpt": 1}
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("leaf", ctypes.c_int32), ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
 class Timing(ctypes.Structure):
     _fields_ = [("ms_cull", ctypes.c_double), ("ms_leaf", ctypes.c_double), ("ms_norms", ctypes.c_double),
                 ("ms_total", ctypes.c_double)]
@@ -92,7 +99,8 @@ def lib():
         "spamm_build": ([_VP, i64, i64, i32, i32, _VP, PP], i32),
         "spamm_multiply": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Stats)], i32),
         "spamm_multiply_timed": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Timing)], i32),
-        "spamm_multiply_batched": ([i32, PP, PP, ctypes.POINTER(dbl), i32, _VP, PP, ctypes.POINTER(Stats)], i32),
+        "spamm_multiply_batched": ([i32, PP, PP, ctypes.POINTER(dbl), i32, ctypes.POINTER(Tune), _VP, PP,
+                                    ctypes.POINTER(Stats)], i32),
         "spamm_sp2": ([_VP, i64, dbl, i32, dbl, i32, _VP, PP, ctypes.POINTER(Sp2Log)], i32),
         "spamm_to_dense": ([_VP, _VP, i64, _VP], i32),
         "spamm_info": ([_VP, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -253,16 +261,23 @@ def multiply_timed(A: Matrix, B: Matrix, tau: float, prec: str = "f32", out: Mat
     return C, t.to_dict()
 
 
-def multiply_batched(As, Bs, taus, prec: str = "f32", outs=None, stats: bool = False, stream=None):
-    """Independent products C_m ~= A_m B_m in one cull pass and one leaf launch."""
+def multiply_batched(As, Bs, taus, prec: str = "f32", outs=None, stats: bool = False,
+                     schedule: str | None = None, stream=None):
+    """Independent products C_m ~= A_m B_m in one cull pass and one leaf launch.
+
+    schedule: None/"lpt" (persistent, largest first) or "static"."""
     count = len(As)
     PA = (ctypes.c_void_p * count)(*[a.handle.value for a in As])
     PB = (ctypes.c_void_p * count)(*[b.handle.value for b in Bs])
     PC = (ctypes.c_void_p * count)(*[(o.handle.value if o is not None else None) for o in (outs or [None] * count)])
     T = (ctypes.c_double * count)(*[float(t) for t in taus])
     st = (Stats * count)() if stats else None
-    _check(lib().spamm_multiply_batched(count, PA, PB, T, LEAF[prec], _stream(stream), PC,
-                                        st if st is not None else None))
+    tune = None
+    if schedule is not None:
+        tune = Tune()
+        tune.schedule = SCHEDULE[schedule]
+    _check(lib().spamm_multiply_batched(count, PA, PB, T, LEAF[prec], ctypes.byref(tune) if tune else None,
+                                        _stream(stream), PC, st if st is not None else None))
     Cs = []
     for m in range(count):
         if outs is not None and outs[m] is not None:

@@ -481,9 +481,147 @@ const char* spamm_last_error(void) { return g_err.c_str(); }
 
 extern "C" {
 
-spamm_status spamm_multiply_batched(int32_t, const spamm_matrix* const*, const spamm_matrix* const*, const double*,
-                                    spamm_leaf_prec, void*, spamm_matrix**, spamm_stats*) {
-    return spamm::set_error(SPAMM_EUNSUPPORTED, "spamm_multiply_batched is not built yet");
+spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A, const spamm_matrix* const* B,
+                                    const double* tau, spamm_leaf_prec prec, const spamm_tune* tune, void* stream,
+                                    spamm_matrix** C, spamm_stats* st) {
+    using namespace spamm;
+    if (count < 1 || count > kMaxBatch) return set_error(SPAMM_EINVAL, "count outside [1, 128]");
+    if (!A || !B || !tau || !C) return set_error(SPAMM_EINVAL, "null argument");
+    if (!A[0]) return set_error(SPAMM_EINVAL, "null operand");
+    const int32_t b = A[0]->b;
+    const int sched = tune ? tune->schedule : SPAMM_SCHED_LPT;
+    if (sched != SPAMM_SCHED_STATIC && sched != SPAMM_SCHED_LPT) return set_error(SPAMM_EINVAL, "unknown schedule");
+    if (tune && tune->leaf && tune->leaf != b) return set_error(SPAMM_EINVAL, "tune->leaf differs from the operands");
+    const spamm_dtype cdt = prec == SPAMM_LEAF_F64 ? SPAMM_F64 : SPAMM_F32;
+    for (int m = 0; m < count; ++m) {
+        spamm_status v = check_operands(A[m], B[m], tau[m], prec);
+        if (v != SPAMM_OK) return v;
+        if (A[m]->b != b) return set_error(SPAMM_EINVAL, "products of one batch share the leaf size");
+        if (A[m]->dt != A[0]->dt) return set_error(SPAMM_EINVAL, "products of one batch share the operand type");
+        if (C[m]) {
+            if (C[m]->n != A[m]->n || C[m]->b != b || C[m]->dt != cdt)
+                return set_error(SPAMM_EINVAL, "existing C differs in n, leaf or result type");
+            for (int q = 0; q < count; ++q)
+                if (C[m] == A[q] || C[m] == B[q] || (q != m && C[m] == C[q]))
+                    return set_error(SPAMM_EINVAL, "C handles must be distinct and not alias operands");
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<spamm_matrix*> out(count, nullptr);
+    std::vector<bool> fresh(count, false);
+    spamm_status r = SPAMM_OK;
+    auto release_fresh = [&]() {
+        for (int m = 0; m < count; ++m)
+            if (fresh[m] && out[m]) release(out[m]);
+    };
+    for (int m = 0; m < count && r == SPAMM_OK; ++m) {
+        out[m] = C[m];
+        if (!out[m]) {
+            out[m] = new_handle(A[m]->n, b, cdt);
+            fresh[m] = true;
+            r = alloc_storage(out[m], s);
+        }
+        if (r == SPAMM_OK) {
+            out[m]->last_stream = s;
+            r = ensure_scratch(out[m], s);
+        }
+    }
+    if (r != SPAMM_OK) {
+        release_fresh();
+        return r;
+    }
+    // batch plan
+    int64_t total = 0, cap = 1, items[kMaxLevels] = {};
+    int Lmax = 0, maxc = 1;
+    static thread_local std::vector<ProdDesc> hd;
+    hd.assign(count, ProdDesc{});
+    for (int m = 0; m < count; ++m) {
+        spamm_matrix* Cm = out[m];
+        hd[m] = make_desc(A[m], B[m], Cm, tau[m]);
+        hd[m].tile_base = total;
+        total += Cm->nb * Cm->nb;
+        Lmax = std::max(Lmax, Cm->L);
+        maxc = std::max<int>(maxc, (int)Cm->nb);
+        if (Cm->L >= 2) cap += (int64_t)Cm->lvl_m[1] * Cm->lvl_m[1] * Cm->lvl_m[1];
+        for (int l = 1; l < Cm->L; ++l) items[l] += (int64_t)Cm->lvl_m[l] * Cm->lvl_m[l] * Cm->lvl_m[l];
+    }
+    for (int l = 0; l < kMaxLevels; ++l) items[l] = std::min(items[l], cap);
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_desc = 0, o_f0 = al(sizeof(ProdDesc) * count), o_f1 = o_f0 + al((size_t)cap * 8),
+                 o_ctr = o_f1 + al((size_t)cap * 8), o_cnt = o_ctr + al(sizeof(DevCounters) + 16 * kMaxBatch),
+                 o_ord = o_cnt + al((size_t)total * 4), o_hist = o_ord + al((size_t)total * 4),
+                 o_offs = o_hist + al((size_t)(maxc + 1) * 4), o_q = o_offs + al((size_t)(maxc + 1) * 4),
+                 bytes = o_q + 256;
+    spamm_matrix* owner = out[0];
+    char* ws = (char*)dev_alloc(owner, bytes, s);
+    if (!ws) {
+        release_fresh();
+        return set_error(SPAMM_ENOMEM, "batch scratch allocation failed");
+    }
+    ProdDesc* d_desc = (ProdDesc*)(ws + o_desc);
+    DevCounters* ctr = (DevCounters*)(ws + o_ctr);
+    for (int m = 0; m < count; ++m) {
+        hd[m].nonempty = nonempty_ctr(ctr) + m;
+        out[m]->ps->desc_valid = false;
+    }
+    CullPlan cp;
+    cp.count = count;
+    cp.Lmax = Lmax;
+    cp.front_cap = cap;
+    cp.mask_words = 0;
+    LeafPlan lp;
+    lp.count = count;
+    lp.total_tiles = total;
+    lp.b = b;
+    lp.prec = prec;
+    lp.c_f64 = cdt == SPAMM_F64;
+    lp.sp2 = 0;
+    lp.d_branch = nullptr;
+    lp.d_active = nullptr;
+    if (sched == SPAMM_SCHED_LPT) {
+        lp.order = (uint32_t*)(ws + o_ord);
+        lp.queue = (unsigned long long*)(ws + o_q);
+    }
+    hipError_t e = hipMemcpyAsync(d_desc, hd.data(), sizeof(ProdDesc) * count, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_clear_nonempty(nonempty_ctr(ctr), count, nullptr, s);
+    if (e == hipSuccess) e = launch_clear_masks(d_desc, count, s);
+    if (e == hipSuccess)
+        e = launch_cull_ex(d_desc, cp, nullptr, (uint64_t*)(ws + o_f0), (uint64_t*)(ws + o_f1), ctr, st != nullptr,
+                           nullptr, items, s);
+    if (e == hipSuccess && sched == SPAMM_SCHED_LPT)
+        e = launch_lpt_order(d_desc, count, total, maxc, (uint32_t*)(ws + o_cnt), (uint32_t*)(ws + o_hist),
+                             (uint32_t*)(ws + o_offs), (uint32_t*)(ws + o_ord), lp.queue, s);
+    if (e == hipSuccess) e = launch_leaf_typed(d_desc, lp, A[0]->dt == SPAMM_F64, s);
+    for (int m = 0; m < count && e == hipSuccess; ++m) e = launch_upper_norms(out[m], s, nullptr);
+    if (e == hipSuccess && st) {
+        static thread_local DevCounters h;
+        unsigned long long ne[kMaxBatch];
+        e = hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(ne, nonempty_ctr(ctr), 8 * count, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        for (int m = 0; m < count && e == hipSuccess; ++m) {
+            spamm_stats& o = st[m];
+            std::memset(&o, 0, sizeof o);
+            const spamm_matrix* Cm = out[m];
+            o.n = Cm->n;
+            o.leaf = b;
+            o.levels = Cm->L;
+            o.nb = Cm->nb;
+            for (int l = 0; l <= Cm->L && l < kMaxLevels; ++l) o.survivors[l] = (int64_t)h.survivors[m][l];
+            o.tasks = o.survivors[0];
+            o.nonempty_tiles = (int64_t)ne[m];
+            o.flops = 2.0 * b * (double)b * b * (double)o.tasks;
+            o.culled_bound = h.culled_bound[m];
+        }
+        if (e == hipSuccess && (h.status & kDevCapacity)) r = set_error(SPAMM_ECAPACITY, "frontier capacity exceeded");
+    }
+    dev_free(owner, ws, s);
+    if (e != hipSuccess) {
+        release_fresh();
+        return hip_error(e, "spamm_multiply_batched");
+    }
+    for (int m = 0; m < count; ++m) C[m] = out[m];
+    return r;
 }
 
 spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t max_iter, double idem_tol,

@@ -158,6 +158,15 @@ __global__ void k_clear_mask(uint64_t* mask, int64_t words, const int* active) {
         mask[i] = 0;
 }
 
+// Batch: block (m, y) clears slice y of product m's leaf bitmask.
+__global__ void k_clear_masks(const ProdDesc* __restrict__ desc) {
+    const ProdDesc& d = desc[blockIdx.x];
+    const int64_t words = (int64_t)d.nb * d.nb * d.W;
+    const int64_t per = (words + gridDim.y - 1) / gridDim.y;
+    const int64_t lo = per * blockIdx.y, hi = lo + per < words ? lo + per : words;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) d.mask[i] = 0;
+}
+
 __global__ void k_task_keys(const ProdDesc* __restrict__ desc, int64_t nb, int W, const uint64_t* __restrict__ mask,
                             uint64_t* __restrict__ out, unsigned long long* count, int64_t cap) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -181,7 +190,7 @@ hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t
                           uint64_t* front1, DevCounters* ctr, int want_bound, const int* active,
                           const int64_t* tier_items, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_counters, dim3(8), dim3(256), 0, s, ctr, plan.count, active);
-    {
+    if (mask) {  // (a batch clears its per-product masks with launch_clear_masks)
         int64_t blocks = (plan.mask_words + 255) / 256;
         blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
         hipLaunchKernelGGL(k_clear_mask, dim3((unsigned)blocks), dim3(256), 0, s, mask, plan.mask_words, active);
@@ -198,6 +207,11 @@ hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t
         hipLaunchKernelGGL(k_cull_tier, dim3((unsigned)blocks), dim3(kCullThreads), 0, s, d_desc, plan.count, l,
                            in, out, ctr, plan.front_cap, want_bound, active);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_masks(const ProdDesc* d_desc, int nprod, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_masks, dim3((unsigned)nprod, 64), dim3(256), 0, s, d_desc);
     return hipGetLastError();
 }
 

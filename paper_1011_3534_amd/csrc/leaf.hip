@@ -284,20 +284,14 @@ __device__ inline int find_product(const ProdDesc* desc, int nprod, int64_t t) {
 }
 
 
+// One C tile (global index t) from its kept K to its stored values and norm.
 template <int B, int P, typename TA, typename TC, bool SP2>
-__global__ void __launch_bounds__(256) k_leaf(const ProdDesc* __restrict__ desc, int nprod, int64_t total,
-                                              int64_t chunk, const int* __restrict__ branch,
-                                              const int* __restrict__ active) {
+__device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int nprod, int64_t t, char* smem,
+                                          double (*red)[4], const int* __restrict__ branch) {
     using G = Geo<B, P>;
     using CT = typename G::CT;
     using Acc = typename std::conditional<P == kF64, f64x4, f32x4>::type;
     constexpr int R = G::R, KC = G::KC, NCH = G::NCH;
-    __shared__ __attribute__((aligned(16))) char smem[G::SMEM];
-
-    if (active && *active == 0) return;
-    const int64_t x = blockIdx.x;
-    const int64_t t = (x & 7) * chunk + (x >> 3);
-    if (t >= total) return;
     const int m = nprod > 1 ? find_product(desc, nprod, t) : 0;
     const ProdDesc& d = desc[m];
     const int nb = d.nb;
@@ -427,7 +421,6 @@ __global__ void __launch_bounds__(256) k_leaf(const ProdDesc* __restrict__ desc,
     if constexpr (SP2) __syncthreads();
 
     // block reductions in a fixed order (deterministic)
-    __shared__ double red[2][4];
     for (int dd = 32; dd >= 1; dd >>= 1) {
         mx = fmax(mx, __shfl_xor(mx, dd, 64));
         if constexpr (SP2) idem += __shfl_down(idem, dd, 64);
@@ -493,10 +486,58 @@ __global__ void __launch_bounds__(256) k_leaf(const ProdDesc* __restrict__ desc,
         d.eC[local] = (int8_t)e;
         if constexpr (SP2) d.sp2_part[local] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
     }
+    __syncthreads();  // red and smem are reused by the next tile of a persistent block
+}
+
+// Static schedule: one block per tile; block x runs on XCD x mod 8 and takes
+// tile (x mod 8) * chunk + x / 8, so each XCD walks a contiguous tile range.
+template <int B, int P, typename TA, typename TC, bool SP2>
+__global__ void __launch_bounds__(256) k_leaf(const ProdDesc* __restrict__ desc, int nprod, int64_t total,
+                                              int64_t chunk, const int* __restrict__ branch,
+                                              const int* __restrict__ active) {
+    __shared__ __attribute__((aligned(16))) char smem[Geo<B, P>::SMEM];
+    __shared__ double red[2][4];
+    if (active && *active == 0) return;
+    const int64_t x = blockIdx.x;
+    const int64_t t = (x & 7) * chunk + (x >> 3);
+    if (t >= total) return;
+    leaf_tile<B, P, TA, TC, SP2>(desc, nprod, t, smem, red, branch);
+}
+
+// Persistent schedule: resident blocks pull positions from a queue counter
+// and process tile order[pos] (largest kept-K count first); every block
+// leaves once the queue passes `total`.
+template <int B, int P, typename TA, typename TC, bool SP2>
+__global__ void __launch_bounds__(256) k_leaf_queue(const ProdDesc* __restrict__ desc, int nprod, int64_t total,
+                                                    const uint32_t* __restrict__ order,
+                                                    unsigned long long* __restrict__ queue,
+                                                    const int* __restrict__ branch, const int* __restrict__ active) {
+    __shared__ __attribute__((aligned(16))) char smem[Geo<B, P>::SMEM];
+    __shared__ double red[2][4];
+    __shared__ long long s_pos;
+    if (active && *active == 0) return;
+    while (true) {
+        if (threadIdx.x == 0) s_pos = (long long)atomicAdd(queue, 1ull);
+        __syncthreads();
+        const long long pos = s_pos;
+        __syncthreads();
+        if (pos >= total) break;
+        leaf_tile<B, P, TA, TC, SP2>(desc, nprod, order ? (int64_t)order[pos] : (int64_t)pos, smem, red, branch);
+    }
 }
 
 template <int B, int P, typename TA, typename TC, bool SP2>
 hipError_t go(const ProdDesc* d_desc, const LeafPlan& p, hipStream_t s) {
+    if (p.queue) {
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_leaf_queue<B, P, TA, TC, SP2>, 256, 0);
+        if (e != hipSuccess || per_cu < 1) per_cu = 1;
+        int64_t grid = (int64_t)num_cus() * per_cu;
+        if (grid > p.total_tiles) grid = p.total_tiles < 1 ? 1 : p.total_tiles;
+        hipLaunchKernelGGL((k_leaf_queue<B, P, TA, TC, SP2>), dim3((unsigned)grid), dim3(256), 0, s, d_desc, p.count,
+                           p.total_tiles, p.order, p.queue, p.d_branch, p.d_active);
+        return hipGetLastError();
+    }
     const int64_t chunk = (p.total_tiles + 7) / 8;
     const int64_t grid = chunk * 8;
     hipLaunchKernelGGL((k_leaf<B, P, TA, TC, SP2>), dim3((unsigned)grid), dim3(256), 0, s, d_desc, p.count,

@@ -1,0 +1,89 @@
+// Leaf-product schedule for the persistent launch: every C tile's work is its
+// number of kept K (a popcount of its leaf bitmask); tiles are ordered
+// largest first (LPT) by a counting sort on that number, so a batch of
+// products of very different sizes drains evenly over the resident blocks.
+#include "spamm_internal.hpp"
+
+namespace spamm {
+namespace {
+
+__device__ inline int product_of(const ProdDesc* desc, int nprod, int64_t t) {
+    int lo = 0, hi = nprod - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (desc[mid].tile_base <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_tile_counts(const ProdDesc* __restrict__ desc, int nprod, int64_t total, uint32_t* __restrict__ counts,
+                              uint32_t* __restrict__ hist) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const ProdDesc& d = desc[product_of(desc, nprod, t)];
+        const int64_t local = t - d.tile_base;
+        const uint64_t* w = d.mask + local * d.W;
+        uint32_t c = 0;
+        for (int i = 0; i < d.W; ++i) c += (uint32_t)__popcll(w[i]);
+        counts[t] = c;
+        atomicAdd(&hist[c], 1u);
+    }
+}
+
+// offs[c] = number of tiles with more than c kept K (descending exclusive scan).
+__global__ void __launch_bounds__(1024) k_hist_scan_desc(const uint32_t* hist, int maxc, uint32_t* offs) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (maxc + 1 + 1023) / 1024;
+    // thread t owns counts [t*per, (t+1)*per) walked from the top
+    uint32_t s = 0;
+    for (int c = (t + 1) * per - 1; c >= t * per; --c)
+        if (c <= maxc) s += hist[c];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {  // suffix sums over the 1024 chunks
+        uint32_t run = 0;
+        for (int i = 1023; i >= 0; --i) {
+            const uint32_t v = part[i];
+            part[i] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    uint32_t run = part[t];
+    for (int c = (t + 1) * per - 1; c >= t * per; --c) {
+        if (c > maxc) continue;
+        offs[c] = run;
+        run += hist[c];
+    }
+}
+
+__global__ void k_scatter_order(const uint32_t* __restrict__ counts, int64_t total, uint32_t* __restrict__ offs,
+                                uint32_t* __restrict__ order) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t pos = atomicAdd(&offs[counts[t]], 1u);
+        order[pos] = (uint32_t)t;
+    }
+}
+
+__global__ void k_zero_u32(uint32_t* p, int64_t count, unsigned long long* queue) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && queue) *queue = 0ull;
+}
+
+}  // namespace
+
+// counts/order: total entries; hist/offs: maxc + 1 entries each; queue zeroed.
+hipError_t launch_lpt_order(const ProdDesc* d_desc, int nprod, int64_t total, int maxc, uint32_t* counts,
+                            uint32_t* hist, uint32_t* offs, uint32_t* order, unsigned long long* queue,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, s, hist, (int64_t)maxc + 1, queue);
+    int64_t blocks = (total + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
+    hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)blocks), dim3(256), 0, s, d_desc, nprod, total, counts, hist);
+    hipLaunchKernelGGL(k_hist_scan_desc, dim3(1), dim3(1024), 0, s, hist, maxc, offs);
+    hipLaunchKernelGGL(k_scatter_order, dim3((unsigned)blocks), dim3(256), 0, s, counts, total, offs, order);
+    return hipGetLastError();
+}
+
+}  // namespace spamm

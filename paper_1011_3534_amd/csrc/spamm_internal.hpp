@@ -146,7 +146,13 @@ struct LeafPlan {
     int sp2;                // 1: fuse the TC2 update into the epilogue
     const int* d_branch;    // SP2: device branch flag (0: X^2, 1: 2X - X^2)
     const int* d_active;    // SP2: device flag, 0 = skip (converged)
+    const uint32_t* order = nullptr;       // persistent launch: tile order (NULL = identity)
+    unsigned long long* queue = nullptr;   // persistent launch: zeroed queue counter (NULL = static grid)
 };
+hipError_t launch_lpt_order(const ProdDesc* d_desc, int nprod, int64_t total, int maxc, uint32_t* counts,
+                            uint32_t* hist, uint32_t* offs, uint32_t* order, unsigned long long* queue,
+                            hipStream_t s);
+hipError_t launch_clear_masks(const ProdDesc* d_desc, int nprod, hipStream_t s);
 hipError_t launch_leaf_typed(const ProdDesc* d_desc, const LeafPlan& plan, bool a_f64, hipStream_t s);
 
 // SP2 device state (sp2.hip): the branch/active flags read by the product

@@ -1,0 +1,82 @@
+"""Batched products (one cull pass, one leaf launch) against the oracle and
+against one-at-a-time products."""
+import numpy as np
+import pytest
+
+import oracle
+import spamm_inputs as si
+from gpu_util import elementwise_bound, to_dev
+
+pytestmark = pytest.mark.gpu
+sp = pytest.importorskip("paper_1011_3534_amd")
+
+SIZES = [64, 200, 512, 1000, 130, 700, 33, 300, 1024]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _torch_alloc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sp.use_torch_allocator(True)
+    yield
+
+
+def _batch(leaf, seed=0):
+    rng = np.random.default_rng(seed)
+    mats, taus = [], []
+    for i, n in enumerate(SIZES):
+        lam = float(rng.uniform(0.8, 0.97))
+        mats.append(si.exp_decay(n, lam, 300 + i, np.float32))
+        taus.append(float(10 ** rng.uniform(-7, -3)))
+    return mats, taus
+
+
+@pytest.mark.parametrize("leaf,prec,schedule", [(64, "f32", "lpt"), (32, "f16x3", "lpt"), (64, "bf16x3", "static")])
+def test_batched_matches_oracle(leaf, prec, schedule):
+    print(f"[case] batched leaf={leaf} prec={prec} schedule={schedule}", flush=True)
+    mats, taus = _batch(leaf)
+    hs = [sp.build(to_dev(a), leaf) for a in mats]
+    Cs, sts = sp.multiply_batched(hs, hs, taus, prec, stats=True, schedule=schedule)
+    for a, C, st, tau in zip(mats, Cs, sts, taus):
+        a64 = a.astype(np.float64)
+        S = oracle.tile_sqnorms(a64, leaf)
+        keys, _ = oracle.tasks_flat(S, S, tau)
+        assert np.array_equal(C.task_list(), keys)
+        T, kept = oracle.count_hierarchical(S, S, tau)
+        assert st["tasks"] == T and st["survivors"] == kept.tolist()
+        ref, _ = oracle.spamm_flat(a64, a64, leaf, tau)
+        out = C.to_dense().cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(out - ref) <= elementwise_bound(a64, a64, leaf, tau, prec))
+        for lv, r in enumerate(oracle.norm_pyramid(out, leaf)):
+            assert np.array_equal(C.norms(lv), r)
+
+
+def test_batched_equals_single_products_bitwise():
+    print("[case] batched == single", flush=True)
+    mats, taus = _batch(64, seed=1)
+    hs = [sp.build(to_dev(a), 64) for a in mats]
+    lpt = sp.multiply_batched(hs, hs, taus, "f16x3", schedule="lpt")
+    static = sp.multiply_batched(hs, hs, taus, "f16x3", schedule="static")
+    for h, tau, c1, c2 in zip(hs, taus, lpt, static):
+        single = sp.multiply(h, h, tau, "f16x3")
+        a = single.to_dense().cpu().numpy()
+        assert np.array_equal(c1.to_dense().cpu().numpy(), a)
+        assert np.array_equal(c2.to_dense().cpu().numpy(), a)
+        assert np.array_equal(c1.task_list(), single.task_list())
+
+
+def test_batched_output_reuse_and_errors():
+    print("[case] batched reuse/errors", flush=True)
+    mats, taus = _batch(64, seed=2)
+    hs = [sp.build(to_dev(a), 64) for a in mats]
+    Cs = sp.multiply_batched(hs, hs, taus, "f32")
+    first = [c.to_dense().cpu().numpy().copy() for c in Cs]
+    Cs2 = sp.multiply_batched(hs, hs, taus, "f32", outs=Cs)
+    assert all(a is b for a, b in zip(Cs, Cs2))
+    assert all(np.array_equal(c.to_dense().cpu().numpy(), f) for c, f in zip(Cs2, first))
+    h32 = sp.build(to_dev(mats[0]), 32)
+    with pytest.raises(sp.SpammError, match="EINVAL"):
+        sp.multiply_batched([hs[0], h32], [hs[0], h32], [1e-6, 1e-6])
+    with pytest.raises(sp.SpammError, match="EINVAL"):
+        sp.multiply_batched([hs[0]], [hs[0]], [1e-6], outs=[hs[0]])
