@@ -196,6 +196,41 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
                                     spamm_leaf_prec prec, const spamm_tune* tune, void* stream,
                                     spamm_matrix** C, spamm_stats* st);
 
+/* ------------------------------------------------------------------ autotuner */
+
+#define SPAMM_TUNE_MAX_LEAVES 3
+#define SPAMM_TUNE_MAX_TRIALS 8
+typedef struct {
+    int32_t trials;                              /* candidates timed (0 if from cache)     */
+    int32_t from_cache;                          /* 1: answer read from the cache file     */
+    int32_t leaf[SPAMM_TUNE_MAX_TRIALS];
+    int32_t schedule[SPAMM_TUNE_MAX_TRIALS];
+    int32_t qualified[SPAMM_TUNE_MAX_TRIALS];    /* met max_rel_err                        */
+    double ms[SPAMM_TUNE_MAX_TRIALS];            /* median of reps batched products        */
+    double max_rel_err[SPAMM_TUNE_MAX_TRIALS];   /* worst product of the batch             */
+    double best_ms;
+} spamm_tune_report;
+
+/* Autotuner of spamm_multiply_batched for the products C_m = A_m A_m of the
+ * caller's dense operands (dev_a[m]: n[m] x n[m] row-major, leading
+ * dimension n[m], element type dt).  For every leaf size in leaves[] (each
+ * 32, 64 or 128; at most 3) the operands are built and both schedules are
+ * timed (median of reps products, HIP events on `stream`).  Because the leaf
+ * size changes which block products are kept, a candidate qualifies only if
+ * every product stays within max_rel_err (relative Frobenius error) of the
+ * exact product, formed once with FP64 leaves at tau = 0.  The fastest
+ * qualifying candidate is returned in *best and, if cache_path is non-NULL,
+ * appended to that text file (one line per key: batch sizes, types, tau
+ * range, target, candidates); a later call with the same key returns the
+ * cached answer without trials.  report (optional) lists every trial.
+ * Synchronises.  Errors: EINVAL (bad arguments, no candidate qualifies),
+ * ENOMEM, EHIP. */
+spamm_status spamm_autotune_batched(int32_t count, const void* const* dev_a, const int64_t* n,
+                                    spamm_dtype dt, const double* tau, spamm_leaf_prec prec,
+                                    const int32_t* leaves, int32_t n_leaves, double max_rel_err,
+                                    int32_t reps, const char* cache_path, void* stream,
+                                    spamm_tune* best, spamm_tune_report* report);
+
 /* ------------------------------------------------------------------ SP2 / TC2 */
 
 /* Density matrix P = theta[mu I - H] with n_occ occupied states by TC2
@@ -241,7 +276,8 @@ spamm_status spamm_task_list(const spamm_matrix* C, uint64_t* host_keys, int64_t
                              int64_t* count, void* stream);
 
 /* ||X - Y||_F^2 and ||Y||_F^2 in FP64 over two handles of equal n (any
- * element types), e.g. X = SpAMM result, Y = exact product.  Synchronises. */
+ * element types and leaf sizes), e.g. X = SpAMM result, Y = exact product.
+ * Synchronises. */
 spamm_status spamm_diff_norms(const spamm_matrix* X, const spamm_matrix* Y, double* diff2,
                               double* ref2, void* stream);
 

@@ -50,6 +50,19 @@ class Tune(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int32), ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("leaf", ctypes.c_int32 * 8),
+                ("schedule", ctypes.c_int32 * 8), ("qualified", ctypes.c_int32 * 8), ("ms", ctypes.c_double * 8),
+                ("max_rel_err", ctypes.c_double * 8), ("best_ms", ctypes.c_double)]
+
+    def to_dict(self):
+        sched = {v: k for k, v in SCHEDULE.items()}
+        return {"from_cache": bool(self.from_cache), "best_ms": self.best_ms,
+                "trials": [{"leaf": self.leaf[i], "schedule": sched[self.schedule[i]], "ms": self.ms[i],
+                            "max_rel_err": self.max_rel_err[i], "qualified": bool(self.qualified[i])}
+                           for i in range(self.trials)]}
+
+
 class Timing(ctypes.Structure):
     _fields_ = [("ms_cull", ctypes.c_double), ("ms_leaf", ctypes.c_double), ("ms_norms", ctypes.c_double),
                 ("ms_total", ctypes.c_double)]
@@ -102,6 +115,9 @@ def lib():
         "spamm_multiply_batched": ([i32, PP, PP, ctypes.POINTER(dbl), i32, ctypes.POINTER(Tune), _VP, PP,
                                     ctypes.POINTER(Stats)], i32),
         "spamm_sp2": ([_VP, i64, dbl, i32, dbl, i32, _VP, PP, ctypes.POINTER(Sp2Log)], i32),
+        "spamm_autotune_batched": ([i32, PP, ctypes.POINTER(i64), i32, ctypes.POINTER(dbl), i32,
+                                    ctypes.POINTER(i32), i32, dbl, i32, ctypes.c_char_p, _VP,
+                                    ctypes.POINTER(Tune), ctypes.POINTER(TuneReport)], i32),
         "spamm_to_dense": ([_VP, _VP, i64, _VP], i32),
         "spamm_info": ([_VP, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
                         ctypes.POINTER(i32)], i32),
@@ -285,6 +301,29 @@ def multiply_batched(As, Bs, taus, prec: str = "f32", outs=None, stats: bool = F
         else:
             Cs.append(Matrix(ctypes.c_void_p(PC[m])))
     return (Cs, [s.to_dict() for s in st]) if stats else Cs
+
+
+def autotune_batched(dense, taus, prec: str = "f32", leaves=(32, 64, 128), max_rel_err: float = 1e-5,
+                     reps: int = 3, cache_path: str | None = None, stream=None):
+    """Pick leaf size and schedule for the products A_m A_m of dense CUDA tensors.
+
+    Returns (tune dict {"leaf", "schedule"}, report dict)."""
+    import torch
+    count = len(dense)
+    for a in dense:
+        if not (a.is_cuda and a.is_contiguous() and a.dim() == 2 and a.shape[0] == a.shape[1]):
+            raise ValueError("autotune_batched expects square contiguous CUDA tensors")
+    dt = 0 if dense[0].dtype == torch.float64 else 1
+    PA = (ctypes.c_void_p * count)(*[a.data_ptr() for a in dense])
+    N = (ctypes.c_int64 * count)(*[a.shape[0] for a in dense])
+    T = (ctypes.c_double * count)(*[float(t) for t in taus])
+    Lv = (ctypes.c_int32 * len(leaves))(*leaves)
+    best, rep = Tune(), TuneReport()
+    _check(lib().spamm_autotune_batched(count, PA, N, dt, T, LEAF[prec], Lv, len(leaves), float(max_rel_err),
+                                        int(reps), cache_path.encode() if cache_path else None, _stream(stream),
+                                        ctypes.byref(best), ctypes.byref(rep)))
+    sched = {v: k for k, v in SCHEDULE.items()}
+    return {"leaf": best.leaf, "schedule": sched[best.schedule]}, rep.to_dict()
 
 
 def sp2(H: Matrix, n_occ: int, tau: float, max_iter: int = 60, idem_tol: float = 1e-6,

@@ -443,7 +443,7 @@ spamm_status spamm_task_list(const spamm_matrix* C, uint64_t* host_keys, int64_t
 spamm_status spamm_diff_norms(const spamm_matrix* X, const spamm_matrix* Y, double* diff2, double* ref2,
                               void* stream) {
     if (!X || !Y || !diff2 || !ref2) return set_error(SPAMM_EINVAL, "null argument");
-    if (X->n != Y->n || X->b != Y->b) return set_error(SPAMM_EINVAL, "handles differ in n or leaf");
+    if (X->n != Y->n) return set_error(SPAMM_EINVAL, "handles differ in n");
     hipStream_t s = (hipStream_t)stream;
     double* d = nullptr;
     SPAMM_HIP(hipMalloc(&d, 2 * 1024 * sizeof(double)));

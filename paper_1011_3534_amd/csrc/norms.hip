@@ -205,6 +205,38 @@ __global__ void k_clear_u64(unsigned long long* p, int count, const int* active)
     if ((int)threadIdx.x < count) p[threadIdx.x] = 0ull;
 }
 
+// ||X - Y||^2 and ||Y||^2 for handles of equal n but different leaf sizes:
+// element (row, col) is looked up in each handle's own tile layout.
+template <typename TX, typename TY>
+__global__ void __launch_bounds__(256) k_diff_norms_any(const TX* __restrict__ x, int bx, int64_t nbx,
+                                                        const TY* __restrict__ y, int by, int64_t nby, int64_t n,
+                                                        double* __restrict__ out) {
+    double d2 = 0.0, r2 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n * n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = i / n, col = i % n;
+        const double xv = (double)x[(((row / bx) * nbx + col / bx) * bx + row % bx) * bx + col % bx];
+        const double yv = (double)y[(((row / by) * nby + col / by) * by + row % by) * by + col % by];
+        const double dv = xv - yv;
+        d2 = __fma_rn(dv, dv, d2);
+        r2 = __fma_rn(yv, yv, r2);
+    }
+    for (int d = kWave / 2; d >= 1; d /= 2) {
+        d2 += __shfl_down(d2, d, kWave);
+        r2 += __shfl_down(r2, d, kWave);
+    }
+    __shared__ double sd[4], sr[4];
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        sd[w] = d2;
+        sr[w] = r2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = (sd[0] + sd[1]) + (sd[2] + sd[3]);
+        out[2 * blockIdx.x + 1] = (sr[0] + sr[1]) + (sr[2] + sr[3]);
+    }
+}
+
 __global__ void k_fill_u64(uint64_t* p, int64_t count, uint64_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -282,6 +314,17 @@ hipError_t launch_diff_norms(const spamm_matrix* X, const spamm_matrix* Y, doubl
     const int64_t count = X->nb * X->nb * (int64_t)X->b * X->b;
     const unsigned blocks = 1024;
     const bool xf = X->dt == SPAMM_F32, yf = Y->dt == SPAMM_F32;
+    if (X->b != Y->b) {
+#define SPAMM_DIFF_ANY(TX, TY)                                                                                     \
+    hipLaunchKernelGGL((k_diff_norms_any<TX, TY>), dim3(blocks), dim3(256), 0, s, (const TX*)X->tiles, X->b, X->nb, \
+                       (const TY*)Y->tiles, Y->b, Y->nb, X->n, d_out)
+        if (xf && yf) SPAMM_DIFF_ANY(float, float);
+        else if (xf) SPAMM_DIFF_ANY(float, double);
+        else if (yf) SPAMM_DIFF_ANY(double, float);
+        else SPAMM_DIFF_ANY(double, double);
+#undef SPAMM_DIFF_ANY
+        return hipGetLastError();
+    }
     if (xf && yf)
         hipLaunchKernelGGL((k_diff_norms<float, float>), dim3(blocks), dim3(256), 0, s, (const float*)X->tiles,
                            (const float*)Y->tiles, count, d_out);

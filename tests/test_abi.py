@@ -69,3 +69,30 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(sp, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         sp.lib()
+
+
+def test_autotune_rejects_bad_arguments():
+    L = _lib_or_skip()
+    n = (ctypes.c_int64 * 1)(64)
+    tau = (ctypes.c_double * 1)(1e-6)
+    ptrs = (ctypes.c_void_p * 1)(0x1000)
+    best = sp.Tune()
+    bad_leaf = (ctypes.c_int32 * 1)(48)
+    good = (ctypes.c_int32 * 1)(64)
+    assert L.spamm_autotune_batched(0, ptrs, n, 1, tau, 1, good, 1, 1e-6, 1, None, None, ctypes.byref(best), None) == 1
+    assert L.spamm_autotune_batched(1, ptrs, n, 1, tau, 1, bad_leaf, 1, 1e-6, 1, None, None, ctypes.byref(best), None) == 1
+    assert L.spamm_autotune_batched(1, ptrs, n, 1, tau, 1, good, 4, 1e-6, 1, None, None, ctypes.byref(best), None) == 1
+    assert L.spamm_autotune_batched(1, ptrs, n, 1, tau, 1, good, 1, 0.0, 1, None, None, ctypes.byref(best), None) == 1
+    assert L.spamm_autotune_batched(1, ptrs, n, 1, tau, 1, good, 1, 1e-6, 0, None, None, ctypes.byref(best), None) == 1
+    assert L.spamm_autotune_batched(1, ptrs, n, 1, tau, 1, good, 1, 1e-6, 1, None, None, None, None) == 1
+
+
+def test_batched_and_sp2_reject_bad_arguments():
+    L = _lib_or_skip()
+    PP = ctypes.c_void_p * 1
+    tau = (ctypes.c_double * 1)(1e-6)
+    assert L.spamm_multiply_batched(0, PP(), PP(), tau, 1, None, None, PP(), None) == 1
+    assert L.spamm_multiply_batched(129, PP(), PP(), tau, 1, None, None, PP(), None) == 1
+    assert L.spamm_multiply_batched(1, None, None, tau, 1, None, None, PP(), None) == 1
+    h = ctypes.c_void_p()
+    assert L.spamm_sp2(None, 1, 1e-6, 10, 1e-6, 1, None, ctypes.byref(h), None) == 1
