@@ -281,6 +281,18 @@ spamm_status spamm_task_list(const spamm_matrix* C, uint64_t* host_keys, int64_t
 spamm_status spamm_diff_norms(const spamm_matrix* X, const spamm_matrix* Y, double* diff2,
                               double* ref2, void* stream);
 
+/* Seeded synthetic decay matrix on the device (input generation only; the
+ * multiply never calls it).  a_ij = round(f(|i-j|) * (lo + (hi - lo) u_ij))
+ * with u_ij = (h >> 11) 2^-53, h = SplitMix64(SplitMix64(seed) ^ (i << 32 | j))
+ * (counter (min(i,j), max(i,j)) when symmetric), f = host_table[0..n) in
+ * FP64; host_diag (optional, n entries) overrides the diagonal.  The same
+ * definition as the host-side generator, so both draw identical matrices.
+ * dev_out: n x n row-major, leading dimension ld, element type dt.
+ * Synchronises.  Errors: EINVAL, ENOMEM, EHIP. */
+spamm_status spamm_generate_decay(int64_t n, int64_t ld, spamm_dtype dt, const double* host_table,
+                                  uint64_t seed, double lo, double hi, int32_t symmetric,
+                                  const double* host_diag, void* dev_out, void* stream);
+
 /* Device allocation hook.  alloc(bytes, ctx) returns device memory or NULL;
  * dealloc(ptr, ctx) releases it.  NULL functions restore hipMalloc/hipFree.
  * Handles keep the pair they were allocated with. */

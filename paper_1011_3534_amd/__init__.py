@@ -125,6 +125,8 @@ def lib():
         "spamm_task_list": ([_VP, ctypes.POINTER(ctypes.c_uint64), i64, ctypes.POINTER(i64), _VP], i32),
         "spamm_diff_norms": ([_VP, _VP, ctypes.POINTER(dbl), ctypes.POINTER(dbl), _VP], i32),
         "spamm_set_allocator": ([_ALLOC_FN, _DEALLOC_FN, _VP], i32),
+        "spamm_generate_decay": ([i64, i64, i32, ctypes.POINTER(dbl), ctypes.c_uint64, dbl, dbl, i32,
+                                  ctypes.POINTER(dbl), _VP, _VP], i32),
         "spamm_free": ([_VP], None),
         "spamm_last_error": ([], ctypes.c_char_p),
     }
@@ -338,6 +340,27 @@ def sp2(H: Matrix, n_occ: int, tau: float, max_iter: int = 60, idem_tol: float =
     d = log.to_dict()
     d["status"] = STATUS[code]
     return Matrix(h), d
+
+
+def generate_decay(table, seed: int, lo: float, hi: float, symmetric: bool, dtype="f32", diag=None,
+                   stream=None):
+    """Seeded decay matrix drawn on the device: a_ij = f(|i-j|) (lo + (hi-lo) u_ij).
+
+    table: FP64 numpy array f(0..n-1) (e.g. spamm_inputs.exp_table); diag:
+    optional FP64 diagonal.  Returns an n x n CUDA tensor."""
+    import torch
+    table = np.ascontiguousarray(table, dtype=np.float64)
+    n = table.shape[0]
+    out = torch.empty((n, n), dtype=torch.float64 if dtype == "f64" else torch.float32, device="cuda")
+    dg = None
+    if diag is not None:
+        diag = np.ascontiguousarray(diag, dtype=np.float64)
+        dg = diag.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib().spamm_generate_decay(n, n, 0 if dtype == "f64" else 1,
+                                      table.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(seed), float(lo),
+                                      float(hi), int(bool(symmetric)), dg, ctypes.c_void_p(out.data_ptr()),
+                                      _stream(stream)))
+    return out
 
 
 def diff_norms(X: Matrix, Y: Matrix, stream=None):

@@ -78,19 +78,39 @@ def _decay_matrix(n: int, table: np.ndarray, seed: int, lo: float, hi: float,
     return out
 
 
+def exp_table(n: int, lam: float) -> np.ndarray:
+    """f(d) = lam^d, d = 0..n-1, FP64."""
+    return np.power(float(lam), np.arange(n, dtype=np.float64))
+
+
+def algebraic_table(n: int, p: float) -> np.ndarray:
+    """f(d) = 1 / (d^p + 1), d = 0..n-1, FP64."""
+    d = np.arange(n, dtype=np.float64)
+    return 1.0 / (np.power(d, float(p)) + 1.0)
+
+
 def exp_decay(n: int, lam: float, seed: int, dtype=np.float64, lo=-1.0, hi=1.0,
               symmetric=True) -> np.ndarray:
     """Exponential decay a_ij = lam^|i-j| * u_ij, u ~ U(lo, hi)."""
-    table = np.power(float(lam), np.arange(n, dtype=np.float64))
-    return _decay_matrix(n, table, seed, lo, hi, symmetric, dtype)
+    return _decay_matrix(n, exp_table(n, lam), seed, lo, hi, symmetric, dtype)
 
 
 def algebraic_decay(n: int, p: float, seed: int, dtype=np.float32, lo=0.5, hi=1.5,
                     symmetric=False) -> np.ndarray:
     """Algebraic decay a_ij = u_ij / (|i-j|^p + 1), u ~ U(lo, hi)."""
-    d = np.arange(n, dtype=np.float64)
-    table = 1.0 / (np.power(d, float(p)) + 1.0)
-    return _decay_matrix(n, table, seed, lo, hi, symmetric, dtype)
+    return _decay_matrix(n, algebraic_table(n, p), seed, lo, hi, symmetric, dtype)
+
+
+def sp2_diagonal(n: int, seed: int = 4, gap: float = 0.0, n_occ: int | None = None) -> np.ndarray:
+    """The N(0,1) diagonal of sp2_hamiltonian (PCG64 stream of seed), FP64."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    diag = rng.standard_normal(n)
+    if gap:
+        k = n // 2 if n_occ is None else n_occ
+        diag = diag.copy()
+        diag[:k] -= gap / 2.0
+        diag[k:] += gap / 2.0
+    return diag
 
 
 def sp2_hamiltonian(n: int, lam: float = 0.85, seed: int = 4, dtype=np.float32,
@@ -102,13 +122,7 @@ def sp2_hamiltonian(n: int, lam: float = 0.85, seed: int = 4, dtype=np.float32,
     diagonal entries are shifted by -gap/2 and the rest by +gap/2, which opens
     a spectral gap at the occupation boundary (used for small exact checks).
     """
-    rng = np.random.Generator(np.random.PCG64(seed))
-    diag = rng.standard_normal(n)
-    if gap:
-        k = n // 2 if n_occ is None else n_occ
-        diag = diag.copy()
-        diag[:k] -= gap / 2.0
-        diag[k:] += gap / 2.0
+    diag = sp2_diagonal(n, seed, gap, n_occ)
     table = -np.power(float(lam), np.arange(n, dtype=np.float64))
     h = np.empty((n, n), dtype=np.float64)
     rows = max(1, _ROW_CHUNK_ELEMS // max(n, 1))
@@ -135,6 +149,19 @@ def figure1_pair(n: int = 512, case: str = "A"):
             a = np.where(d > 0, 1.0 / d ** 3, 0.0)
         return a, a.copy()
     raise ValueError(case)
+
+
+def mlp_init(shapes, seed: int) -> np.ndarray:
+    """Initial weights of a ReLU network: He-normal W (std sqrt(2/in)), zero b.
+
+    shapes: list of (in, out) per layer; returns the flat FP64 vector
+    W1 (row-major, in x out), b1, W2, b2, ... drawn from PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for i, o in shapes:
+        parts.append(rng.standard_normal(i * o) * np.sqrt(2.0 / i))
+        parts.append(np.zeros(o))
+    return np.concatenate(parts)
 
 
 # --- workload recipes -------------------------------------------------------
