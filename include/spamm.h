@@ -253,6 +253,76 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
                        double idem_tol, spamm_leaf_prec prec, void* stream, spamm_matrix** P,
                        spamm_sp2_log* log);
 
+/* ------------------------------------------------------------------ learned tau */
+
+/* The paper sets tau by hand to match energy errors (section 3).  The
+ * selector maps the norm structure of A and B and a target relative error
+ * ||C~ - C||_F / ||C||_F to a threshold with a small network trained on
+ * (matrix, tau, error) samples that SpAMM itself produces.
+ *
+ * Features (SPAMM_TAU_NFEAT floats): for operand X in (A, B) and tier
+ * l = 0..7 counted from the leaves (tiers above the root are all zero), the
+ * fraction of the tier's nodes in bin k = #{j in 1..31 : S < S_root * 1e-j}
+ * (32 bins; 1e-j the correctly rounded decimal constants); then
+ * log10(target), log2(nb) / 10, log2(b) / 7.
+ * Network: 515 -> 128 -> 128 -> 128 -> 1, ReLU on hidden layers, FP32;
+ * parameters flat as W1 (in x out, row-major), b1, W2, b2, W3, b3, W4, b4.
+ * Output y = log10(tau / (||A||_F ||B||_F)).  Training minimises the mean
+ * squared error of y with Adam (beta 0.9 / 0.999, eps 1e-8) over fixed-order
+ * minibatches. */
+#define SPAMM_TAU_NFEAT 515
+#define SPAMM_TAU_HIDDEN 128
+#define SPAMM_TAU_NPARAM (515 * 128 + 128 + 2 * (128 * 128 + 128) + 128 + 1)
+
+typedef struct spamm_tau_model spamm_tau_model;  /* device weights + Adam moments */
+
+typedef struct {
+    double tau_pred;      /* the network's threshold                         */
+    double err_pred;      /* relative error of the product at tau_pred       */
+    double tau;           /* returned threshold (tau_pred unless fallback)   */
+    double rel_err;       /* relative error at tau                           */
+    int64_t tasks;        /* leaf products at tau                            */
+    int32_t evaluations;  /* SpAMM + error evaluations performed             */
+    int32_t fallback;     /* 1: tau_pred missed the target, bisection ran    */
+} spamm_tau_info;
+
+/* Model from SPAMM_TAU_NPARAM host floats (initial or trained weights). */
+spamm_status spamm_tau_model_create(const float* host_params, spamm_tau_model** out);
+/* Copy the current weights to host_params (SPAMM_TAU_NPARAM floats); syncs. */
+spamm_status spamm_tau_model_params(const spamm_tau_model* m, float* host_params);
+void spamm_tau_model_free(spamm_tau_model* m);
+
+/* Features of (A, B, target) into dev_out (SPAMM_TAU_NFEAT device floats). */
+spamm_status spamm_tau_features(const spamm_matrix* A, const spamm_matrix* B, double target,
+                                float* dev_out, void* stream);
+/* y for count feature rows dev_x (count x 515, device) into dev_y; syncs. */
+spamm_status spamm_tau_forward(const spamm_tau_model* m, const float* dev_x, int64_t count,
+                               float* dev_y, void* stream);
+/* Gradient of the mean squared error over the count rows (host_grad:
+ * SPAMM_TAU_NPARAM floats) and the loss; syncs.  For checking. */
+spamm_status spamm_tau_grad(const spamm_tau_model* m, const float* dev_x, const float* dev_y,
+                            int64_t count, float* host_grad, float* host_loss, void* stream);
+/* epochs passes of Adam over minibatches of `batch` consecutive rows;
+ * host_loss (optional, epochs floats) receives each epoch's mean loss. */
+spamm_status spamm_tau_train(spamm_tau_model* m, const float* dev_x, const float* dev_y,
+                             int64_t count, int32_t epochs, int32_t batch, float lr, void* stream,
+                             float* host_loss);
+/* tau = 10^y ||A||_F ||B||_F for the target relative error; syncs. */
+spamm_status spamm_tau_predict(const spamm_matrix* A, const spamm_matrix* B, double target,
+                               const spamm_tau_model* m, void* stream, double* tau_out);
+/* Threshold that meets the target, judged against the exact product (FP64
+ * leaves at tau = 0): the starting tau -- the network's prediction for half
+ * the target (m non-NULL), else 10 target ||A||_F ||B||_F -- is checked; if
+ * its error exceeds the target, tau steps down (a quarter decade at a time
+ * from a prediction, a decade at a time otherwise) until the target holds and
+ * is then bisected in log10(tau) to resolution_decades.  *C (in/out as for spamm_multiply) holds the product at
+ * the returned tau.  Syncs.  Errors: EINVAL, ENOMEM, EHIP, ENOCONV (no tau
+ * within 12 decades met the target). */
+spamm_status spamm_tau_select(const spamm_matrix* A, const spamm_matrix* B, double target,
+                              const spamm_tau_model* m, spamm_leaf_prec prec,
+                              double resolution_decades, void* stream, spamm_matrix** C,
+                              spamm_tau_info* info);
+
 /* ------------------------------------------------------------------ helpers */
 
 /* Dense row-major copy of M (n x n, leading dimension ldo, M's element type)

@@ -63,6 +63,19 @@ class TuneReport(ctypes.Structure):
                            for i in range(self.trials)]}
 
 
+TAU_NFEAT = 515
+TAU_NPARAM = 515 * 128 + 128 + 2 * (128 * 128 + 128) + 128 + 1
+
+
+class TauInfo(ctypes.Structure):
+    _fields_ = [("tau_pred", ctypes.c_double), ("err_pred", ctypes.c_double), ("tau", ctypes.c_double),
+                ("rel_err", ctypes.c_double), ("tasks", ctypes.c_int64), ("evaluations", ctypes.c_int32),
+                ("fallback", ctypes.c_int32)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Timing(ctypes.Structure):
     _fields_ = [("ms_cull", ctypes.c_double), ("ms_leaf", ctypes.c_double), ("ms_norms", ctypes.c_double),
                 ("ms_total", ctypes.c_double)]
@@ -125,6 +138,17 @@ def lib():
         "spamm_task_list": ([_VP, ctypes.POINTER(ctypes.c_uint64), i64, ctypes.POINTER(i64), _VP], i32),
         "spamm_diff_norms": ([_VP, _VP, ctypes.POINTER(dbl), ctypes.POINTER(dbl), _VP], i32),
         "spamm_set_allocator": ([_ALLOC_FN, _DEALLOC_FN, _VP], i32),
+        "spamm_tau_model_create": ([ctypes.POINTER(ctypes.c_float), PP], i32),
+        "spamm_tau_model_params": ([_VP, ctypes.POINTER(ctypes.c_float)], i32),
+        "spamm_tau_model_free": ([_VP], None),
+        "spamm_tau_features": ([_VP, _VP, dbl, _VP, _VP], i32),
+        "spamm_tau_forward": ([_VP, _VP, i64, _VP, _VP], i32),
+        "spamm_tau_grad": ([_VP, _VP, _VP, i64, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                            _VP], i32),
+        "spamm_tau_train": ([_VP, _VP, _VP, i64, i32, i32, ctypes.c_float, _VP, ctypes.POINTER(ctypes.c_float)],
+                            i32),
+        "spamm_tau_predict": ([_VP, _VP, dbl, _VP, _VP, ctypes.POINTER(dbl)], i32),
+        "spamm_tau_select": ([_VP, _VP, dbl, _VP, i32, dbl, _VP, PP, ctypes.POINTER(TauInfo)], i32),
         "spamm_generate_decay": ([i64, i64, i32, ctypes.POINTER(dbl), ctypes.c_uint64, dbl, dbl, i32,
                                   ctypes.POINTER(dbl), _VP, _VP], i32),
         "spamm_free": ([_VP], None),
@@ -340,6 +364,89 @@ def sp2(H: Matrix, n_occ: int, tau: float, max_iter: int = 60, idem_tol: float =
     d = log.to_dict()
     d["status"] = STATUS[code]
     return Matrix(h), d
+
+
+class TauModel:
+    """Device-resident tau network (weights + Adam moments)."""
+
+    def __init__(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != TAU_NPARAM:
+            raise ValueError(f"expected {TAU_NPARAM} parameters, got {p.size}")
+        h = ctypes.c_void_p()
+        _check(lib().spamm_tau_model_create(p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def params(self) -> np.ndarray:
+        out = np.empty(TAU_NPARAM, dtype=np.float32)
+        _check(lib().spamm_tau_model_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def free(self):
+        if self._h:
+            lib().spamm_tau_model_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def forward(self, X, stream=None):
+        import torch
+        X = X.contiguous()
+        y = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
+        _check(lib().spamm_tau_forward(self._h, ctypes.c_void_p(X.data_ptr()), X.shape[0],
+                                       ctypes.c_void_p(y.data_ptr()), _stream(stream)))
+        return y
+
+    def grad(self, X, y, stream=None):
+        g = np.empty(TAU_NPARAM, dtype=np.float32)
+        loss = ctypes.c_float()
+        X, y = X.contiguous(), y.contiguous()
+        _check(lib().spamm_tau_grad(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                    X.shape[0], g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                    ctypes.byref(loss), _stream(stream)))
+        return g, loss.value
+
+    def train(self, X, y, epochs: int, batch: int, lr: float, stream=None):
+        X, y = X.contiguous(), y.contiguous()
+        losses = np.zeros(epochs, dtype=np.float32)
+        _check(lib().spamm_tau_train(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                     X.shape[0], int(epochs), int(batch), float(lr), _stream(stream),
+                                     losses.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return losses
+
+
+def tau_features(A: Matrix, B: Matrix, target: float, stream=None):
+    import torch
+    out = torch.empty(TAU_NFEAT, dtype=torch.float32, device="cuda")
+    _check(lib().spamm_tau_features(A.handle, B.handle, float(target), ctypes.c_void_p(out.data_ptr()),
+                                    _stream(stream)))
+    return out
+
+
+def tau_predict(A: Matrix, B: Matrix, target: float, model: TauModel, stream=None) -> float:
+    t = ctypes.c_double()
+    _check(lib().spamm_tau_predict(A.handle, B.handle, float(target), model.handle, _stream(stream),
+                                   ctypes.byref(t)))
+    return t.value
+
+
+def tau_select(A: Matrix, B: Matrix, target: float, model: TauModel | None = None, prec: str = "f32",
+               resolution_decades: float = 0.05, out: Matrix | None = None, stream=None):
+    """(C at the selected tau, info dict); judged against the exact product."""
+    h = ctypes.c_void_p(out.handle.value if out is not None else None)
+    info = TauInfo()
+    _check(lib().spamm_tau_select(A.handle, B.handle, float(target), model.handle if model else None, LEAF[prec],
+                                  float(resolution_decades), _stream(stream), ctypes.byref(h), ctypes.byref(info)))
+    C = out if out is not None else Matrix(h)
+    return C, info.to_dict()
 
 
 def generate_decay(table, seed: int, lo: float, hi: float, symmetric: bool, dtype="f32", diag=None,

@@ -151,6 +151,34 @@ def figure1_pair(n: int = 512, case: str = "A"):
     raise ValueError(case)
 
 
+def tau_training_params(count: int, seed: int = 10000, n_lo: int = 512, n_hi: int = 8192,
+                        leaves=(32, 64, 128), taus_per_matrix: int = 20, log_tau_rel=(-13.0, -3.0)):
+    """Recipes of the matrices of a tau training set, drawn from PCG64(seed).
+
+    Each entry: family "exp" (lam ~ U(0.8, 0.97), u ~ U(-1, 1), symmetric, as the
+    exponential workloads) or "alg" (p ~ U(1.25, 3), u ~ U(0.5, 1.5), as the
+    algebraic ones), n ~ U{n_lo..n_hi step 64}, leaf from `leaves`, u-seed
+    seed + i, and taus_per_matrix values of log10(tau / ||A||_F^2) ~ U(log_tau_rel)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(count):
+        fam = "exp" if rng.integers(2) == 0 else "alg"
+        n = int(rng.integers(n_lo // 64, n_hi // 64 + 1)) * 64
+        leaf = int(leaves[int(rng.integers(len(leaves)))])
+        if fam == "exp":
+            par, lo, hi, sym = float(rng.uniform(0.8, 0.97)), -1.0, 1.0, True
+        else:
+            par, lo, hi, sym = float(rng.uniform(1.25, 3.0)), 0.5, 1.5, False
+        taus = rng.uniform(log_tau_rel[0], log_tau_rel[1], taus_per_matrix)
+        out.append({"family": fam, "n": n, "leaf": leaf, "param": par, "lo": lo, "hi": hi, "symmetric": sym,
+                    "seed": seed + i, "log_tau_rel": taus})
+    return out
+
+
+def recipe_table(r) -> np.ndarray:
+    return exp_table(r["n"], r["param"]) if r["family"] == "exp" else algebraic_table(r["n"], r["param"])
+
+
 def mlp_init(shapes, seed: int) -> np.ndarray:
     """Initial weights of a ReLU network: He-normal W (std sqrt(2/in)), zero b.
 
