@@ -107,11 +107,22 @@ def main():
                     help="use this tau for every precision instead of the sweep (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 256 MiB device copy first (reference for HBM byte counters)")
+    ap.add_argument("--workload", default="algebraic8192",
+                    choices=["algebraic8192", "exp1024", "batched64", "sp2", "learned-tau"],
+                    help="algebraic8192 (default): the headline line; the others measure the remaining "
+                         "hot-path rows and print their own JSON line")
+    ap.add_argument("--sp2-n", type=int, default=16384)
+    ap.add_argument("--learn-n", type=int, default=32768)
+    ap.add_argument("--train-matrices", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "
               f"multi-GPU path.", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "algebraic8192":
+        {"exp1024": run_exp1024, "batched64": run_batched64, "sp2": run_sp2,
+         "learned-tau": run_learned_tau}[args.workload](args)
+        return
 
     import torch
 
@@ -225,6 +236,192 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(a.astype(np.float64), b, r["tau"], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+# --------------------------------------------------------------------------- other hot-path rows
+
+def _setup():
+    import torch
+
+    import paper_1011_3534_amd as sp
+    torch.cuda.set_device(0)
+    sp.use_torch_allocator(True)
+    return torch, sp
+
+
+def _time(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def run_exp1024(args):
+    """Exponential decay 0.9^|i-j| u, u ~ U(-1,1) symmetric, n = 1024, leaf 32, FP64, C = A A,
+    tau = 1e-6 and tau = 0 (checked against torch's FP64 dense product)."""
+    torch, sp = _setup()
+    import spamm_inputs as si
+    a = si.exp_decay_workload()
+    A_d = torch.from_numpy(a).cuda()
+    A = sp.build(A_d, 32)
+    dense = torch.matmul(A_d, A_d)
+    Dh = sp.build(dense, 32)
+    out = {"metric": METRIC, "workload": "exp1024", "config": {
+        "workload": "exponential decay 0.9^|i-j| u, u~U(-1,1) symmetric, n=1024, leaf 32, FP64, C=A*A"}}
+    for tau in (1e-6, 0.0):
+        C, st = sp.multiply(A, A, tau, "f64", stats=True)
+        ms = _time(torch, lambda: (sp.build(A_d, 32, out=A), sp.multiply(A, A, tau, "f64", out=C)),
+                   max(args.steps, 50), args.warmup)
+        phases = [sp.multiply_timed(A, A, tau, "f64", out=C)[1] for _ in range(20)]
+        leaf_ms = float(np.mean([p["ms_leaf"] for p in phases]))
+        out[f"tau={tau:g}"] = {"tasks": st["tasks"], "step_ms": ms, "leaf_ms": leaf_ms,
+                               "leaf_tflops": st["flops"] / leaf_ms / 1e9,
+                               "rel_err_vs_dense_fp64": sp.rel_err(C, Dh)}
+    dense_ms = _time(torch, lambda: torch.matmul(A_d, A_d), 50, 3)
+    out["dense_fp64_gemm_ms"] = dense_ms
+    print(json.dumps(out), flush=True)
+
+
+def run_batched64(args):
+    """64 exponential-decay matrices, lam ~ U(0.8, 0.97), n ~ U{512..8192 step 64}, FP32, tau = 1e-6,
+    one batched product with leaf size and schedule chosen by the autotuner."""
+    torch, sp = _setup()
+    import spamm_inputs as si
+    params = si.batch_params()
+    log(f"generating 64 matrices on the device (sum n^2 = {sum(n * n for n, _, _ in params):.3e})")
+    dense = [sp.generate_decay(si.exp_table(n, lam), useed, -1.0, 1.0, True) for n, lam, useed in params]
+    taus = [1e-6] * len(dense)
+    t0 = time.perf_counter()
+    tune, rep = sp.autotune_batched(dense, taus, "f32", leaves=(32, 64, 128), max_rel_err=1e-5, reps=3)
+    tune_s = time.perf_counter() - t0
+    log(f"autotune: {tune} in {tune_s:.1f} s")
+    b = tune["leaf"]
+    hs = [sp.build(d, b) for d in dense]
+    Cs, sts = sp.multiply_batched(hs, hs, taus, "f32", stats=True, schedule=tune["schedule"])
+    T = sum(s["tasks"] for s in sts)
+    flops = 2.0 * b ** 3 * T
+
+    def step():
+        for d, h in zip(dense, hs):
+            sp.build(d, b, out=h)
+        sp.multiply_batched(hs, hs, taus, "f32", outs=Cs, schedule=tune["schedule"])
+
+    step_ms = _time(torch, step, args.steps, args.warmup)
+    mult_ms = _time(torch, lambda: sp.multiply_batched(hs, hs, taus, "f32", outs=Cs, schedule=tune["schedule"]),
+                    args.steps, args.warmup)
+    other = "static" if tune["schedule"] == "lpt" else "lpt"
+    other_ms = _time(torch, lambda: sp.multiply_batched(hs, hs, taus, "f32", outs=Cs, schedule=other),
+                     args.steps, args.warmup)
+    dense_ms = _time(torch, lambda: [torch.matmul(d, d) for d in dense], 3, 1)
+    dense_flops = sum(2.0 * d.shape[0] ** 3 for d in dense)
+    print(json.dumps({"metric": METRIC, "workload": "batched64", "tune": tune, "tune_report": rep,
+                      "tune_seconds": tune_s, "tasks": T, "leaf_flops": flops, "step_ms": step_ms,
+                      "multiply_ms": mult_ms, f"multiply_ms_{other}": other_ms,
+                      "step_tflops": flops / step_ms / 1e9, "dense_fp32_gemm_ms": dense_ms,
+                      "dense_flops": dense_flops, "speedup_vs_dense_fp32": dense_ms / step_ms,
+                      "config": {"workload": "64 exp-decay matrices lam~U(0.8,0.97), n~U{512..8192 step 64}, "
+                                             "FP32, tau=1e-6, autotuned leaf/schedule, one batched product"}}),
+          flush=True)
+
+
+def run_sp2(args):
+    """SP2 on H: h_ii ~ N(0,1), h_ij = -0.85^|i-j|, n = 16384, n_occ = n/2, leaf 64, up to 60
+    steps in one hipGraph; tau sweep with the energy error against the tau = 0 run."""
+    torch, sp = _setup()
+    import spamm_inputs as si
+    n = args.sp2_n
+    Hd = sp.generate_decay(-si.exp_table(n, 0.85), 0, 1.0, 1.0, False, "f32", si.sp2_diagonal(n, 4))
+    H = sp.build(Hd, 64)
+    res = {}
+    for tau in (0.0, 1e-4, 1e-5, 1e-6, 1e-7):
+        for prec in ("f32", "f16x3"):
+            if tau == 0.0 and prec != "f32":
+                continue
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            P, lg = sp.sp2(H, n // 2, tau, max_iter=60, idem_tol=1e-5, prec=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            res[f"{prec}@{tau:g}"] = {"ms": ms, "iterations": lg["iterations"], "status": lg["status"],
+                                      "converged": lg["converged"], "stagnated": lg["stagnated"],
+                                      "final_trace": lg["final_trace"], "energy": lg["energy"],
+                                      "last_idem": lg["idem"][-1] if lg["idem"] else None,
+                                      "tasks_total": sum(lg["tasks"]),
+                                      "leaf_flops": 2.0 * 64 ** 3 * sum(lg["tasks"])}
+            log(f"sp2 {prec} tau={tau:g}: {ms:.1f} ms, {lg['iterations']} steps, E={lg['energy']:.10g}")
+            del P
+    e0 = res["f32@0"]["energy"]
+    for k, v in res.items():
+        v["dE_rel"] = abs(v["energy"] - e0) / abs(e0)
+    print(json.dumps({"metric": METRIC, "workload": "sp2", "n": n, "n_occ": n // 2, "results": res,
+                      "config": {"workload": f"SP2, h_ii~N(0,1), h_ij=-0.85^|i-j|, n={n}, n_occ=n/2, leaf 64, "
+                                             f"max 60 steps in one hipGraph"}}), flush=True)
+
+
+def run_learned_tau(args):
+    """Learned tau: train on SpAMM-generated samples (exponential / algebraic families, n <= 8192),
+    then select tau at n = 32768, algebraic decay p = 1.5, FP32 leaves, target 1e-6."""
+    torch, sp = _setup()
+    import spamm_inputs as si
+    from paper_1011_3534_amd import tau_data
+    recipes = si.tau_training_params(args.train_matrices, seed=10000, taus_per_matrix=20)
+    t0 = time.perf_counter()
+    X, y, meta = tau_data.training_set(recipes, log=log)
+    data_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    model, losses = tau_data.train_model(X, y, epochs=300, batch=256, lr=1e-3)
+    train_s = time.perf_counter() - t0
+    log(f"{X.shape[0]} samples in {data_s:.1f} s; training {train_s:.1f} s, loss {losses[0]:.3f} -> {losses[-1]:.4f}")
+    n = args.learn_n
+    Ad = sp.generate_decay(si.algebraic_table(n, 1.5), 5, 0.5, 1.5, False)
+    A = sp.build(Ad, 64)
+    target = args.target
+    out = {"metric": METRIC, "workload": "learned-tau", "samples": int(X.shape[0]), "data_seconds": data_s,
+           "train_seconds": train_s, "loss_first": float(losses[0]), "loss_last": float(losses[-1]), "n": n}
+    # the leaf-precision floor at this size (tau = 0): a target below it cannot be met
+    E = sp.multiply(A, A, 0.0, "f64")
+    for p in ("f32", "f16x3"):
+        out[f"floor_{p}"] = sp.rel_err(sp.multiply(A, A, 0.0, p), E)
+    del E
+    log(f"floors: f32 {out['floor_f32']:.2e}, f16x3 {out['floor_f16x3']:.2e}")
+    for name, mdl in (("learned", model), ("bisection", None)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            C, info = sp.tau_select(A, A, target, mdl, "f32", 0.05)
+        except sp.SpammError as exc:
+            out[name] = {"error": str(exc)}
+            log(f"{name}: {exc}")
+            continue
+        torch.cuda.synchronize()
+        info["seconds"] = time.perf_counter() - t0
+        info["step_ms"] = _time(torch, lambda: sp.multiply(A, A, info["tau"], "f32", out=C), 5, 1)
+        out[name] = info
+        log(f"{name}: tau={info['tau']:.3e} err={info['rel_err']:.2e} evals={info['evaluations']} "
+            f"T={info['tasks']} {info['seconds']:.1f} s")
+        del C
+    best = {}
+    for i, _, _, _, lt, err in meta:
+        if err <= target:
+            best[i] = max(best.get(i, -99.0), lt)
+    const_lt = min(best.values()) if best else None
+    if const_lt is not None:
+        sroot = float(A.norms(A.levels)[0, 0])
+        Cc, st = sp.multiply(A, A, 10 ** const_lt * sroot, "f32", stats=True)
+        E = sp.multiply(A, A, 0.0, "f64")
+        out["constant_rule"] = {"log10_tau_rel": const_lt, "tasks": st["tasks"], "rel_err": sp.rel_err(Cc, E)}
+        del E, Cc
+    out["dense_fp32_gemm_ms"] = _time(torch, lambda: torch.matmul(Ad, Ad), 2, 1)
+    out["config"] = {"workload": f"algebraic decay u/(|i-j|^1.5+1), n={n}, leaf 64, FP32 leaves, target {target:g}"}
     print(json.dumps(out), flush=True)
 
 

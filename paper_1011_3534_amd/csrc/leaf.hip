@@ -348,15 +348,22 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
                 stage_load<B, P, TA>(st, Ab + ((int64_t)I * nb + knext) * TS, Bb + ((int64_t)knext * nb + J) * TS,
                                      chn * KC, tid);
             }
-            if constexpr (isf16(P)) {
+            if constexpr (P != kF64) {
+                // each leaf product is summed in a fresh FP32 accumulator and added
+                // to the tile sum once (two-level summation: the rounding error no
+                // longer grows with the number of kept products of the tile)
                 chunk_mma<B, P, Acc>(smem + buf * G::BUF_BYTES, part, lane, wr, wc);
-                if (ch == NCH - 1) {  // task done: undo its power-of-two scales
+                if (ch == NCH - 1) {
 #pragma unroll
                     for (int i = 0; i < R; ++i)
 #pragma unroll
                         for (int j = 0; j < R; ++j) {
+                            if constexpr (isf16(P)) {  // undo the task's power-of-two scales
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) acc[i][j][q] += ldexpf(part[i][j][q], unscale);
+                                for (int q = 0; q < 4; ++q) acc[i][j][q] += ldexpf(part[i][j][q], unscale);
+                            } else {
+                                acc[i][j] += part[i][j];
+                            }
                             part[i][j] = Acc{0, 0, 0, 0};
                         }
                 }
