@@ -1,9 +1,12 @@
 // Dense leaf products of SpAMM (the finest tier of Eq. 4) on gfx950 MFMA.
 //
-// One 256-thread workgroup owns one C tile (I, J): it walks the kept K of the
-// tile in ascending order straight from the leaf bitmask written by the cull,
-// streams A_IK and B_KJ through double-buffered LDS in k-chunks and
-// accumulates with 16x16 MFMA blocks; the four waves split the tile 2 x 2.
+// One 256-thread workgroup owns one C tile (I, J): it lists the kept K of the
+// tile in ascending order from the leaf bitmask written by the cull, streams
+// A_IK and B_KJ through double-buffered LDS in k-chunks, with the global loads
+// of two chunks in flight, and accumulates with 16x16 MFMA blocks; the four
+// waves split the tile 2 x 2.  Operand pointers are cast to the global address
+// space so the loads are global (not flat) loads: flat loads would also count
+// against the LDS wait counter and serialise the MFMA chunk with the prefetch.
 // Tiles are handed out XCD by XCD (block x runs on XCD x mod 8), each XCD
 // taking a contiguous run of tiles so that neighbouring tiles, which share
 // operand panels, meet in the same L2.
@@ -18,6 +21,8 @@
 
 namespace spamm {
 namespace {
+
+#define GLOBAL __attribute__((address_space(1)))
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -50,6 +55,14 @@ struct Geo {
     static constexpr int SC = B + (P == kF64 ? 2 : 4);                            // C staging stride
     static constexpr int C_BYTES = B * SC * (int)sizeof(CT);
     static constexpr int SMEM = (2 * BUF_BYTES > C_BYTES) ? 2 * BUF_BYTES : C_BYTES;
+};
+
+// Kept K of one segment of a tile's mask (four words), with the FP16 scale
+// exponents of A_IK and B_KJ.
+struct KList {
+    int k[256];
+    int16_t sa[256];
+    int16_t sb[256];
 };
 
 __device__ inline uint16_t bf16_bits(float x) {
@@ -97,8 +110,10 @@ struct Stage {
 };
 
 template <int B, int P, typename TA>
-__device__ inline void stage_load(Stage<B, P, TA>& st, const TA* __restrict__ At, const TA* __restrict__ Bt, int kc,
-                                  int tid) {
+__device__ inline void stage_load(Stage<B, P, TA>& st, const GLOBAL TA* __restrict__ At,
+                                  const GLOBAL TA* __restrict__ Bt, int tid) {
+    // At: A tile + chunk column offset (row stride B); Bt: B tile + chunk row
+    // offset (row stride B)
     using S = Stage<B, P, TA>;
     constexpr int KC = S::KC, VA = S::VA;
 #pragma unroll
@@ -106,7 +121,7 @@ __device__ inline void stage_load(Stage<B, P, TA>& st, const TA* __restrict__ At
         const int unit = tid + u * 256;
         if (S::PARTIAL && unit >= S::NU) break;
         const int r = unit / (KC / VA), k = (unit % (KC / VA)) * VA;
-        const TA* src = At + (int64_t)r * B + kc + k;
+        const GLOBAL TA* src = At + r * B + k;
 #pragma unroll
         for (int j = 0; j < VA; ++j) st.a[u][j] = src[j];
     }
@@ -115,18 +130,18 @@ __device__ inline void stage_load(Stage<B, P, TA>& st, const TA* __restrict__ At
 #pragma unroll
         for (int u = 0; u < S::UB; ++u) {
             const int unit = tid + u * 256;
-        if (S::PARTIAL && unit >= S::NU) break;
+            if (S::PARTIAL && unit >= S::NU) break;
             const int c = unit % B, k = (unit / B) * 8;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) st.b[u][j] = Bt[(int64_t)(kc + k + j) * B + c];
+            for (int j = 0; j < 8; ++j) st.b[u][j] = Bt[(k + j) * B + c];
         }
     } else {
 #pragma unroll
         for (int u = 0; u < S::UB; ++u) {
             const int unit = tid + u * 256;
-        if (S::PARTIAL && unit >= S::NU) break;
+            if (S::PARTIAL && unit >= S::NU) break;
             const int k = unit / (B / VA), c = (unit % (B / VA)) * VA;
-            const TA* src = Bt + (int64_t)(kc + k) * B + c;
+            const GLOBAL TA* src = Bt + k * B + c;
 #pragma unroll
             for (int j = 0; j < VA; ++j) st.b[u][j] = src[j];
         }
@@ -258,22 +273,6 @@ __device__ inline void chunk_mma(const char* buf, Acc (&acc)[Geo<B, P>::R][Geo<B
     }
 }
 
-// Iterator over the kept K of one C tile (ascending), from its bitmask.
-struct KIter {
-    const uint64_t* w;
-    int W, wi;
-    uint64_t bits;
-    __device__ int next() {
-        while (bits == 0) {
-            if (++wi >= W) return -1;
-            bits = w[wi];
-        }
-        const int k = __ffsll((unsigned long long)bits) - 1;
-        bits &= bits - 1;
-        return wi * 64 + k;
-    }
-};
-
 __device__ inline int find_product(const ProdDesc* desc, int nprod, int64_t t) {
     int lo = 0, hi = nprod - 1;
     while (lo < hi) {
@@ -284,10 +283,30 @@ __device__ inline int find_product(const ProdDesc* desc, int nprod, int64_t t) {
 }
 
 
-// One C tile (global index t) from its kept K to its stored values and norm.
+// Schedule position p of an nb x nb tile grid -> tile (I, J), walking 8-row
+// panels top to bottom and, inside a panel, 8-column blocks left to right
+// (row-major inside a block; edge panels and blocks are narrower).  A bijection
+// on [0, nb^2): tiles processed together form 2-D neighbourhoods that share
+// both A row panels and B column panels in L2.
+__device__ inline void block_order(int64_t p, int nb, int& I, int& J) {
+    constexpr int G = 8;
+    const int64_t panel = p / ((int64_t)G * nb);
+    const int64_t rem = p - panel * G * nb;
+    const int h = nb - (int)panel * G < G ? nb - (int)panel * G : G;
+    const int64_t bj = rem / ((int64_t)h * G);
+    const int64_t rem2 = rem - bj * h * G;
+    const int w = nb - (int)bj * G < G ? nb - (int)bj * G : G;
+    I = (int)(panel * G + rem2 / w);
+    J = (int)(bj * G + rem2 % w);
+}
+
+// One C tile from its kept K to its stored values and norm.  t is a global
+// schedule position (blocked = true: panel/block order inside each product)
+// or a global tile index (blocked = false: row-major).
 template <int B, int P, typename TA, typename TC, bool SP2>
 __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int nprod, int64_t t, char* smem,
-                                          double (*red)[4], const int* __restrict__ branch) {
+                                          KList* kl, double (*red)[4], const int* __restrict__ branch,
+                                          bool blocked) {
     using G = Geo<B, P>;
     using CT = typename G::CT;
     using Acc = typename std::conditional<P == kF64, f64x4, f32x4>::type;
@@ -295,11 +314,17 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
     const int m = nprod > 1 ? find_product(desc, nprod, t) : 0;
     const ProdDesc& d = desc[m];
     const int nb = d.nb;
-    const int64_t local = t - d.tile_base;
-    const int I = (int)(local / nb), J = (int)(local % nb);
+    int I, J;
+    if (blocked) {
+        block_order(t - d.tile_base, nb, I, J);
+    } else {
+        I = (int)((t - d.tile_base) / nb);
+        J = (int)((t - d.tile_base) % nb);
+    }
+    const int64_t local = (int64_t)I * nb + J;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
-    const TA* Ab = reinterpret_cast<const TA*>(d.A);
-    const TA* Bb = reinterpret_cast<const TA*>(d.B);
+    const GLOBAL TA* Ag = (const GLOBAL TA*)d.A;
+    const GLOBAL TA* Bg = (const GLOBAL TA*)d.B;
     constexpr int64_t TS = (int64_t)B * B;
 
     Acc acc[R][R], part[R][R];
@@ -311,56 +336,67 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             part[i][j] = Acc{0, 0, 0, 0};
         }
 
-    KIter it{d.mask + local * d.W, d.W, 0, d.mask[local * d.W]};
-    int kcur = it.next();
-    if (kcur >= 0) {
-        if (tid == 0) atomicAdd(d.nonempty, 1ull);
-        Stage<B, P, TA> st;
-        // fp16: A_IK is scaled by 2^sa, B_KJ by 2^sb, their product undone by 2^unscale
-        int sa = 0, sb = 0, unscale = 0;
-        auto scales = [&](int k, int& a_s, int& b_s, int& un) {
-            if constexpr (isf16(P)) {
-                int ea = d.eA[(int64_t)I * nb + k], eb = d.eB[(int64_t)k * nb + J];
-                ea = ea == -128 ? 0 : ea;
-                eb = eb == -128 ? 0 : eb;
-                a_s = kF16Bias - ea;
-                b_s = kF16Bias - eb;
-                un = -(a_s + b_s);
+    // The kept K of this tile, a segment of four mask words (256 K) at a
+    // time, become a list in LDS (with the FP16 scales of each product), so
+    // that the pipelined loop issues no global load besides operand chunks.
+    const uint64_t* mrow = d.mask + local * d.W;
+    bool counted = false;
+    for (int w0 = 0; w0 < d.W; w0 += 4) {
+        uint64_t wd[4];
+        int pre[4], nk = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            wd[j] = (w0 + j < d.W) ? mrow[w0 + j] : 0ull;
+            pre[j] = nk;
+            nk += __popcll(wd[j]);
+        }
+        if (nk == 0) continue;
+        if (!counted) {
+            counted = true;
+            if (tid == 0) atomicAdd(d.nonempty, 1ull);
+        }
+        {
+            // wave w lists the K of word w0 + w in ascending order
+            const uint64_t mine = w == 0 ? wd[0] : w == 1 ? wd[1] : w == 2 ? wd[2] : wd[3];
+            const int base = w == 0 ? pre[0] : w == 1 ? pre[1] : w == 2 ? pre[2] : pre[3];
+            if ((mine >> lane) & 1ull) {
+                const int pos = base + __popcll(mine & ((1ull << lane) - 1ull));
+                const int k = (w0 + w) * 64 + lane;
+                kl->k[pos] = k;
+                if constexpr (isf16(P)) {
+                    // A_IK is scaled by 2^sa, B_KJ by 2^sb (exact powers of two)
+                    int ea = d.eA[(int64_t)I * nb + k], eb = d.eB[(int64_t)k * nb + J];
+                    ea = ea == -128 ? 0 : ea;
+                    eb = eb == -128 ? 0 : eb;
+                    kl->sa[pos] = (int16_t)(kF16Bias - ea);
+                    kl->sb[pos] = (int16_t)(kF16Bias - eb);
+                }
             }
-        };
-        scales(kcur, sa, sb, unscale);
-        int ch = 0;
-        stage_load<B, P, TA>(st, Ab + ((int64_t)I * nb + kcur) * TS, Bb + ((int64_t)kcur * nb + J) * TS, 0, tid);
-        stage_store<B, P, TA>(st, smem, tid, sa, sb);
+        }
         __syncthreads();
-        int buf = 0;
-        while (true) {
-            // next (task, chunk)
-            int knext = kcur, chn = ch + 1;
-            if (chn == NCH) {
-                knext = it.next();
-                chn = 0;
-            }
-            const bool more = knext >= 0;
-            int nsa = sa, nsb = sb, nun = unscale;
-            if (more) {
-                if (knext != kcur) scales(knext, nsa, nsb, nun);
-                stage_load<B, P, TA>(st, Ab + ((int64_t)I * nb + knext) * TS, Bb + ((int64_t)knext * nb + J) * TS,
-                                     chn * KC, tid);
-            }
+
+        // step t = (list entry t / NCH, k-chunk t % NCH)
+        const int T = nk * NCH;
+        auto a_src = [&](int t) { return Ag + ((int64_t)I * nb + kl->k[t / NCH]) * TS + (t % NCH) * KC; };
+        auto b_src = [&](int t) { return Bg + ((int64_t)kl->k[t / NCH] * nb + J) * TS + (int64_t)(t % NCH) * KC * B; };
+        auto sa_of = [&](int t) { return isf16(P) ? (int)kl->sa[t / NCH] : 0; };
+        auto sb_of = [&](int t) { return isf16(P) ? (int)kl->sb[t / NCH] : 0; };
+        // MFMA on the chunk of step t in LDS buffer bf; at the last chunk of a
+        // leaf product its fresh accumulator is added to the tile sum
+        // (two-level summation: the rounding error does not grow with the
+        // number of kept products)
+        auto compute = [&](int bf, int t) {
             if constexpr (P != kF64) {
-                // each leaf product is summed in a fresh FP32 accumulator and added
-                // to the tile sum once (two-level summation: the rounding error no
-                // longer grows with the number of kept products of the tile)
-                chunk_mma<B, P, Acc>(smem + buf * G::BUF_BYTES, part, lane, wr, wc);
-                if (ch == NCH - 1) {
+                chunk_mma<B, P, Acc>(smem + bf * G::BUF_BYTES, part, lane, wr, wc);
+                if (t % NCH == NCH - 1) {
+                    const int un = -(sa_of(t) + sb_of(t));
 #pragma unroll
                     for (int i = 0; i < R; ++i)
 #pragma unroll
                         for (int j = 0; j < R; ++j) {
-                            if constexpr (isf16(P)) {  // undo the task's power-of-two scales
+                            if constexpr (isf16(P)) {  // undo the product's power-of-two scales
 #pragma unroll
-                                for (int q = 0; q < 4; ++q) acc[i][j][q] += ldexpf(part[i][j][q], unscale);
+                                for (int q = 0; q < 4; ++q) acc[i][j][q] += ldexpf(part[i][j][q], un);
                             } else {
                                 acc[i][j] += part[i][j];
                             }
@@ -368,19 +404,34 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
                         }
                 }
             } else {
-                chunk_mma<B, P, Acc>(smem + buf * G::BUF_BYTES, acc, lane, wr, wc);
+                chunk_mma<B, P, Acc>(smem + bf * G::BUF_BYTES, acc, lane, wr, wc);
             }
-            if (!more) break;
-            stage_store<B, P, TA>(st, smem + (buf ^ 1) * G::BUF_BYTES, tid, nsa, nsb);
+        };
+        // Two register stages keep two chunks of loads in flight while LDS
+        // double-buffers the chunk under MFMA and the next one.
+        Stage<B, P, TA> s0, s1;
+        stage_load<B, P, TA>(s0, a_src(0), b_src(0), tid);
+        stage_store<B, P, TA>(s0, smem, tid, sa_of(0), sb_of(0));
+        __syncthreads();
+        if (1 < T) stage_load<B, P, TA>(s0, a_src(1), b_src(1), tid);
+        int buf = 0;
+        for (int t = 0;;) {
+            if (t + 2 < T) stage_load<B, P, TA>(s1, a_src(t + 2), b_src(t + 2), tid);
+            compute(buf, t);
+            if (t + 1 >= T) break;
+            stage_store<B, P, TA>(s0, smem + (buf ^ 1) * G::BUF_BYTES, tid, sa_of(t + 1), sb_of(t + 1));
             __syncthreads();
             buf ^= 1;
-            kcur = knext;
-            ch = chn;
-            sa = nsa;
-            sb = nsb;
-            unscale = nun;
+            ++t;
+            if (t + 2 < T) stage_load<B, P, TA>(s0, a_src(t + 2), b_src(t + 2), tid);
+            compute(buf, t);
+            if (t + 1 >= T) break;
+            stage_store<B, P, TA>(s1, smem + (buf ^ 1) * G::BUF_BYTES, tid, sa_of(t + 1), sb_of(t + 1));
+            __syncthreads();
+            buf ^= 1;
+            ++t;
         }
-        __syncthreads();  // all waves done reading the stage buffers
+        __syncthreads();  // stage buffers and the list are free again
     }
 
     // ---------------------------------------------------------------- epilogue
@@ -399,10 +450,10 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             }
     __syncthreads();
 
-    TC* Cg = reinterpret_cast<TC*>(d.C) + local * TS;
+    GLOBAL TC* Cg = (GLOBAL TC*)d.C + local * TS;
     constexpr int VC = 16 / (int)sizeof(TC);
     double mx = 0.0, idem = 0.0;
-    const TC* Xg = SP2 ? reinterpret_cast<const TC*>(d.X) + local * TS : nullptr;
+    const GLOBAL TC* Xg = SP2 ? (const GLOBAL TC*)d.X + local * TS : nullptr;
     const int br = SP2 ? *branch : 0;
     for (int u = tid; u < B * B / VC; u += 256) {
         const int r = u / (B / VC), c = (u % (B / VC)) * VC;
@@ -503,12 +554,13 @@ __global__ void __launch_bounds__(256) k_leaf(const ProdDesc* __restrict__ desc,
                                               int64_t chunk, const int* __restrict__ branch,
                                               const int* __restrict__ active) {
     __shared__ __attribute__((aligned(16))) char smem[Geo<B, P>::SMEM];
+    __shared__ KList kl;
     __shared__ double red[2][4];
     if (active && *active == 0) return;
     const int64_t x = blockIdx.x;
     const int64_t t = (x & 7) * chunk + (x >> 3);
     if (t >= total) return;
-    leaf_tile<B, P, TA, TC, SP2>(desc, nprod, t, smem, red, branch);
+    leaf_tile<B, P, TA, TC, SP2>(desc, nprod, t, smem, &kl, red, branch, true);
 }
 
 // Persistent schedule: resident blocks pull positions from a queue counter
@@ -520,6 +572,7 @@ __global__ void __launch_bounds__(256) k_leaf_queue(const ProdDesc* __restrict__
                                                     unsigned long long* __restrict__ queue,
                                                     const int* __restrict__ branch, const int* __restrict__ active) {
     __shared__ __attribute__((aligned(16))) char smem[Geo<B, P>::SMEM];
+    __shared__ KList kl;
     __shared__ double red[2][4];
     __shared__ long long s_pos;
     if (active && *active == 0) return;
@@ -529,7 +582,8 @@ __global__ void __launch_bounds__(256) k_leaf_queue(const ProdDesc* __restrict__
         const long long pos = s_pos;
         __syncthreads();
         if (pos >= total) break;
-        leaf_tile<B, P, TA, TC, SP2>(desc, nprod, order ? (int64_t)order[pos] : (int64_t)pos, smem, red, branch);
+        leaf_tile<B, P, TA, TC, SP2>(desc, nprod, order ? (int64_t)order[pos] : (int64_t)pos, smem, &kl, red, branch,
+                                     false);
     }
 }
 
