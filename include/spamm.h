@@ -154,7 +154,9 @@ typedef struct {
     double ms_cull;    /* counter reset, mask clear and every cull tier      */
     double ms_leaf;    /* the leaf-product launch (incl. its epilogue)       */
     double ms_norms;   /* upper tiers of the result's norm pyramid           */
-    double ms_total;   /* first to last event                                */
+    double ms_total;   /* first to last event (split + cull + leaf + norms)  */
+    double ms_split;   /* 16-bit leaves: hi/lo split of operands whose tiles
+                          changed since their last split (0 otherwise)       */
 } spamm_timing;
 
 /* spamm_multiply with phase timing: same arguments and result; records HIP

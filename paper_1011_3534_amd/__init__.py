@@ -78,7 +78,7 @@ class TauInfo(ctypes.Structure):
 
 class Timing(ctypes.Structure):
     _fields_ = [("ms_cull", ctypes.c_double), ("ms_leaf", ctypes.c_double), ("ms_norms", ctypes.c_double),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("ms_split", ctypes.c_double)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -118,6 +118,7 @@ void release(spamm_matrix* M) {
     dev_free(M, M->tiles, M->last_stream);
     dev_free(M, M->norms, M->last_stream);
     dev_free(M, M->texp, M->last_stream);
+    dev_free(M, M->split, M->last_stream);
     delete M;
 }
 
@@ -181,6 +182,8 @@ ProdDesc make_desc(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C
     d.eA = A->texp;
     d.eB = B->texp;
     d.eC = C->texp;
+    d.A16 = A->split;
+    d.B16 = B->split;
     d.mask = C->ps->mask;
     d.nonempty = nonempty_ctr(C->ps->ctr);
     for (int l = 0; l < kMaxLevels; ++l) {
@@ -241,7 +244,38 @@ spamm_status read_stats(spamm_matrix* C, hipStream_t s, spamm_stats* st, double 
     return SPAMM_OK;
 }
 
+// Split 16-bit tiles a leaf precision reads (-1: none).
+int split_kind(spamm_leaf_prec p) {
+    if (p == SPAMM_LEAF_F16 || p == SPAMM_LEAF_F16X3) return kSplitF16;
+    if (p == SPAMM_LEAF_BF16 || p == SPAMM_LEAF_BF16X3) return kSplitBF16;
+    return -1;
+}
+
 }  // namespace
+
+// Allocate M's split tiles if needed (allocation only: safe before a capture).
+static spamm_status alloc_split(const spamm_matrix* Mc, hipStream_t s) {
+    auto* M = const_cast<spamm_matrix*>(Mc);  // the split is a cache of the tiles
+    if (M->split) return SPAMM_OK;
+    M->split = (uint16_t*)dev_alloc(M, (size_t)(M->nb * M->nb) * M->b * M->b * 2 * sizeof(uint16_t), s);
+    if (!M->split) return set_error(SPAMM_ENOMEM, "device allocation of split tiles failed");
+    M->split_gen = 0;
+    return SPAMM_OK;
+}
+
+// Bring M's split tiles in line with its current tiles (always re-split when
+// forced, e.g. inside a captured graph whose products rewrite the tiles).
+static spamm_status ensure_split(const spamm_matrix* Mc, int kind, hipStream_t s, const int* active, bool force) {
+    auto* M = const_cast<spamm_matrix*>(Mc);
+    spamm_status r = alloc_split(M, s);
+    if (r != SPAMM_OK) return r;
+    if (force || M->split_kind != kind || M->split_gen != M->gen) {
+        SPAMM_HIP(launch_split(M, kind, active, s));
+        M->split_kind = kind;
+        M->split_gen = M->gen;
+    }
+    return SPAMM_OK;
+}
 
 // Shared by multiply and SP2: cull + leaf products + C pyramid, all enqueued.
 spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C, double tau,
@@ -249,6 +283,15 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
                              const int* d_active, ProdDesc* d_desc_override) {
     ProductScratch* ps = C->ps;
     ProdDesc* d_desc = d_desc_override;
+    if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[4], s));
+    const int kind = split_kind(prec);
+    if (kind >= 0 && !sp2) {
+        // (SP2 splits its operands itself, inside the captured iteration)
+        spamm_status r = ensure_split(A, kind, s, d_active, false);
+        if (r == SPAMM_OK && B != A) r = ensure_split(B, kind, s, d_active, false);
+        if (r != SPAMM_OK) return r;
+    }
+    C->gen++;
     if (!d_desc) {
         ProdDesc d = make_desc(A, B, C, tau);
         if (!ps->desc_valid || std::memcmp(&d, &ps->host_desc, sizeof d) != 0) {
@@ -314,6 +357,7 @@ spamm_status spamm_build(const void* dev_a, int64_t n, int64_t lda, spamm_dtype 
         return set_error(SPAMM_EINVAL, "existing handle differs in n, leaf or dtype");
     }
     M->last_stream = s;
+    M->gen++;
     hipError_t e = hipMemsetAsync(status_word(M), 0, 4, s);
     if (e == hipSuccess) e = launch_pack_norm(dev_a, n, lda, dt, M, status_word(M), s);
     if (e == hipSuccess) e = launch_upper_norms(M, s, nullptr);
@@ -364,7 +408,7 @@ spamm_status spamm_multiply(const spamm_matrix* A, const spamm_matrix* B, double
 spamm_status spamm_multiply_timed(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,
                                   void* stream, spamm_matrix** C, spamm_timing* t) {
     if (!t) return set_error(SPAMM_EINVAL, "timing output is null");
-    static thread_local hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    static thread_local hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     if (!ev[0])
         for (auto& e : ev) SPAMM_HIP(hipEventCreate(&e));
     t_phase = ev;
@@ -372,15 +416,17 @@ spamm_status spamm_multiply_timed(const spamm_matrix* A, const spamm_matrix* B, 
     t_phase = nullptr;
     if (r != SPAMM_OK) return r;
     SPAMM_HIP(hipEventSynchronize(ev[3]));
-    float a = 0, b = 0, c = 0, d = 0;
+    float a = 0, b = 0, c = 0, d = 0, sp = 0;
+    SPAMM_HIP(hipEventElapsedTime(&sp, ev[4], ev[0]));
     SPAMM_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
     SPAMM_HIP(hipEventElapsedTime(&b, ev[1], ev[2]));
     SPAMM_HIP(hipEventElapsedTime(&c, ev[2], ev[3]));
-    SPAMM_HIP(hipEventElapsedTime(&d, ev[0], ev[3]));
+    SPAMM_HIP(hipEventElapsedTime(&d, ev[4], ev[3]));
     t->ms_cull = a;
     t->ms_leaf = b;
     t->ms_norms = c;
     t->ms_total = d;
+    t->ms_split = sp;
     return SPAMM_OK;
 }
 
@@ -533,10 +579,20 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
     // batch plan
     int64_t total = 0, cap = 1, items[kMaxLevels] = {};
     int Lmax = 0, maxc = 1;
+    const int kind = split_kind(prec);
+    for (int m = 0; m < count && kind >= 0 && r == SPAMM_OK; ++m) {
+        r = ensure_split(A[m], kind, s, nullptr, false);
+        if (r == SPAMM_OK) r = ensure_split(B[m], kind, s, nullptr, false);
+    }
+    if (r != SPAMM_OK) {
+        release_fresh();
+        return r;
+    }
     static thread_local std::vector<ProdDesc> hd;
     hd.assign(count, ProdDesc{});
     for (int m = 0; m < count; ++m) {
         spamm_matrix* Cm = out[m];
+        Cm->gen++;
         hd[m] = make_desc(A[m], B[m], Cm, tau[m]);
         hd[m].tile_base = total;
         total += Cm->nb * Cm->nb;
@@ -692,9 +748,16 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
         cleanup();
         return r;
     };
+    const int kind = split_kind(prec);
+    for (int i = 0; i < 2 && kind >= 0 && r == SPAMM_OK; ++i) r = alloc_split(X[i], s);
+    if (r != SPAMM_OK) {
+        cleanup();
+        return r;
+    }
     hipError_t e = hipMemcpyAsync(st, &h, sizeof h, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_gershgorin(H, glo, ghi, st, s);
     if (e == hipSuccess) e = launch_sp2_init(H, X[0], part, st, s);
+    if (e == hipSuccess && kind >= 0) e = launch_split(X[0], kind, nullptr, s);
     // descriptors of the two directions X0 -> X1 and X1 -> X0
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
         spamm_matrix* src = X[i];
@@ -716,6 +779,11 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
         spamm_matrix* src = X[m & 1];
         spamm_matrix* dst = X[(m + 1) & 1];
         r = enqueue_product(src, src, dst, tau, prec, cs, 0, 1, d_branch, d_active, dst->ps->desc);
+        if (r == SPAMM_OK && kind >= 0) {
+            // the next step reads X_{m+1} through its split tiles
+            e = launch_split(dst, kind, d_active, cs);
+            if (e != hipSuccess) r = hip_error(e, "sp2 split launch");
+        }
         if (r == SPAMM_OK) {
             e = launch_sp2_finalize(part, nb, &dst->ps->ctr->survivors[0][0], st, m, cs);
             if (e != hipSuccess) r = hip_error(e, "sp2 finalize launch");
@@ -763,6 +831,7 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
     cs = nullptr;
     dev_free(owner, scratch, s);
     scratch = nullptr;
+    X[res]->gen++;  // its split tiles are not kept in step with the result
     *P = X[res];
     X[res] = nullptr;
     cleanup();

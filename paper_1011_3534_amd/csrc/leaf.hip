@@ -34,7 +34,6 @@ enum Kind { kF64 = 0, kF32 = 1, kBF16 = 2, kBF16X3 = 3, kF16 = 4, kF16X3 = 5 };
 constexpr bool is16(int k) { return k >= kBF16; }
 constexpr bool isx3(int k) { return k == kBF16X3 || k == kF16X3; }
 constexpr bool isf16(int k) { return k == kF16 || k == kF16X3; }
-constexpr int kF16Bias = 14;  // scaled tile max lies in [2^14, 2^15)
 
 // Geometry of one (leaf size, precision) instance.
 template <int B, int P>
@@ -57,63 +56,58 @@ struct Geo {
     static constexpr int SMEM = (2 * BUF_BYTES > C_BYTES) ? 2 * BUF_BYTES : C_BYTES;
 };
 
-// Kept K of one segment of a tile's mask (four words), with the FP16 scale
-// exponents of A_IK and B_KJ.
+// Kept K of one segment of a tile's mask (four words), with the exponent that
+// undoes the FP16 scales of A_IK and B_KJ on the product.
 struct KList {
     int k[256];
-    int16_t sa[256];
-    int16_t sb[256];
+    int16_t un[256];
 };
 
-__device__ inline uint16_t bf16_bits(float x) {
-    __bf16 h = (__bf16)x;
-    return __builtin_bit_cast(uint16_t, h);
-}
-__device__ inline float bf16_val(uint16_t u) { return (float)__builtin_bit_cast(__bf16, u); }
-__device__ inline uint16_t f16_bits(float x) {
-    _Float16 h = (_Float16)x;
-    return __builtin_bit_cast(uint16_t, h);
-}
-__device__ inline float f16_val(uint16_t u) { return (float)__builtin_bit_cast(_Float16, u); }
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <int P>
-__device__ inline void split16(float x, uint16_t& hi, uint16_t& lo) {
-    if constexpr (P == kBF16 || P == kBF16X3) {
-        hi = bf16_bits(x);
-        if constexpr (isx3(P)) lo = bf16_bits(x - bf16_val(hi));
-    } else {
-        hi = f16_bits(x);
-        if constexpr (isx3(P)) lo = f16_bits(x - f16_val(hi));
-    }
-}
-
-// fp16 operands are scaled by 2^e per tile (exact); bf16 needs no scaling
-template <int P>
-__device__ inline float scale_in(float x, int e) {
-    if constexpr (isf16(P)) return ldexpf(x, e);
-    return x;
-}
-
-// Register stage of one k-chunk: the raw operand values of this thread.
+// Register stage of one k-chunk, FP32/FP64 leaves: float4/double2-sized units
+// of A rows and of B rows.
 template <int B, int P, typename TA>
 struct Stage {
     using G = Geo<B, P>;
     static constexpr int KC = G::KC;
-    // 32-bit and FP64 paths: float4/double2-sized units of A rows and B rows
-    static constexpr int VA = is16(P) ? 8 : (16 / (int)sizeof(TA));
+    static constexpr int VA = 16 / (int)sizeof(TA);
     static constexpr int NU = B * KC / VA;                                // units per operand chunk
     static constexpr int UA = (NU + 255) / 256;                           // units per thread
-    static constexpr int UB = UA;
     static constexpr bool PARTIAL = (NU % 256) != 0;
     TA a[UA][VA];
-    TA b[UB][VA];
+    TA b[UA][VA];
 };
 
+// Register stage of one k-chunk, 16-bit leaves (pre-split hi/lo tiles):
+// A units are 8 consecutive k of one row (16 bytes); B units are 8
+// consecutive k of a column pair, one 32-bit word per k.
+template <int B, int P>
+struct Stage16 {
+    using G = Geo<B, P>;
+    static constexpr int KC = G::KC;
+    static constexpr int NA = B * KC / 8;
+    static constexpr int UA = (NA + 255) / 256;
+    static constexpr bool PA = (NA % 256) != 0;
+    static constexpr int NB = (B / 2) * (KC / 8);
+    static constexpr int UB = (NB + 255) / 256;
+    static constexpr bool PB = (NB % 256) != 0;
+    u32x4 a[G::NARR][UA];
+    uint32_t b[G::NARR][UB][8];
+};
+
+// Buffer resource over `bytes` bytes from `base` (uniform).  A load whose
+// offset lies outside [0, bytes) returns zero without a memory access, so a
+// resource with bytes = 0 turns a whole stage load into a no-op.
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// ra: A tile from the chunk's first column (row stride B); rb: B tile from
+// the chunk's first row (row stride B).
 template <int B, int P, typename TA>
-__device__ inline void stage_load(Stage<B, P, TA>& st, const GLOBAL TA* __restrict__ At,
-                                  const GLOBAL TA* __restrict__ Bt, int tid) {
-    // At: A tile + chunk column offset (row stride B); Bt: B tile + chunk row
-    // offset (row stride B)
+__device__ inline void stage_load(Stage<B, P, TA>& st, __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rb,
+                                  int tid) {
     using S = Stage<B, P, TA>;
     constexpr int KC = S::KC, VA = S::VA;
 #pragma unroll
@@ -121,86 +115,112 @@ __device__ inline void stage_load(Stage<B, P, TA>& st, const GLOBAL TA* __restri
         const int unit = tid + u * 256;
         if (S::PARTIAL && unit >= S::NU) break;
         const int r = unit / (KC / VA), k = (unit % (KC / VA)) * VA;
-        const GLOBAL TA* src = At + r * B + k;
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(ra, (r * B + k) * (int)sizeof(TA), 0, 0);
+        const TA* e = reinterpret_cast<const TA*>(&v);
 #pragma unroll
-        for (int j = 0; j < VA; ++j) st.a[u][j] = src[j];
+        for (int j = 0; j < VA; ++j) st.a[u][j] = e[j];
     }
-    if constexpr (is16(P)) {
-        // B^T units: column c, 8 consecutive k (each load coalesced over c)
 #pragma unroll
-        for (int u = 0; u < S::UB; ++u) {
-            const int unit = tid + u * 256;
-            if (S::PARTIAL && unit >= S::NU) break;
-            const int c = unit % B, k = (unit / B) * 8;
+    for (int u = 0; u < S::UA; ++u) {
+        const int unit = tid + u * 256;
+        if (S::PARTIAL && unit >= S::NU) break;
+        const int k = unit / (B / VA), c = (unit % (B / VA)) * VA;
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rb, (k * B + c) * (int)sizeof(TA), 0, 0);
+        const TA* e = reinterpret_cast<const TA*>(&v);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) st.b[u][j] = Bt[(k + j) * B + c];
-        }
-    } else {
-#pragma unroll
-        for (int u = 0; u < S::UB; ++u) {
-            const int unit = tid + u * 256;
-            if (S::PARTIAL && unit >= S::NU) break;
-            const int k = unit / (B / VA), c = (unit % (B / VA)) * VA;
-            const GLOBAL TA* src = Bt + k * B + c;
-#pragma unroll
-            for (int j = 0; j < VA; ++j) st.b[u][j] = src[j];
-        }
+        for (int j = 0; j < VA; ++j) st.b[u][j] = e[j];
     }
 }
 
 template <int B, int P, typename TA>
-__device__ inline void stage_store(const Stage<B, P, TA>& st, char* buf, int tid, int sa, int sb) {
+__device__ inline void stage_store(const Stage<B, P, TA>& st, char* buf, int tid) {
     using G = Geo<B, P>;
     using S = Stage<B, P, TA>;
     using E = typename G::E;
     constexpr int KC = G::KC, VA = S::VA;
     E* As = reinterpret_cast<E*>(buf);
-    E* Bs = As + G::NARR * G::A_ELEMS;
+    E* Bs = As + G::A_ELEMS;
 #pragma unroll
     for (int u = 0; u < S::UA; ++u) {
         const int unit = tid + u * 256;
         if (S::PARTIAL && unit >= S::NU) break;
         const int r = unit / (KC / VA), k = (unit % (KC / VA)) * VA;
-        if constexpr (is16(P)) {
-            uint16_t h[8], l[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) split16<P>(scale_in<P>((float)st.a[u][j], sa), h[j], l[j]);
-            uint4 vh, vl;
-            vh.x = h[0] | ((uint32_t)h[1] << 16); vh.y = h[2] | ((uint32_t)h[3] << 16);
-            vh.z = h[4] | ((uint32_t)h[5] << 16); vh.w = h[6] | ((uint32_t)h[7] << 16);
-            *reinterpret_cast<uint4*>(As + r * G::SA + k) = vh;
-            if constexpr (isx3(P)) {
-                vl.x = l[0] | ((uint32_t)l[1] << 16); vl.y = l[2] | ((uint32_t)l[3] << 16);
-                vl.z = l[4] | ((uint32_t)l[5] << 16); vl.w = l[6] | ((uint32_t)l[7] << 16);
-                *reinterpret_cast<uint4*>(As + G::A_ELEMS + r * G::SA + k) = vl;
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < VA; ++j) As[r * G::SA + k + j] = (E)st.a[u][j];
-        }
+        for (int j = 0; j < VA; ++j) As[r * G::SA + k + j] = (E)st.a[u][j];
     }
 #pragma unroll
-    for (int u = 0; u < S::UB; ++u) {
+    for (int u = 0; u < S::UA; ++u) {
         const int unit = tid + u * 256;
         if (S::PARTIAL && unit >= S::NU) break;
-        if constexpr (is16(P)) {
-            const int c = unit % B, k = (unit / B) * 8;
-            uint16_t h[8], l[8];
+        const int k = unit / (B / VA), c = (unit % (B / VA)) * VA;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) split16<P>(scale_in<P>((float)st.b[u][j], sb), h[j], l[j]);
-            uint4 vh, vl;
-            vh.x = h[0] | ((uint32_t)h[1] << 16); vh.y = h[2] | ((uint32_t)h[3] << 16);
-            vh.z = h[4] | ((uint32_t)h[5] << 16); vh.w = h[6] | ((uint32_t)h[7] << 16);
-            *reinterpret_cast<uint4*>(Bs + c * G::SB + k) = vh;
-            if constexpr (isx3(P)) {
-                vl.x = l[0] | ((uint32_t)l[1] << 16); vl.y = l[2] | ((uint32_t)l[3] << 16);
-                vl.z = l[4] | ((uint32_t)l[5] << 16); vl.w = l[6] | ((uint32_t)l[7] << 16);
-                *reinterpret_cast<uint4*>(Bs + G::B_ELEMS + c * G::SB + k) = vl;
-            }
-        } else {
-            const int k = unit / (B / VA), c = (unit % (B / VA)) * VA;
+        for (int j = 0; j < VA; ++j) Bs[k * G::SB + c + j] = (E)st.b[u][j];
+    }
+}
+
+// ra[h] / rb[h]: hi (h = 0) and lo (h = 1) tiles as in stage_load.
+template <int B, int P>
+__device__ inline void stage16_load(Stage16<B, P>& st, const __amdgpu_buffer_rsrc_t* ra,
+                                    const __amdgpu_buffer_rsrc_t* rb, int tid) {
+    using S = Stage16<B, P>;
+    constexpr int KC = S::KC;
 #pragma unroll
-            for (int j = 0; j < VA; ++j) Bs[k * G::SB + c + j] = (E)st.b[u][j];
+    for (int h = 0; h < Geo<B, P>::NARR; ++h) {
+#pragma unroll
+        for (int u = 0; u < S::UA; ++u) {
+            const int unit = tid + u * 256;
+            if (S::PA && unit >= S::NA) break;
+            const int r = unit / (KC / 8), k = (unit % (KC / 8)) * 8;
+            st.a[h][u] = __builtin_amdgcn_raw_buffer_load_b128(ra[h], (r * B + k) * 2, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < S::UB; ++u) {
+            const int unit = tid + u * 256;
+            if (S::PB && unit >= S::NB) break;
+            const int cp = unit % (B / 2), k = (unit / (B / 2)) * 8;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                st.b[h][u][j] = __builtin_amdgcn_raw_buffer_load_b32(rb[h], ((k + j) * (B / 2) + cp) * 4, 0, 0);
+        }
+    }
+}
+
+// A rows go to LDS as loaded; each B unit is transposed into two LDS rows of
+// B^T (columns 2cp and 2cp+1, 8 consecutive k each).
+template <int B, int P>
+__device__ inline void stage16_store(const Stage16<B, P>& st, char* buf, int tid) {
+    using G = Geo<B, P>;
+    using S = Stage16<B, P>;
+    constexpr int KC = G::KC;
+    uint16_t* As = reinterpret_cast<uint16_t*>(buf);
+    uint16_t* Bs = As + G::NARR * G::A_ELEMS;
+#pragma unroll
+    for (int h = 0; h < G::NARR; ++h) {
+#pragma unroll
+        for (int u = 0; u < S::UA; ++u) {
+            const int unit = tid + u * 256;
+            if (S::PA && unit >= S::NA) break;
+            const int r = unit / (KC / 8), k = (unit % (KC / 8)) * 8;
+            *reinterpret_cast<u32x4*>(As + h * G::A_ELEMS + r * G::SA + k) = st.a[h][u];
+        }
+#pragma unroll
+        for (int u = 0; u < S::UB; ++u) {
+            const int unit = tid + u * 256;
+            if (S::PB && unit >= S::NB) break;
+            const int cp = unit % (B / 2), k = (unit / (B / 2)) * 8;
+            const uint32_t* w = st.b[h][u];
+            u32x4 ev, od;
+            ev.x = (w[0] & 0xFFFFu) | (w[1] << 16);
+            ev.y = (w[2] & 0xFFFFu) | (w[3] << 16);
+            ev.z = (w[4] & 0xFFFFu) | (w[5] << 16);
+            ev.w = (w[6] & 0xFFFFu) | (w[7] << 16);
+            od.x = (w[0] >> 16) | (w[1] & 0xFFFF0000u);
+            od.y = (w[2] >> 16) | (w[3] & 0xFFFF0000u);
+            od.z = (w[4] >> 16) | (w[5] & 0xFFFF0000u);
+            od.w = (w[6] >> 16) | (w[7] & 0xFFFF0000u);
+            uint16_t* dst = Bs + h * G::B_ELEMS + (2 * cp) * G::SB + k;
+            *reinterpret_cast<u32x4*>(dst) = ev;
+            *reinterpret_cast<u32x4*>(dst + G::SB) = od;
         }
     }
 }
@@ -323,8 +343,7 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
     }
     const int64_t local = (int64_t)I * nb + J;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
-    const GLOBAL TA* Ag = (const GLOBAL TA*)d.A;
-    const GLOBAL TA* Bg = (const GLOBAL TA*)d.B;
+    const int64_t lo16 = (int64_t)nb * nb * B * B;  // hi tiles -> lo tiles
     constexpr int64_t TS = (int64_t)B * B;
 
     Acc acc[R][R], part[R][R];
@@ -363,24 +382,15 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
                 const int pos = base + __popcll(mine & ((1ull << lane) - 1ull));
                 const int k = (w0 + w) * 64 + lane;
                 kl->k[pos] = k;
-                if constexpr (isf16(P)) {
-                    // A_IK is scaled by 2^sa, B_KJ by 2^sb (exact powers of two)
-                    int ea = d.eA[(int64_t)I * nb + k], eb = d.eB[(int64_t)k * nb + J];
-                    ea = ea == -128 ? 0 : ea;
-                    eb = eb == -128 ? 0 : eb;
-                    kl->sa[pos] = (int16_t)(kF16Bias - ea);
-                    kl->sb[pos] = (int16_t)(kF16Bias - eb);
-                }
+                if constexpr (isf16(P))
+                    kl->un[pos] = (int16_t)-(f16_shift(d.eA[(int64_t)I * nb + k]) + f16_shift(d.eB[(int64_t)k * nb + J]));
             }
         }
         __syncthreads();
 
-        // step t = (list entry t / NCH, k-chunk t % NCH)
-        const int T = nk * NCH;
-        auto a_src = [&](int t) { return Ag + ((int64_t)I * nb + kl->k[t / NCH]) * TS + (t % NCH) * KC; };
-        auto b_src = [&](int t) { return Bg + ((int64_t)kl->k[t / NCH] * nb + J) * TS + (int64_t)(t % NCH) * KC * B; };
-        auto sa_of = [&](int t) { return isf16(P) ? (int)kl->sa[t / NCH] : 0; };
-        auto sb_of = [&](int t) { return isf16(P) ? (int)kl->sb[t / NCH] : 0; };
+        // step t = (list entry t / NCH, k-chunk t % NCH); T is uniform, and
+        // the loop control stays in scalar registers
+        const int T = __builtin_amdgcn_readfirstlane(nk * NCH);
         // MFMA on the chunk of step t in LDS buffer bf; at the last chunk of a
         // leaf product its fresh accumulator is added to the tile sum
         // (two-level summation: the rounding error does not grow with the
@@ -389,7 +399,7 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             if constexpr (P != kF64) {
                 chunk_mma<B, P, Acc>(smem + bf * G::BUF_BYTES, part, lane, wr, wc);
                 if (t % NCH == NCH - 1) {
-                    const int un = -(sa_of(t) + sb_of(t));
+                    const int un = isf16(P) ? (int)kl->un[t / NCH] : 0;
 #pragma unroll
                     for (int i = 0; i < R; ++i)
 #pragma unroll
@@ -409,28 +419,81 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         };
         // Two register stages keep two chunks of loads in flight while LDS
         // double-buffers the chunk under MFMA and the next one.
-        Stage<B, P, TA> s0, s1;
-        stage_load<B, P, TA>(s0, a_src(0), b_src(0), tid);
-        stage_store<B, P, TA>(s0, smem, tid, sa_of(0), sb_of(0));
+        using St = typename std::conditional<is16(P), Stage16<B, P>, Stage<B, P, TA>>::type;
+        // Loads are issued for every step t < T + 3 (those past the end with
+        // empty resources, which load nothing), so that every path through
+        // the loop has the same loads in flight and the waits before each LDS
+        // store need only cover the older stage.
+        auto ld = [&](St& st, int t) {
+            const bool live = t < T;
+            const int tt = live ? t : T - 1;
+            const int k = __builtin_amdgcn_readfirstlane(kl->k[tt / NCH]);
+            const int ch = tt % NCH;
+            const int64_t ta = ((int64_t)I * nb + k) * TS, tb = ((int64_t)k * nb + J) * TS;
+            if constexpr (is16(P)) {
+                const uint32_t na = live ? (uint32_t)((TS - ch * KC) * 2) : 0u;
+                const uint32_t nbb = live ? (uint32_t)((TS - ch * KC * B) * 2) : 0u;
+                __amdgpu_buffer_rsrc_t ra[2], rb[2];
+#pragma unroll
+                for (int h = 0; h < G::NARR; ++h) {
+                    ra[h] = rsrc(d.A16 + h * lo16 + ta + ch * KC, na);
+                    rb[h] = rsrc(d.B16 + h * lo16 + tb + (int64_t)ch * KC * B, nbb);
+                }
+                stage16_load<B, P>(st, ra, rb, tid);
+            } else {
+                const uint32_t na = live ? (uint32_t)((TS - ch * KC) * sizeof(TA)) : 0u;
+                const uint32_t nbb = live ? (uint32_t)((TS - ch * KC * B) * sizeof(TA)) : 0u;
+                stage_load<B, P, TA>(st, rsrc((const TA*)d.A + ta + ch * KC, na),
+                                     rsrc((const TA*)d.B + tb + (int64_t)ch * KC * B, nbb), tid);
+            }
+        };
+        auto sto = [&](const St& st, int bf) {
+            if constexpr (is16(P)) stage16_store<B, P>(st, smem + bf * G::BUF_BYTES, tid);
+            else stage_store<B, P, TA>(st, smem + bf * G::BUF_BYTES, tid);
+        };
+        // Invariant at the top of each half step: LDS buffer `buf` holds step
+        // t, one register stage holds (or is receiving) step t + 1 and the
+        // other step t + 2.  A stage is refilled right after it is stored, so
+        // both stages stay live throughout (their registers are never reused
+        // for other values) and every load has two steps to arrive.
+        St s0, s1;
+        ld(s0, 0);
+        sto(s0, 0);
         __syncthreads();
-        if (1 < T) stage_load<B, P, TA>(s0, a_src(1), b_src(1), tid);
+        ld(s0, 1);
+        __builtin_amdgcn_sched_barrier(0);  // stage s0 is the older one on every path
+        ld(s1, 2);
+        __builtin_amdgcn_sched_barrier(0);
         int buf = 0;
-        for (int t = 0;;) {
-            if (t + 2 < T) stage_load<B, P, TA>(s1, a_src(t + 2), b_src(t + 2), tid);
+        // (scheduling barriers keep each stage's loads ahead of the MFMA work
+        // they overlap; no exit follows a refill of s0 before s1 is refilled,
+        // so on every path s0's loads are older than s1's)
+        for (int t = 0;; t += 2) {
+            __builtin_amdgcn_sched_barrier(0);
             compute(buf, t);
+            __builtin_amdgcn_sched_barrier(0);
             if (t + 1 >= T) break;
-            stage_store<B, P, TA>(s0, smem + (buf ^ 1) * G::BUF_BYTES, tid, sa_of(t + 1), sb_of(t + 1));
+            sto(s0, buf ^ 1);
             __syncthreads();
             buf ^= 1;
-            ++t;
-            if (t + 2 < T) stage_load<B, P, TA>(s0, a_src(t + 2), b_src(t + 2), tid);
-            compute(buf, t);
-            if (t + 1 >= T) break;
-            stage_store<B, P, TA>(s1, smem + (buf ^ 1) * G::BUF_BYTES, tid, sa_of(t + 1), sb_of(t + 1));
+            if (t + 2 >= T) {
+                compute(buf, t + 1);
+                break;
+            }
+            ld(s0, t + 3);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(buf, t + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            sto(s1, buf ^ 1);
             __syncthreads();
             buf ^= 1;
-            ++t;
+            ld(s1, t + 4);
+            __builtin_amdgcn_sched_barrier(0);
         }
+        // Drain the memory counters: no load issued in this segment is still
+        // pending, so the wait analysis at the top of the next segment's loop
+        // need not assume one (it would otherwise wait for every load in flight).
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();  // stage buffers and the list are free again
     }
 

@@ -28,6 +28,16 @@ __host__ __device__ inline uint32_t key_j(uint64_t k) { return (uint32_t)((k >> 
 __host__ __device__ inline uint32_t key_k(uint64_t k) { return (uint32_t)(k & 0x7FFFF); }
 constexpr int64_t kMaxNb = (int64_t)1 << 19;
 
+// FP16 leaves: a tile whose largest |x| has binary exponent e (-128 for an
+// all-zero tile) is scaled by 2^f16_shift(e), which puts that largest value in
+// [2^14, 2^15); the product of two scaled tiles is scaled back exactly.
+constexpr int kF16Bias = 14;
+__host__ __device__ inline int f16_shift(int e) { return kF16Bias - (e == -128 ? 0 : e); }
+
+// Split 16-bit copies of FP32 tiles read by the 16-bit leaf precisions.
+constexpr int kSplitF16 = 0;   // hi = fp16(x 2^s), lo = fp16(x 2^s - hi), s = f16_shift(tile exponent)
+constexpr int kSplitBF16 = 1;  // hi = bf16(x), lo = bf16(x - hi)
+
 // Per-product descriptor read by the cull and leaf kernels.  Operand and
 // result pyramids share the same tier shapes (equal n and leaf).
 struct ProdDesc {
@@ -43,6 +53,8 @@ struct ProdDesc {
     uint64_t* mask;           // leaf bitmask, W words per C tile
     double* sp2_part;         // SP2: per-tile FP64 partials (idempotency, trace)
     const void* X;            // SP2: the operand tiles X_m (== A == B)
+    const uint16_t* A16;      // split 16-bit tiles of A and B: hi tiles, then lo
+    const uint16_t* B16;      //   tiles at +nb^2 b^2 elements (16-bit leaves only)
     unsigned long long* nonempty;  // count of C tiles with at least one kept product
     int64_t lvl_off[kMaxLevels];
     int32_t lvl_m[kMaxLevels];
@@ -86,6 +98,10 @@ struct spamm_matrix {
     void* tiles = nullptr;
     double* norms = nullptr;
     int8_t* texp = nullptr;
+    uint16_t* split = nullptr;   // split 16-bit tiles (hi, then lo), made on demand
+    int split_kind = -1;         // kSplitF16 / kSplitBF16 of the current split
+    uint64_t gen = 1;            // bumped whenever the tiles are written
+    uint64_t split_gen = 0;      // gen the split was made from
     int64_t lvl_off[spamm::kMaxLevels] = {};
     int32_t lvl_m[spamm::kMaxLevels] = {};
     int64_t norms_total = 0;
@@ -122,6 +138,9 @@ hipError_t launch_clear_nonempty(unsigned long long* p, int count, const int* ac
 hipError_t launch_to_dense(const spamm_matrix* M, void* out, int64_t ldo, hipStream_t s);
 hipError_t launch_diff_norms(const spamm_matrix* X, const spamm_matrix* Y, double* d_out, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s);
+
+// split.hip: hi/lo 16-bit copies of an FP32 handle's tiles into M->split
+hipError_t launch_split(const spamm_matrix* M, int kind, const int* active, hipStream_t s);
 
 // launchers (cull.hip) ----------------------------------------------------------
 struct CullPlan {
