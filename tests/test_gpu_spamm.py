@@ -69,6 +69,12 @@ CASES = [
     (450, 32, 1e-5, "f32", "alg"),
     (450, 32, 1e-5, "bf16x3", "alg"),
     (2048, 64, 1e-7, "f32", "alg"),
+    # odd tile counts: the last row and column of 2 x 2 tile blocks are partial
+    (900, 64, 1e-6, "f16x3", "alg"),
+    (900, 64, 1e-6, "f32", "alg"),
+    (900, 64, 1e-6, "f64", "alg"),
+    (700, 64, 1e-6, "f64", "exp"),
+    (130, 64, 1e-6, "bf16x3", "alg"),
 ]
 
 
