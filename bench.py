@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--tau", type=float, default=None,
                     help="use this tau for every precision instead of the sweep (profiling runs)")
+    ap.add_argument("--presplit", action="store_true",
+                    help="16-bit leaves: build the operand with its split hi/lo tiles (spamm_build_ex) "
+                         "instead of splitting on the fly in the leaf kernel")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 256 MiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--workload", default="algebraic8192",
@@ -186,13 +189,16 @@ def main():
             continue
         tau, err, T = d["found"]
         C = d["handle"]
+        # a step builds the operand and multiplies (with --presplit the build
+        # also writes the split hi/lo tiles the 16-bit leaves then read)
+        bp = p if args.presplit else None
         for _ in range(args.warmup):
-            sp.build(A_d, b, out=A)
+            sp.build(A_d, b, out=A, prec=bp)
             sp.multiply(A, A, tau, p, out=C)
         torch.cuda.synchronize()
         ev0.record()
         for _ in range(args.steps):
-            sp.build(A_d, b, out=A)
+            sp.build(A_d, b, out=A, prec=bp)
             sp.multiply(A, A, tau, p, out=C)
         ev1.record()
         torch.cuda.synchronize()

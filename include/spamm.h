@@ -129,6 +129,21 @@ typedef struct {
 spamm_status spamm_build(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf,
                          void* stream, spamm_matrix** out);
 
+/* spamm_build for operands of products with leaf precision `prec`.  For the
+ * 16-bit precisions (FP32 input only) the same pass also writes the handle's
+ * split tiles: x = hi + lo per element in FP16 (tile scaled by a power of two
+ * that puts its largest |x| in [2^14, 2^15)) or BF16, rounded to nearest,
+ * which the 16-bit leaf products read (4 more bytes of device memory per tile
+ * element, owned by the handle) instead of splitting each operand tile again
+ * for every product that reads it; worth it when an operand feeds several
+ * products.  Products of operands without current split tiles (built by
+ * spamm_build, rebuilt since, or products of other calls) split on the fly;
+ * the results are the same bits either way.  For the FP32 and FP64
+ * precisions it is spamm_build.  Errors: as spamm_build;
+ * EINVAL for an unknown prec; EUNSUPPORTED for a 16-bit prec with FP64 input. */
+spamm_status spamm_build_ex(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf,
+                            spamm_leaf_prec prec, void* stream, spamm_matrix** out);
+
 /* ------------------------------------------------------------------ multiply */
 
 /* C ~= A B by Eq. (4) with absolute threshold tau.
@@ -154,9 +169,7 @@ typedef struct {
     double ms_cull;    /* counter reset, mask clear and every cull tier      */
     double ms_leaf;    /* the leaf-product launch (incl. its epilogue)       */
     double ms_norms;   /* upper tiers of the result's norm pyramid           */
-    double ms_total;   /* first to last event (split + cull + leaf + norms)  */
-    double ms_split;   /* 16-bit leaves: hi/lo split of operands whose tiles
-                          changed since their last split (0 otherwise)       */
+    double ms_total;   /* first to last event                                */
 } spamm_timing;
 
 /* spamm_multiply with phase timing: same arguments and result; records HIP

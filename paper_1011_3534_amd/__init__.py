@@ -78,7 +78,7 @@ class TauInfo(ctypes.Structure):
 
 class Timing(ctypes.Structure):
     _fields_ = [("ms_cull", ctypes.c_double), ("ms_leaf", ctypes.c_double), ("ms_norms", ctypes.c_double),
-                ("ms_total", ctypes.c_double), ("ms_split", ctypes.c_double)]
+                ("ms_total", ctypes.c_double)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -123,6 +123,7 @@ def lib():
     PP = ctypes.POINTER(_VP)
     sig = {
         "spamm_build": ([_VP, i64, i64, i32, i32, _VP, PP], i32),
+        "spamm_build_ex": ([_VP, i64, i64, i32, i32, i32, _VP, PP], i32),
         "spamm_multiply": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Stats)], i32),
         "spamm_multiply_timed": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Timing)], i32),
         "spamm_multiply_batched": ([i32, PP, PP, ctypes.POINTER(dbl), i32, ctypes.POINTER(Tune), _VP, PP,
@@ -264,10 +265,12 @@ class Matrix:
         return np.sort(keys[:cnt.value])
 
 
-def build(a, leaf: int, out: Matrix | None = None, stream=None) -> Matrix:
+def build(a, leaf: int, out: Matrix | None = None, stream=None, prec: str | None = None) -> Matrix:
     """Quadtree of a dense CUDA tensor (float32 or float64, row-major).
 
-    With out given (same n, leaf, dtype) the handle is rebuilt in place."""
+    With out given (same n, leaf, dtype) the handle is rebuilt in place.  With
+    prec naming a 16-bit leaf precision the same pass also writes the split
+    hi/lo tiles those products read (spamm_build_ex)."""
     import torch
     if not (a.is_cuda and a.dim() == 2 and a.shape[0] == a.shape[1]):
         raise ValueError("build expects a square CUDA tensor")
@@ -276,8 +279,13 @@ def build(a, leaf: int, out: Matrix | None = None, stream=None) -> Matrix:
     if a.stride(1) != 1:
         raise ValueError("build expects unit column stride")
     h = ctypes.c_void_p(out.handle.value if out is not None else None)
-    _check(lib().spamm_build(ctypes.c_void_p(a.data_ptr()), a.shape[0], a.stride(0),
-                             0 if a.dtype == torch.float64 else 1, leaf, _stream(stream), ctypes.byref(h)))
+    dt = 0 if a.dtype == torch.float64 else 1
+    if prec is None:
+        _check(lib().spamm_build(ctypes.c_void_p(a.data_ptr()), a.shape[0], a.stride(0), dt, leaf,
+                                 _stream(stream), ctypes.byref(h)))
+    else:
+        _check(lib().spamm_build_ex(ctypes.c_void_p(a.data_ptr()), a.shape[0], a.stride(0), dt, leaf, LEAF[prec],
+                                    _stream(stream), ctypes.byref(h)))
     return out if out is not None else Matrix(h)
 
 

@@ -182,7 +182,7 @@ ProdDesc make_desc(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C
     d.eA = A->texp;
     d.eB = B->texp;
     d.eC = C->texp;
-    d.A16 = A->split;
+    d.A16 = A->split;  // read only when current (LeafPlan::presplit)
     d.B16 = B->split;
     d.mask = C->ps->mask;
     d.nonempty = nonempty_ctr(C->ps->ctr);
@@ -263,18 +263,9 @@ static spamm_status alloc_split(const spamm_matrix* Mc, hipStream_t s) {
     return SPAMM_OK;
 }
 
-// Bring M's split tiles in line with its current tiles (always re-split when
-// forced, e.g. inside a captured graph whose products rewrite the tiles).
-static spamm_status ensure_split(const spamm_matrix* Mc, int kind, hipStream_t s, const int* active, bool force) {
-    auto* M = const_cast<spamm_matrix*>(Mc);
-    spamm_status r = alloc_split(M, s);
-    if (r != SPAMM_OK) return r;
-    if (force || M->split_kind != kind || M->split_gen != M->gen) {
-        SPAMM_HIP(launch_split(M, kind, active, s));
-        M->split_kind = kind;
-        M->split_gen = M->gen;
-    }
-    return SPAMM_OK;
+// M's split tiles hold the split of kind `kind` of its current tiles.
+static bool split_current(const spamm_matrix* M, int kind) {
+    return kind >= 0 && M->split && M->split_kind == kind && M->split_gen == M->gen;
 }
 
 // Shared by multiply and SP2: cull + leaf products + C pyramid, all enqueued.
@@ -283,14 +274,11 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
                              const int* d_active, ProdDesc* d_desc_override) {
     ProductScratch* ps = C->ps;
     ProdDesc* d_desc = d_desc_override;
-    if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[4], s));
+    // 16-bit leaves read the operands' split tiles when both are current
+    // (spamm_build_ex, or SP2, which maintains them); otherwise they split
+    // the FP32 tiles on the fly
     const int kind = split_kind(prec);
-    if (kind >= 0 && !sp2) {
-        // (SP2 splits its operands itself, inside the captured iteration)
-        spamm_status r = ensure_split(A, kind, s, d_active, false);
-        if (r == SPAMM_OK && B != A) r = ensure_split(B, kind, s, d_active, false);
-        if (r != SPAMM_OK) return r;
-    }
+    const bool presplit = split_current(A, kind) && split_current(B, kind);
     C->gen++;
     if (!d_desc) {
         ProdDesc d = make_desc(A, B, C, tau);
@@ -320,6 +308,7 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
     lp.sp2 = sp2;
     lp.d_branch = d_branch;
     lp.d_active = d_active;
+    lp.presplit = presplit;
     if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[1], s));
     SPAMM_HIP(launch_leaf_typed(d_desc, lp, A->dt == SPAMM_F64, s));
     if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[2], s));
@@ -334,14 +323,18 @@ using namespace spamm;
 
 extern "C" {
 
-spamm_status spamm_build(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf, void* stream,
-                         spamm_matrix** out) {
+spamm_status spamm_build_ex(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf,
+                            spamm_leaf_prec prec, void* stream, spamm_matrix** out) {
     if (!out) return set_error(SPAMM_EINVAL, "out is null");
     if (!dev_a) return set_error(SPAMM_EINVAL, "dev_a is null");
     if (n < 1 || lda < n) return set_error(SPAMM_EINVAL, "need n >= 1 and lda >= n");
     if (dt != SPAMM_F32 && dt != SPAMM_F64) return set_error(SPAMM_EINVAL, "unknown dtype");
     if (!leaf_ok(leaf)) return set_error(SPAMM_EINVAL, "leaf must be 32, 64 or 128");
+    if ((int)prec < 0 || (int)prec > 5) return set_error(SPAMM_EINVAL, "unknown leaf precision");
     if (ceil_div(n, leaf) > kMaxNb) return set_error(SPAMM_EINVAL, "n / leaf exceeds 2^19 leaves");
+    const int kind = split_kind(prec);
+    if (kind >= 0 && dt != SPAMM_F32)
+        return set_error(SPAMM_EUNSUPPORTED, "16-bit leaf precisions take FP32 tiles");
     hipStream_t s = (hipStream_t)stream;
     spamm_matrix* M = *out;
     const bool fresh = M == nullptr;
@@ -356,18 +349,31 @@ spamm_status spamm_build(const void* dev_a, int64_t n, int64_t lda, spamm_dtype 
     } else if (M->n != n || M->b != leaf || M->dt != dt) {
         return set_error(SPAMM_EINVAL, "existing handle differs in n, leaf or dtype");
     }
+    if (kind >= 0 && (st = alloc_split(M, s)) != SPAMM_OK) {
+        if (fresh) release(M);
+        return st;
+    }
     M->last_stream = s;
     M->gen++;
     hipError_t e = hipMemsetAsync(status_word(M), 0, 4, s);
-    if (e == hipSuccess) e = launch_pack_norm(dev_a, n, lda, dt, M, status_word(M), s);
+    if (e == hipSuccess) e = launch_pack_norm(dev_a, n, lda, dt, M, status_word(M), kind, s);
     if (e == hipSuccess) e = launch_upper_norms(M, s, nullptr);
     if (e != hipSuccess) {
         st = hip_error(e, "spamm_build kernels");
         if (fresh) release(M);
         return st;
     }
+    if (kind >= 0) {
+        M->split_kind = kind;
+        M->split_gen = M->gen;
+    }
     *out = M;
     return SPAMM_OK;
+}
+
+spamm_status spamm_build(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf, void* stream,
+                         spamm_matrix** out) {
+    return spamm_build_ex(dev_a, n, lda, dt, leaf, dt == SPAMM_F64 ? SPAMM_LEAF_F64 : SPAMM_LEAF_F32, stream, out);
 }
 
 spamm_status spamm_multiply(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,
@@ -408,7 +414,7 @@ spamm_status spamm_multiply(const spamm_matrix* A, const spamm_matrix* B, double
 spamm_status spamm_multiply_timed(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,
                                   void* stream, spamm_matrix** C, spamm_timing* t) {
     if (!t) return set_error(SPAMM_EINVAL, "timing output is null");
-    static thread_local hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    static thread_local hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (!ev[0])
         for (auto& e : ev) SPAMM_HIP(hipEventCreate(&e));
     t_phase = ev;
@@ -416,17 +422,15 @@ spamm_status spamm_multiply_timed(const spamm_matrix* A, const spamm_matrix* B, 
     t_phase = nullptr;
     if (r != SPAMM_OK) return r;
     SPAMM_HIP(hipEventSynchronize(ev[3]));
-    float a = 0, b = 0, c = 0, d = 0, sp = 0;
-    SPAMM_HIP(hipEventElapsedTime(&sp, ev[4], ev[0]));
+    float a = 0, b = 0, c = 0, d = 0;
     SPAMM_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
     SPAMM_HIP(hipEventElapsedTime(&b, ev[1], ev[2]));
     SPAMM_HIP(hipEventElapsedTime(&c, ev[2], ev[3]));
-    SPAMM_HIP(hipEventElapsedTime(&d, ev[4], ev[3]));
+    SPAMM_HIP(hipEventElapsedTime(&d, ev[0], ev[3]));
     t->ms_cull = a;
     t->ms_leaf = b;
     t->ms_norms = c;
     t->ms_total = d;
-    t->ms_split = sp;
     return SPAMM_OK;
 }
 
@@ -580,14 +584,8 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
     int64_t total = 0, cap = 1, items[kMaxLevels] = {};
     int Lmax = 0, maxc = 1;
     const int kind = split_kind(prec);
-    for (int m = 0; m < count && kind >= 0 && r == SPAMM_OK; ++m) {
-        r = ensure_split(A[m], kind, s, nullptr, false);
-        if (r == SPAMM_OK) r = ensure_split(B[m], kind, s, nullptr, false);
-    }
-    if (r != SPAMM_OK) {
-        release_fresh();
-        return r;
-    }
+    bool presplit = kind >= 0;
+    for (int m = 0; m < count; ++m) presplit = presplit && split_current(A[m], kind) && split_current(B[m], kind);
     static thread_local std::vector<ProdDesc> hd;
     hd.assign(count, ProdDesc{});
     for (int m = 0; m < count; ++m) {
@@ -634,6 +632,7 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
     lp.sp2 = 0;
     lp.d_branch = nullptr;
     lp.d_active = nullptr;
+    lp.presplit = presplit;
     if (sched == SPAMM_SCHED_LPT) {
         lp.order = (uint32_t*)(ws + o_ord);
         lp.queue = (unsigned long long*)(ws + o_q);
@@ -765,6 +764,11 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
         ProdDesc d = make_desc(src, src, dst, tau);
         d.sp2_part = part;
         d.X = src->tiles;
+        if (kind >= 0) {
+            // the epilogue writes X_{m+1}'s split tiles for the next step
+            d.C16 = dst->split;
+            d.c16_kind = kind;
+        }
         dst->ps->host_desc = d;
         dst->ps->desc_valid = false;  // differs from any plain product's descriptor
         e = hipMemcpyAsync(dst->ps->desc, &dst->ps->host_desc, sizeof d, hipMemcpyHostToDevice, s);
@@ -779,11 +783,6 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
         spamm_matrix* src = X[m & 1];
         spamm_matrix* dst = X[(m + 1) & 1];
         r = enqueue_product(src, src, dst, tau, prec, cs, 0, 1, d_branch, d_active, dst->ps->desc);
-        if (r == SPAMM_OK && kind >= 0) {
-            // the next step reads X_{m+1} through its split tiles
-            e = launch_split(dst, kind, d_active, cs);
-            if (e != hipSuccess) r = hip_error(e, "sp2 split launch");
-        }
         if (r == SPAMM_OK) {
             e = launch_sp2_finalize(part, nb, &dst->ps->ctr->survivors[0][0], st, m, cs);
             if (e != hipSuccess) r = hip_error(e, "sp2 finalize launch");

@@ -45,11 +45,12 @@ struct Geo {
     static constexpr int SMEM = (2 * BUF_BYTES > C_BYTES) ? 2 * BUF_BYTES : C_BYTES;
 };
 
-// Kept K of one segment of a tile's mask (four words), with the exponent that
-// undoes the FP16 scales of A_IK and B_KJ on the product.
+// Kept K of one segment of a tile's mask (four words), with the FP16 scale
+// exponents of A_IK and B_KJ.
 struct KList {
     int k[256];
-    int16_t un[256];
+    int16_t sa[256];  // FP16: A_IK is scaled by 2^sa, B_KJ by 2^sb
+    int16_t sb[256];
 };
 
 // Register stage of one k-chunk, FP32/FP64 leaves: float4/double2-sized units
@@ -205,6 +206,92 @@ __device__ inline void stage16_store(const Stage16<B, P>& st, char* buf, int tid
     }
 }
 
+// Register stage of one k-chunk, 16-bit leaves split on the fly from FP32
+// tiles (operands without split tiles): A units are 8 consecutive k of one
+// row, B units 8 consecutive k of one column (8 loads, coalesced over c).
+template <int B, int P>
+struct Stage16c {
+    using G = Geo<B, P>;
+    static constexpr int KC = G::KC;
+    static constexpr int NU = B * KC / 8;
+    static constexpr int U = (NU + 255) / 256;
+    static constexpr bool PARTIAL = (NU % 256) != 0;
+    float a[U][8];
+    float b[U][8];
+};
+
+template <int B, int P>
+__device__ inline void stage16c_load(Stage16c<B, P>& st, __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rb,
+                                     int tid) {
+    using S = Stage16c<B, P>;
+    constexpr int KC = S::KC;
+#pragma unroll
+    for (int u = 0; u < S::U; ++u) {
+        const int unit = tid + u * 256;
+        if (S::PARTIAL && unit >= S::NU) break;
+        const int r = unit / (KC / 8), k = (unit % (KC / 8)) * 8;
+        const f32x4 v0 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, (r * B + k) * 4, 0, 0));
+        const f32x4 v1 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, (r * B + k + 4) * 4, 0, 0));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            st.a[u][j] = v0[j];
+            st.a[u][4 + j] = v1[j];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < S::U; ++u) {
+        const int unit = tid + u * 256;
+        if (S::PARTIAL && unit >= S::NU) break;
+        const int c = unit % B, k = (unit / B) * 8;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            st.b[u][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, ((k + j) * B + c) * 4, 0, 0));
+    }
+}
+
+// Split (after the FP16 tile scales sa, sb) into the hi (+ lo) LDS arrays.
+template <int B, int P>
+__device__ inline void stage16c_store(const Stage16c<B, P>& st, char* buf, int tid, int sa, int sb) {
+    using G = Geo<B, P>;
+    using S = Stage16c<B, P>;
+    constexpr int KC = G::KC;
+    constexpr int KIND = isf16(P) ? kSplitF16 : kSplitBF16;
+    uint16_t* As = reinterpret_cast<uint16_t*>(buf);
+    uint16_t* Bs = As + G::NARR * G::A_ELEMS;
+    auto put = [&](const float* x, int s, uint16_t* dh, uint16_t* dl) {
+        uint16_t h[8], l[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) split16<KIND>(isf16(P) ? ldexpf(x[j], s) : x[j], h[j], l[j]);
+        u32x4 vh, vl;
+        vh.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+        vh.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+        vh.z = (uint32_t)h[4] | ((uint32_t)h[5] << 16);
+        vh.w = (uint32_t)h[6] | ((uint32_t)h[7] << 16);
+        *reinterpret_cast<u32x4*>(dh) = vh;
+        if constexpr (isx3(P)) {
+            vl.x = (uint32_t)l[0] | ((uint32_t)l[1] << 16);
+            vl.y = (uint32_t)l[2] | ((uint32_t)l[3] << 16);
+            vl.z = (uint32_t)l[4] | ((uint32_t)l[5] << 16);
+            vl.w = (uint32_t)l[6] | ((uint32_t)l[7] << 16);
+            *reinterpret_cast<u32x4*>(dl) = vl;
+        }
+    };
+#pragma unroll
+    for (int u = 0; u < S::U; ++u) {
+        const int unit = tid + u * 256;
+        if (S::PARTIAL && unit >= S::NU) break;
+        const int r = unit / (KC / 8), k = (unit % (KC / 8)) * 8;
+        put(st.a[u], sa, As + r * G::SA + k, As + G::A_ELEMS + r * G::SA + k);
+    }
+#pragma unroll
+    for (int u = 0; u < S::U; ++u) {
+        const int unit = tid + u * 256;
+        if (S::PARTIAL && unit >= S::NU) break;
+        const int c = unit % B, k = (unit / B) * 8;
+        put(st.b[u], sb, Bs + c * G::SB + k, Bs + G::B_ELEMS + c * G::SB + k);
+    }
+}
+
 // MFMA accumulation of one k-chunk held in LDS.
 template <int B, int P, typename Acc>
 __device__ inline void chunk_mma(const char* buf, Acc (&acc)[Geo<B, P>::R][Geo<B, P>::R], int lane, int wr, int wc) {
@@ -276,7 +363,7 @@ __device__ inline void chunk_mma(const char* buf, Acc (&acc)[Geo<B, P>::R][Geo<B
 // One C tile from its kept K to its stored values and norm.  t is a global
 // schedule position (blocked = true: panel/block order inside each product)
 // or a global tile index (blocked = false: row-major).
-template <int B, int P, typename TA, typename TC, bool SP2>
+template <int B, int P, typename TA, typename TC, bool SP2, bool PRESPLIT>
 __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int nprod, int64_t t, char* smem,
                                           KList* kl, double (*red)[4], const int* __restrict__ branch,
                                           bool blocked) {
@@ -335,8 +422,10 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
                 const int pos = base + __popcll(mine & ((1ull << lane) - 1ull));
                 const int k = (w0 + w) * 64 + lane;
                 kl->k[pos] = k;
-                if constexpr (isf16(P))
-                    kl->un[pos] = (int16_t)-(f16_shift(d.eA[(int64_t)I * nb + k]) + f16_shift(d.eB[(int64_t)k * nb + J]));
+                if constexpr (isf16(P)) {
+                    kl->sa[pos] = (int16_t)f16_shift(d.eA[(int64_t)I * nb + k]);
+                    kl->sb[pos] = (int16_t)f16_shift(d.eB[(int64_t)k * nb + J]);
+                }
             }
         }
         __syncthreads();
@@ -352,7 +441,7 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             if constexpr (P != kF64) {
                 chunk_mma<B, P, Acc>(smem + bf * G::BUF_BYTES, part, lane, wr, wc);
                 if (t % NCH == NCH - 1) {
-                    const int un = isf16(P) ? (int)kl->un[t / NCH] : 0;
+                    const int un = isf16(P) ? -((int)kl->sa[t / NCH] + (int)kl->sb[t / NCH]) : 0;
 #pragma unroll
                     for (int i = 0; i < R; ++i)
 #pragma unroll
@@ -372,7 +461,8 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         };
         // Two register stages keep two chunks of loads in flight while LDS
         // double-buffers the chunk under MFMA and the next one.
-        using St = typename std::conditional<is16(P), Stage16<B, P>, Stage<B, P, TA>>::type;
+        using St16 = typename std::conditional<PRESPLIT, Stage16<B, P>, Stage16c<B, P>>::type;
+        using St = typename std::conditional<is16(P), St16, Stage<B, P, TA>>::type;
         // Loads are issued for every step t < T + 3 (those past the end with
         // empty resources, which load nothing), so that every path through
         // the loop has the same loads in flight and the waits before each LDS
@@ -383,7 +473,12 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             const int k = __builtin_amdgcn_readfirstlane(kl->k[tt / NCH]);
             const int ch = tt % NCH;
             const int64_t ta = ((int64_t)I * nb + k) * TS, tb = ((int64_t)k * nb + J) * TS;
-            if constexpr (is16(P)) {
+            if constexpr (is16(P) && !PRESPLIT) {
+                const uint32_t na = live ? (uint32_t)((TS - ch * KC) * 4) : 0u;
+                const uint32_t nbb = live ? (uint32_t)((TS - ch * KC * B) * 4) : 0u;
+                stage16c_load<B, P>(st, rsrc((const float*)d.A + ta + ch * KC, na),
+                                    rsrc((const float*)d.B + tb + (int64_t)ch * KC * B, nbb), tid);
+            } else if constexpr (is16(P)) {
                 const uint32_t na = live ? (uint32_t)((TS - ch * KC) * 2) : 0u;
                 const uint32_t nbb = live ? (uint32_t)((TS - ch * KC * B) * 2) : 0u;
                 __amdgpu_buffer_rsrc_t ra[2], rb[2];
@@ -400,9 +495,17 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
                                      rsrc((const TA*)d.B + tb + (int64_t)ch * KC * B, nbb), tid);
             }
         };
-        auto sto = [&](const St& st, int bf) {
-            if constexpr (is16(P)) stage16_store<B, P>(st, smem + bf * G::BUF_BYTES, tid);
-            else stage_store<B, P, TA>(st, smem + bf * G::BUF_BYTES, tid);
+        // (step t's FP16 scales apply when splitting on the fly)
+        auto sto = [&](const St& st, int bf, int t) {
+            if constexpr (is16(P) && !PRESPLIT) {
+                const int e = t / NCH;
+                stage16c_store<B, P>(st, smem + bf * G::BUF_BYTES, tid, isf16(P) ? (int)kl->sa[e] : 0,
+                                     isf16(P) ? (int)kl->sb[e] : 0);
+            } else if constexpr (is16(P)) {
+                stage16_store<B, P>(st, smem + bf * G::BUF_BYTES, tid);
+            } else {
+                stage_store<B, P, TA>(st, smem + bf * G::BUF_BYTES, tid);
+            }
         };
         // Invariant at the top of each half step: LDS buffer `buf` holds step
         // t, one register stage holds (or is receiving) step t + 1 and the
@@ -411,7 +514,7 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         // for other values) and every load has two steps to arrive.
         St s0, s1;
         ld(s0, 0);
-        sto(s0, 0);
+        sto(s0, 0, 0);
         __syncthreads();
         ld(s0, 1);
         __builtin_amdgcn_sched_barrier(0);  // stage s0 is the older one on every path
@@ -426,7 +529,7 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             compute(buf, t);
             __builtin_amdgcn_sched_barrier(0);
             if (t + 1 >= T) break;
-            sto(s0, buf ^ 1);
+            sto(s0, buf ^ 1, t + 1);
             __syncthreads();
             buf ^= 1;
             if (t + 2 >= T) {
@@ -437,7 +540,7 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             __builtin_amdgcn_sched_barrier(0);
             compute(buf, t + 1);
             __builtin_amdgcn_sched_barrier(0);
-            sto(s1, buf ^ 1);
+            sto(s1, buf ^ 1, t + 2);
             __syncthreads();
             buf ^= 1;
             ld(s1, t + 4);
@@ -559,13 +662,41 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         }
         d.eC[local] = (int8_t)e;
         if constexpr (SP2) d.sp2_part[local] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        red[0][0] = (double)e;
     }
     __syncthreads();  // red and smem are reused by the next tile of a persistent block
+    if constexpr (P != kF64) {
+        if (d.C16) {
+            // split hi/lo tiles of the stored values (the next product reads
+            // them), with the tile exponent just computed
+            const int sh = d.c16_kind == kSplitF16 ? f16_shift((int)red[0][0]) : 0;
+            GLOBAL uint16_t* hi = (GLOBAL uint16_t*)d.C16 + local * TS;
+            GLOBAL uint16_t* lo = hi + lo16;
+            for (int u = tid; u < B * B / 4; u += 256) {
+                const int r = u / (B / 4), c = (u % (B / 4)) * 4;
+                uint16_t h[4], l[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float x = (float)Cs[r * G::SC + c + j];
+                    if (d.c16_kind == kSplitF16) split16<kSplitF16>(ldexpf(x, sh), h[j], l[j]);
+                    else split16<kSplitBF16>(x, h[j], l[j]);
+                }
+                u32x2 vh, vl;
+                vh.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+                vh.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+                vl.x = (uint32_t)l[0] | ((uint32_t)l[1] << 16);
+                vl.y = (uint32_t)l[2] | ((uint32_t)l[3] << 16);
+                *(GLOBAL u32x2*)(hi + r * B + c) = vh;
+                *(GLOBAL u32x2*)(lo + r * B + c) = vl;
+            }
+            __syncthreads();
+        }
+    }
 }
 
 // Static schedule: one block per tile; block x runs on XCD x mod 8 and takes
 // tile (x mod 8) * chunk + x / 8, so each XCD walks a contiguous tile range.
-template <int B, int P, typename TA, typename TC, bool SP2>
+template <int B, int P, typename TA, typename TC, bool SP2, bool PS>
 __global__ void __launch_bounds__(256) k_leaf(const ProdDesc* __restrict__ desc, int nprod, int64_t total,
                                               int64_t chunk, const int* __restrict__ branch,
                                               const int* __restrict__ active) {
@@ -576,13 +707,13 @@ __global__ void __launch_bounds__(256) k_leaf(const ProdDesc* __restrict__ desc,
     const int64_t x = blockIdx.x;
     const int64_t t = (x & 7) * chunk + (x >> 3);
     if (t >= total) return;
-    leaf_tile<B, P, TA, TC, SP2>(desc, nprod, t, smem, &kl, red, branch, true);
+    leaf_tile<B, P, TA, TC, SP2, PS>(desc, nprod, t, smem, &kl, red, branch, true);
 }
 
 // Persistent schedule: resident blocks pull positions from a queue counter
 // and process tile order[pos] (largest kept-K count first); every block
 // leaves once the queue passes `total`.
-template <int B, int P, typename TA, typename TC, bool SP2>
+template <int B, int P, typename TA, typename TC, bool SP2, bool PS>
 __global__ void __launch_bounds__(256) k_leaf_queue(const ProdDesc* __restrict__ desc, int nprod, int64_t total,
                                                     const uint32_t* __restrict__ order,
                                                     unsigned long long* __restrict__ queue,
@@ -598,28 +729,37 @@ __global__ void __launch_bounds__(256) k_leaf_queue(const ProdDesc* __restrict__
         const long long pos = s_pos;
         __syncthreads();
         if (pos >= total) break;
-        leaf_tile<B, P, TA, TC, SP2>(desc, nprod, order ? (int64_t)order[pos] : (int64_t)pos, smem, &kl, red, branch,
-                                     false);
+        leaf_tile<B, P, TA, TC, SP2, PS>(desc, nprod, order ? (int64_t)order[pos] : (int64_t)pos, smem, &kl, red,
+                                         branch, false);
     }
 }
 
-template <int B, int P, typename TA, typename TC, bool SP2>
+template <int B, int P, typename TA, typename TC, bool SP2, bool PS = false>
 hipError_t go(const ProdDesc* d_desc, const LeafPlan& p, hipStream_t s) {
     if (p.queue) {
         int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_leaf_queue<B, P, TA, TC, SP2>, 256, 0);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_leaf_queue<B, P, TA, TC, SP2, PS>, 256, 0);
         if (e != hipSuccess || per_cu < 1) per_cu = 1;
         int64_t grid = (int64_t)num_cus() * per_cu;
         if (grid > p.total_tiles) grid = p.total_tiles < 1 ? 1 : p.total_tiles;
-        hipLaunchKernelGGL((k_leaf_queue<B, P, TA, TC, SP2>), dim3((unsigned)grid), dim3(256), 0, s, d_desc, p.count,
+        hipLaunchKernelGGL((k_leaf_queue<B, P, TA, TC, SP2, PS>), dim3((unsigned)grid), dim3(256), 0, s, d_desc, p.count,
                            p.total_tiles, p.order, p.queue, p.d_branch, p.d_active);
         return hipGetLastError();
     }
     const int64_t chunk = (p.total_tiles + 7) / 8;
     const int64_t grid = chunk * 8;
-    hipLaunchKernelGGL((k_leaf<B, P, TA, TC, SP2>), dim3((unsigned)grid), dim3(256), 0, s, d_desc, p.count,
+    hipLaunchKernelGGL((k_leaf<B, P, TA, TC, SP2, PS>), dim3((unsigned)grid), dim3(256), 0, s, d_desc, p.count,
                        p.total_tiles, chunk, p.d_branch, p.d_active);
     return hipGetLastError();
+}
+
+// 16-bit leaves: operands with split tiles (always in SP2, whose epilogue
+// writes them) or split on the fly from the FP32 tiles
+template <int B, int P>
+hipError_t go16(const ProdDesc* d_desc, const LeafPlan& p, hipStream_t s) {
+    if (p.sp2) return go<B, P, float, float, true, true>(d_desc, p, s);
+    if (p.presplit) return go<B, P, float, float, false, true>(d_desc, p, s);
+    return go<B, P, float, float, false, false>(d_desc, p, s);
 }
 
 template <int B>
@@ -630,16 +770,10 @@ hipError_t dispatch_b(const ProdDesc* d_desc, const LeafPlan& p, bool a_f64, hip
             return go<B, kF64, float, double, false>(d_desc, p, s);
         case SPAMM_LEAF_F32:
             return p.sp2 ? go<B, kF32, float, float, true>(d_desc, p, s) : go<B, kF32, float, float, false>(d_desc, p, s);
-        case SPAMM_LEAF_BF16:
-            return p.sp2 ? go<B, kBF16, float, float, true>(d_desc, p, s) : go<B, kBF16, float, float, false>(d_desc, p, s);
-        case SPAMM_LEAF_BF16X3:
-            return p.sp2 ? go<B, kBF16X3, float, float, true>(d_desc, p, s)
-                         : go<B, kBF16X3, float, float, false>(d_desc, p, s);
-        case SPAMM_LEAF_F16:
-            return p.sp2 ? go<B, kF16, float, float, true>(d_desc, p, s) : go<B, kF16, float, float, false>(d_desc, p, s);
-        case SPAMM_LEAF_F16X3:
-            return p.sp2 ? go<B, kF16X3, float, float, true>(d_desc, p, s)
-                         : go<B, kF16X3, float, float, false>(d_desc, p, s);
+        case SPAMM_LEAF_BF16: return go16<B, kBF16>(d_desc, p, s);
+        case SPAMM_LEAF_BF16X3: return go16<B, kBF16X3>(d_desc, p, s);
+        case SPAMM_LEAF_F16: return go16<B, kF16>(d_desc, p, s);
+        case SPAMM_LEAF_F16X3: return go16<B, kF16X3>(d_desc, p, s);
     }
     return hipErrorInvalidValue;
 }

@@ -20,6 +20,7 @@ constexpr bool isx3(int k) { return k == kBF16X3 || k == kF16X3; }
 constexpr bool isf16(int k) { return k == kF16 || k == kF16X3; }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // Buffer resource over `bytes` bytes from `base` (uniform).  A load whose
 // offset lies outside [0, bytes) returns zero without a memory access, so a

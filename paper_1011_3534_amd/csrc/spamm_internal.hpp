@@ -38,6 +38,21 @@ __host__ __device__ inline int f16_shift(int e) { return kF16Bias - (e == -128 ?
 constexpr int kSplitF16 = 0;   // hi = fp16(x 2^s), lo = fp16(x 2^s - hi), s = f16_shift(tile exponent)
 constexpr int kSplitBF16 = 1;  // hi = bf16(x), lo = bf16(x - hi)
 
+// x = hi + lo + (rounding of lo), both halves rounded to nearest even; x is
+// the (FP16: already scaled) FP32 value.
+template <int KIND>
+__device__ inline void split16(float x, uint16_t& hi, uint16_t& lo) {
+    if constexpr (KIND == kSplitF16) {
+        const _Float16 h = (_Float16)x;
+        hi = __builtin_bit_cast(uint16_t, h);
+        lo = __builtin_bit_cast(uint16_t, (_Float16)(x - (float)h));
+    } else {
+        const __bf16 h = (__bf16)x;
+        hi = __builtin_bit_cast(uint16_t, h);
+        lo = __builtin_bit_cast(uint16_t, (__bf16)(x - (float)h));
+    }
+}
+
 // Per-product descriptor read by the cull and leaf kernels.  Operand and
 // result pyramids share the same tier shapes (equal n and leaf).
 struct ProdDesc {
@@ -55,6 +70,7 @@ struct ProdDesc {
     const void* X;            // SP2: the operand tiles X_m (== A == B)
     const uint16_t* A16;      // split 16-bit tiles of A and B: hi tiles, then lo
     const uint16_t* B16;      //   tiles at +nb^2 b^2 elements (16-bit leaves only)
+    uint16_t* C16;            // optional: split tiles of C written by the epilogue
     unsigned long long* nonempty;  // count of C tiles with at least one kept product
     int64_t lvl_off[kMaxLevels];
     int32_t lvl_m[kMaxLevels];
@@ -62,7 +78,7 @@ struct ProdDesc {
     double tau2;
     int32_t nb, L, W;
     int32_t a_f64, b_f64;     // operand tile element types (1 = FP64)
-    int32_t pad_;
+    int32_t c16_kind;         // kSplitF16 / kSplitBF16 when C16 is set
 };
 
 // Device-side counters of one product launch sequence.
@@ -131,8 +147,10 @@ void dev_free(spamm_matrix* owner, void* p, hipStream_t s);
 int num_cus();
 
 // launchers (norms.hip) ---------------------------------------------------------
+// split_kind >= 0 (FP32 input, M->split allocated): the same pass also writes
+// the split 16-bit tiles of that kind.
 hipError_t launch_pack_norm(const void* a, int64_t n, int64_t lda, spamm_dtype dt, spamm_matrix* M,
-                            unsigned* status, hipStream_t s);
+                            unsigned* status, int split_kind, hipStream_t s);
 hipError_t launch_upper_norms(spamm_matrix* M, hipStream_t s, const int* active);
 hipError_t launch_clear_nonempty(unsigned long long* p, int count, const int* active, hipStream_t s);
 hipError_t launch_to_dense(const spamm_matrix* M, void* out, int64_t ldo, hipStream_t s);
@@ -167,6 +185,7 @@ struct LeafPlan {
     const int* d_active;    // SP2: device flag, 0 = skip (converged)
     const uint32_t* order = nullptr;       // persistent launch: tile order (NULL = identity)
     unsigned long long* queue = nullptr;   // persistent launch: zeroed queue counter (NULL = static grid)
+    bool presplit = false;                 // 16-bit leaves: every operand has current split tiles
 };
 hipError_t launch_lpt_order(const ProdDesc* d_desc, int nprod, int64_t total, int maxc, uint32_t* counts,
                             uint32_t* hist, uint32_t* offs, uint32_t* order, unsigned long long* queue,

@@ -24,19 +24,6 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline uint32_t pack2(uint16_t a, uint16_t b) { return (uint32_t)a | ((uint32_t)b << 16); }
 
-template <int KIND>
-__device__ inline void split1(float x, uint16_t& hi, uint16_t& lo) {
-    if constexpr (KIND == kSplitF16) {
-        const _Float16 h = (_Float16)x;
-        hi = __builtin_bit_cast(uint16_t, h);
-        lo = __builtin_bit_cast(uint16_t, (_Float16)(x - (float)h));
-    } else {
-        const __bf16 h = (__bf16)x;
-        hi = __builtin_bit_cast(uint16_t, h);
-        lo = __builtin_bit_cast(uint16_t, (__bf16)(x - (float)h));
-    }
-}
-
 // One thread per 8 consecutive elements of the tile storage.
 template <int B, int KIND>
 __global__ void __launch_bounds__(256) k_split(const float* __restrict__ tiles, const int8_t* __restrict__ texp,
@@ -52,7 +39,7 @@ __global__ void __launch_bounds__(256) k_split(const float* __restrict__ tiles, 
     float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
     uint16_t h[8], l[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) split1<KIND>(KIND == kSplitF16 ? ldexpf(x[j], sh) : x[j], h[j], l[j]);
+    for (int j = 0; j < 8; ++j) split16<KIND>(KIND == kSplitF16 ? ldexpf(x[j], sh) : x[j], h[j], l[j]);
     u32x4 vh, vl;
     vh.x = pack2(h[0], h[1]);
     vh.y = pack2(h[2], h[3]);

@@ -110,6 +110,42 @@ def test_multiply_matches_oracle(n, b, tau, prec, fam):
     print(f"  T={len(keys)} relerr_vs_oracle={oracle.rel_err(out, ref):.3e}", flush=True)
 
 
+@pytest.mark.parametrize("n,leaf,prec", [(901, 64, "f16x3"), (900, 64, "bf16x3"), (513, 32, "f16"),
+                                         (200, 64, "bf16"), (700, 128, "f16x3")])
+def test_presplit_operands_match_split_on_the_fly(n, leaf, prec):
+    # operands built with their split tiles (read by the leaf kernel) and
+    # operands split on the fly inside it give the same hi/lo bits, so the
+    # products agree exactly
+    _case(f"build_ex split n={n} leaf={leaf} {prec}")
+    a = si.algebraic_decay(n, 2.0, 2, np.float32)
+    A1 = sp.build(to_dev(a), leaf)
+    C1 = sp.multiply(A1, A1, 1e-6, prec)
+    A2 = sp.build(to_dev(a), leaf, prec=prec)
+    C2 = sp.multiply(A2, A2, 1e-6, prec)
+    assert np.array_equal(C1.to_dense().cpu().numpy(), C2.to_dense().cpu().numpy())
+    assert np.array_equal(A1.to_dense().cpu().numpy(), A2.to_dense().cpu().numpy())
+    for lv in range(A1.levels + 1):
+        assert np.array_equal(A1.norms(lv), A2.norms(lv)), f"level {lv}"
+    # a rebuild from other values refreshes the split tiles of the same handle,
+    # and a plain rebuild makes them stale (products split on the fly again)
+    b = si.algebraic_decay(n, 2.0, 7, np.float32)
+    sp.build(to_dev(b), leaf, out=A2, prec=prec)
+    C3 = sp.multiply(A2, A2, 1e-6, prec)
+    B1 = sp.build(to_dev(b), leaf)
+    C4 = sp.multiply(B1, B1, 1e-6, prec)
+    assert np.array_equal(C3.to_dense().cpu().numpy(), C4.to_dense().cpu().numpy())
+    sp.build(to_dev(a), leaf, out=A2)
+    C5 = sp.multiply(A2, A2, 1e-6, prec)
+    assert np.array_equal(C5.to_dense().cpu().numpy(), C1.to_dense().cpu().numpy())
+
+
+def test_build_ex_rejects_16bit_split_of_fp64():
+    _case("build_ex fp64 + f16x3")
+    a = si.algebraic_decay(64, 2.0, 2, np.float64)
+    with pytest.raises(sp.SpammError):
+        sp.build(to_dev(a), 32, prec="f16x3")
+
+
 def test_precision_ladder_error_order():
     # on the same kept set, error vs the FP64 oracle falls bf16 > f16 > bf16x3 > f16x3 ~ f32
     _case("precision ladder")
