@@ -28,7 +28,7 @@ using namespace leafk;
 template <int B, int P>
 struct Geo {
     static constexpr int R = B / 32;                                   // 16x16 blocks per wave per dim
-    static constexpr int KC = (P == kF64) ? (B == 128 ? 16 : 32) : (B == 64 ? 64 : 32);  // k-chunk
+    static constexpr int KC = (P == kF64) ? (B == 128 ? 16 : 32) : 32;  // k-chunk (small: 3 blocks per CU)
     static constexpr int NCH = B / KC;                                 // chunks per task
     // operand element in LDS
     using E = typename std::conditional<P == kF64, double, typename std::conditional<is16(P), uint16_t, float>::type>::type;
