@@ -294,10 +294,10 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
     cp.Lmax = C->L;
     cp.front_cap = ps->front_cap;
     cp.mask_words = C->nb * C->nb * ceil_div(C->nb, 64);
+    cp.nonempty = nonempty_ctr(ps->ctr);
     int64_t items[kMaxLevels];
     tier_items(C, ps->front_cap, items);
     if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[0], s));
-    SPAMM_HIP(launch_clear_nonempty(nonempty_ctr(ps->ctr), 1, d_active, s));
     SPAMM_HIP(launch_cull_ex(d_desc, cp, ps->mask, ps->front[0], ps->front[1], ps->ctr, want_bound, d_active, items, s));
     LeafPlan lp;
     lp.count = 1;
@@ -623,6 +623,7 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
     cp.Lmax = Lmax;
     cp.front_cap = cap;
     cp.mask_words = 0;
+    cp.nonempty = nonempty_ctr(ctr);
     LeafPlan lp;
     lp.count = count;
     lp.total_tiles = total;
@@ -638,7 +639,6 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
         lp.queue = (unsigned long long*)(ws + o_q);
     }
     hipError_t e = hipMemcpyAsync(d_desc, hd.data(), sizeof(ProdDesc) * count, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_clear_nonempty(nonempty_ctr(ctr), count, nullptr, s);
     if (e == hipSuccess) e = launch_clear_masks(d_desc, count, s);
     if (e == hipSuccess)
         e = launch_cull_ex(d_desc, cp, nullptr, (uint64_t*)(ws + o_f0), (uint64_t*)(ws + o_f1), ctr, st != nullptr,

@@ -24,21 +24,23 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
     return v;
 }
 
-__global__ void __launch_bounds__(kCullThreads)
-    k_cull_tier(const ProdDesc* __restrict__ desc, int nprod, int l, const uint64_t* __restrict__ in,
-                uint64_t* __restrict__ out, DevCounters* __restrict__ ctr, int64_t out_cap, int want_bound,
-                const int* __restrict__ active) {
-    if (active && *active == 0) return;
-    __shared__ unsigned wave_tot[kCullThreads / kWave];
-    __shared__ unsigned long long block_base;
-    const int64_t P = (int64_t)ctr->front_count[l];
+// One pass over the items of tier l (the stored frontier, then the virtual
+// roots).  ONE_BLOCK: the whole tier is handled by this block, which keeps the
+// frontier sizes in LDS (s_count) instead of the global counters, so several
+// small tiers run in one launch.
+template <bool ONE_BLOCK>
+__device__ void cull_pass(const ProdDesc* __restrict__ desc, int nprod, int l, const uint64_t* __restrict__ in,
+                          uint64_t* __restrict__ out, DevCounters* __restrict__ ctr, int64_t out_cap, int want_bound,
+                          unsigned* wave_tot, unsigned long long* block_base, unsigned long long* s_count) {
+    const int64_t P = ONE_BLOCK ? (int64_t)s_count[l] : (int64_t)ctr->front_count[l];
     const int64_t items = P + nprod;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int c = l - 1;  // child tier
+    const int64_t first = ONE_BLOCK ? 0 : (int64_t)blockIdx.x * kCullThreads;
+    const int64_t stride = ONE_BLOCK ? kCullThreads : (int64_t)gridDim.x * kCullThreads;
 
-    for (int64_t base = (int64_t)blockIdx.x * kCullThreads; base < items;
-         base += (int64_t)gridDim.x * kCullThreads) {
+    for (int64_t base = first; base < items; base += stride) {
         const int64_t idx = base + threadIdx.x;
         uint32_t m = 0, I = 0, J = 0, K = 0;
         bool have = false;
@@ -123,10 +125,16 @@ __global__ void __launch_bounds__(kCullThreads)
             if (w < wid) wave_off += wave_tot[w];
             block_tot += wave_tot[w];
         }
-        if (threadIdx.x == 0)
-            block_base = block_tot ? atomicAdd(&ctr->front_count[c], (unsigned long long)block_tot) : 0ull;
+        if (threadIdx.x == 0) {
+            if (ONE_BLOCK) {
+                *block_base = s_count[c];
+                s_count[c] += block_tot;
+            } else {
+                *block_base = block_tot ? atomicAdd(&ctr->front_count[c], (unsigned long long)block_tot) : 0ull;
+            }
+        }
         __syncthreads();
-        int64_t pos = (int64_t)block_base + wave_off + (incl - nk);
+        int64_t pos = (int64_t)*block_base + wave_off + (incl - nk);
         if (keep) {
             if (pos + nk > out_cap) {
                 atomicOr(&ctr->status, kDevCapacity);
@@ -141,21 +149,54 @@ __global__ void __launch_bounds__(kCullThreads)
     }
 }
 
-__global__ void k_zero_counters(DevCounters* ctr, int nprod, const int* active) {
+
+__global__ void __launch_bounds__(kCullThreads)
+    k_cull_tier(const ProdDesc* __restrict__ desc, int nprod, int l, const uint64_t* __restrict__ in,
+                uint64_t* __restrict__ out, DevCounters* __restrict__ ctr, int64_t out_cap, int want_bound,
+                const int* __restrict__ active) {
     if (active && *active == 0) return;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < kMaxLevels) ctr->front_count[t] = 0;
-    if (t == 0) ctr->status = 0;
-    for (int i = t; i < nprod * kMaxLevels; i += gridDim.x * blockDim.x)
-        ctr->survivors[i / kMaxLevels][i % kMaxLevels] = 0;
-    for (int i = t; i < nprod; i += gridDim.x * blockDim.x) ctr->culled_bound[i] = 0.0;
+    __shared__ unsigned wave_tot[kCullThreads / kWave];
+    __shared__ unsigned long long block_base;
+    cull_pass<false>(desc, nprod, l, in, out, ctr, out_cap, want_bound, wave_tot, &block_base, nullptr);
 }
 
-__global__ void k_clear_mask(uint64_t* mask, int64_t words, const int* active) {
+// Tiers top .. stop + 1 in one block (small frontiers): the frontier of tier l
+// lives in buffer (l & 1) as in the per-tier launches, and the sizes reach the
+// global counters for the launches that follow.
+__global__ void __launch_bounds__(kCullThreads)
+    k_cull_top(const ProdDesc* __restrict__ desc, int nprod, int top, int stop, uint64_t* __restrict__ front0,
+               uint64_t* __restrict__ front1, DevCounters* __restrict__ ctr, int64_t out_cap, int want_bound,
+               const int* __restrict__ active) {
     if (active && *active == 0) return;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
-         i += (int64_t)gridDim.x * blockDim.x)
-        mask[i] = 0;
+    __shared__ unsigned wave_tot[kCullThreads / kWave];
+    __shared__ unsigned long long block_base;
+    __shared__ unsigned long long s_count[kMaxLevels];
+    if (threadIdx.x < kMaxLevels) s_count[threadIdx.x] = 0;
+    __syncthreads();
+    for (int l = top; l > stop; --l) {
+        const uint64_t* in = (l & 1) ? front1 : front0;
+        uint64_t* out = ((l - 1) & 1) ? front1 : front0;
+        cull_pass<true>(desc, nprod, l, in, out, ctr, out_cap, want_bound, wave_tot, &block_base, s_count);
+        __syncthreads();  // this tier's stores are read by the next pass of the same block
+    }
+    if (threadIdx.x < kMaxLevels) ctr->front_count[threadIdx.x] = s_count[threadIdx.x];
+}
+
+// Counters, per-product non-empty tile counts and (single product) the leaf
+// bitmask, zeroed in one launch.
+__global__ void k_cull_prep(DevCounters* ctr, unsigned long long* nonempty, int nprod, uint64_t* mask,
+                            int64_t words, const int* active) {
+    if (active && *active == 0) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    if (t < kMaxLevels) ctr->front_count[t] = 0;
+    if (t == 0) ctr->status = 0;
+    for (int64_t i = t; i < (int64_t)nprod * kMaxLevels; i += nt) ctr->survivors[i / kMaxLevels][i % kMaxLevels] = 0;
+    for (int64_t i = t; i < nprod; i += nt) {
+        ctr->culled_bound[i] = 0.0;
+        if (nonempty) nonempty[i] = 0;
+    }
+    for (int64_t i = t; i < words; i += nt) mask[i] = 0;
 }
 
 // Batch: block (m, y) clears slice y of product m's leaf bitmask.
@@ -189,14 +230,25 @@ __global__ void k_task_keys(const ProdDesc* __restrict__ desc, int64_t nb, int W
 hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t* mask, uint64_t* front0,
                           uint64_t* front1, DevCounters* ctr, int want_bound, const int* active,
                           const int64_t* tier_items, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_counters, dim3(8), dim3(256), 0, s, ctr, plan.count, active);
-    if (mask) {  // (a batch clears its per-product masks with launch_clear_masks)
-        int64_t blocks = (plan.mask_words + 255) / 256;
-        blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
-        hipLaunchKernelGGL(k_clear_mask, dim3((unsigned)blocks), dim3(256), 0, s, mask, plan.mask_words, active);
+    {
+        const int64_t words = mask ? plan.mask_words : 0;  // (a batch clears its masks with launch_clear_masks)
+        int64_t blocks = (words + 255) / 256;
+        blocks = blocks < 8 ? 8 : (blocks > 2048 ? 2048 : blocks);
+        hipLaunchKernelGGL(k_cull_prep, dim3((unsigned)blocks), dim3(256), 0, s, ctr, plan.nonempty, plan.count, mask,
+                           words, active);
     }
     const int top = plan.Lmax < 1 ? 1 : plan.Lmax;
-    for (int l = top; l >= 1; --l) {
+    // tiers whose items fit a few passes of one block go to one launch
+    constexpr int64_t kOneBlockItems = 16 * kCullThreads;
+    int l = top;
+    int stop = top;
+    while (stop >= 1 && tier_items[stop] + plan.count <= kOneBlockItems) --stop;
+    if (stop < top) {
+        hipLaunchKernelGGL(k_cull_top, dim3(1), dim3(kCullThreads), 0, s, d_desc, plan.count, top, stop, front0,
+                           front1, ctr, plan.front_cap, want_bound, active);
+        l = stop;
+    }
+    for (; l >= 1; --l) {
         // frontier of tier l lives in buffer (l & 1); children go to ((l-1) & 1)
         const uint64_t* in = (l & 1) ? front1 : front0;
         uint64_t* out = ((l - 1) & 1) ? front1 : front0;

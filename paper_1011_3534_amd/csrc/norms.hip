@@ -200,11 +200,6 @@ __global__ void __launch_bounds__(256) k_diff_norms(const TX* __restrict__ x, co
     }
 }
 
-__global__ void k_clear_u64(unsigned long long* p, int count, const int* active) {
-    if (active && *active == 0) return;
-    if ((int)threadIdx.x < count) p[threadIdx.x] = 0ull;
-}
-
 // ||X - Y||^2 and ||Y||^2 for handles of equal n but different leaf sizes:
 // element (row, col) is looked up in each handle's own tile layout.
 template <typename TX, typename TY>
@@ -349,11 +344,6 @@ hipError_t launch_diff_norms(const spamm_matrix* X, const spamm_matrix* Y, doubl
     else
         hipLaunchKernelGGL((k_diff_norms<double, double>), dim3(blocks), dim3(256), 0, s,
                            (const double*)X->tiles, (const double*)Y->tiles, count, d_out);
-    return hipGetLastError();
-}
-
-hipError_t launch_clear_nonempty(unsigned long long* p, int count, const int* active, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(256), 0, s, p, count, active);
     return hipGetLastError();
 }
 

@@ -152,7 +152,6 @@ int num_cus();
 hipError_t launch_pack_norm(const void* a, int64_t n, int64_t lda, spamm_dtype dt, spamm_matrix* M,
                             unsigned* status, int split_kind, hipStream_t s);
 hipError_t launch_upper_norms(spamm_matrix* M, hipStream_t s, const int* active);
-hipError_t launch_clear_nonempty(unsigned long long* p, int count, const int* active, hipStream_t s);
 hipError_t launch_to_dense(const spamm_matrix* M, void* out, int64_t ldo, hipStream_t s);
 hipError_t launch_diff_norms(const spamm_matrix* X, const spamm_matrix* Y, double* d_out, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s);
@@ -166,6 +165,7 @@ struct CullPlan {
     int Lmax;               // highest tier among the products
     int64_t front_cap;      // capacity of each frontier buffer (keys)
     int64_t mask_words;     // total leaf-bitmask words
+    unsigned long long* nonempty = nullptr;  // per-product non-empty tile counters (zeroed with the rest)
 };
 hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t* mask, uint64_t* front0,
                           uint64_t* front1, DevCounters* ctr, int want_bound, const int* active,
