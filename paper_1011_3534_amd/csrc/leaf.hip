@@ -259,22 +259,16 @@ __device__ inline void stage16c_store(const Stage16c<B, P>& st, char* buf, int t
     uint16_t* As = reinterpret_cast<uint16_t*>(buf);
     uint16_t* Bs = As + G::NARR * G::A_ELEMS;
     auto put = [&](const float* x, int s, uint16_t* dh, uint16_t* dl) {
-        uint16_t h[8], l[8];
+        // pairs: one packed conversion for hi and one for lo
+        uint32_t h[4], l[4];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) split16<KIND>(isf16(P) ? ldexpf(x[j], s) : x[j], h[j], l[j]);
-        u32x4 vh, vl;
-        vh.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-        vh.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
-        vh.z = (uint32_t)h[4] | ((uint32_t)h[5] << 16);
-        vh.w = (uint32_t)h[6] | ((uint32_t)h[7] << 16);
-        *reinterpret_cast<u32x4*>(dh) = vh;
-        if constexpr (isx3(P)) {
-            vl.x = (uint32_t)l[0] | ((uint32_t)l[1] << 16);
-            vl.y = (uint32_t)l[2] | ((uint32_t)l[3] << 16);
-            vl.z = (uint32_t)l[4] | ((uint32_t)l[5] << 16);
-            vl.w = (uint32_t)l[6] | ((uint32_t)l[7] << 16);
-            *reinterpret_cast<u32x4*>(dl) = vl;
+        for (int j = 0; j < 4; ++j) {
+            spamm_f2 v = {x[2 * j], x[2 * j + 1]};
+            if constexpr (isf16(P)) v = spamm_f2{ldexpf(v.x, s), ldexpf(v.y, s)};
+            split16x2<KIND>(v, h[j], l[j]);
         }
+        *reinterpret_cast<u32x4*>(dh) = u32x4{h[0], h[1], h[2], h[3]};
+        if constexpr (isx3(P)) *reinterpret_cast<u32x4*>(dl) = u32x4{l[0], l[1], l[2], l[3]};
     };
 #pragma unroll
     for (int u = 0; u < S::U; ++u) {
@@ -441,19 +435,39 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             if constexpr (P != kF64) {
                 chunk_mma<B, P, Acc>(smem + bf * G::BUF_BYTES, part, lane, wr, wc);
                 if (t % NCH == NCH - 1) {
-                    const int un = isf16(P) ? -((int)kl->sa[t / NCH] + (int)kl->sb[t / NCH]) : 0;
+                    const int un = isf16(P) ? __builtin_amdgcn_readfirstlane(
+                                                  -((int)kl->sa[t / NCH] + (int)kl->sb[t / NCH]))
+                                            : 0;
+                    if constexpr (isf16(P)) {
+                        // undo the product's power-of-two scales: one FMA by 2^un
+                        // when 2^un is a normal float (the same value as ldexpf)
+                        if (un >= -126 && un <= 127) {
+                            const float f = ldexpf(1.0f, un);
+#pragma unroll
+                            for (int i = 0; i < R; ++i)
+#pragma unroll
+                                for (int j = 0; j < R; ++j)
+#pragma unroll
+                                    for (int q = 0; q < 4; ++q)
+                                        acc[i][j][q] = __builtin_fmaf(part[i][j][q], f, acc[i][j][q]);
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < R; ++i)
+#pragma unroll
+                                for (int j = 0; j < R; ++j)
+#pragma unroll
+                                    for (int q = 0; q < 4; ++q) acc[i][j][q] += ldexpf(part[i][j][q], un);
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < R; ++i)
+#pragma unroll
+                            for (int j = 0; j < R; ++j) acc[i][j] += part[i][j];
+                    }
 #pragma unroll
                     for (int i = 0; i < R; ++i)
 #pragma unroll
-                        for (int j = 0; j < R; ++j) {
-                            if constexpr (isf16(P)) {  // undo the product's power-of-two scales
-#pragma unroll
-                                for (int q = 0; q < 4; ++q) acc[i][j][q] += ldexpf(part[i][j][q], un);
-                            } else {
-                                acc[i][j] += part[i][j];
-                            }
-                            part[i][j] = Acc{0, 0, 0, 0};
-                        }
+                        for (int j = 0; j < R; ++j) part[i][j] = Acc{0, 0, 0, 0};
                 }
             } else {
                 chunk_mma<B, P, Acc>(smem + bf * G::BUF_BYTES, acc, lane, wr, wc);

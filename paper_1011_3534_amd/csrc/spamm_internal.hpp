@@ -39,7 +39,8 @@ constexpr int kSplitF16 = 0;   // hi = fp16(x 2^s), lo = fp16(x 2^s - hi), s = f
 constexpr int kSplitBF16 = 1;  // hi = bf16(x), lo = bf16(x - hi)
 
 // x = hi + lo + (rounding of lo), both halves rounded to nearest even; x is
-// the (FP16: already scaled) FP32 value.
+// the (FP16: already scaled) FP32 value.  split16 (one value) and split16x2
+// (two values, packed: element 0 in the low half) give the same bits.
 template <int KIND>
 __device__ inline void split16(float x, uint16_t& hi, uint16_t& lo) {
     if constexpr (KIND == kSplitF16) {
@@ -50,6 +51,25 @@ __device__ inline void split16(float x, uint16_t& hi, uint16_t& lo) {
         const __bf16 h = (__bf16)x;
         hi = __builtin_bit_cast(uint16_t, h);
         lo = __builtin_bit_cast(uint16_t, (__bf16)(x - (float)h));
+    }
+}
+
+typedef float spamm_f2 __attribute__((ext_vector_type(2)));
+typedef _Float16 spamm_h2 __attribute__((ext_vector_type(2)));
+typedef __bf16 spamm_b2 __attribute__((ext_vector_type(2)));
+
+template <int KIND>
+__device__ inline void split16x2(spamm_f2 x, uint32_t& hi, uint32_t& lo) {
+    if constexpr (KIND == kSplitF16) {
+        const spamm_h2 h = __builtin_convertvector(x, spamm_h2);
+        const spamm_f2 r = x - __builtin_convertvector(h, spamm_f2);
+        hi = __builtin_bit_cast(uint32_t, h);
+        lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, spamm_h2));
+    } else {
+        const spamm_b2 h = __builtin_convertvector(x, spamm_b2);
+        const spamm_f2 r = x - __builtin_convertvector(h, spamm_f2);
+        hi = __builtin_bit_cast(uint32_t, h);
+        lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, spamm_b2));
     }
 }
 
