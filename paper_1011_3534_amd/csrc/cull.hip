@@ -18,6 +18,7 @@ namespace spamm {
 namespace {
 
 constexpr int kCullThreads = 256;
+constexpr int kTopThreads = 1024;  // the single-block launch of the small upper tiers
 
 __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
     for (int d = kWave / 2; d >= 1; d /= 2) v += __shfl_xor(v, d, kWave);
@@ -28,7 +29,7 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
 // roots).  ONE_BLOCK: the whole tier is handled by this block, which keeps the
 // frontier sizes in LDS (s_count) instead of the global counters, so several
 // small tiers run in one launch.
-template <bool ONE_BLOCK>
+template <bool ONE_BLOCK, int NT>
 __device__ void cull_pass(const ProdDesc* __restrict__ desc, int nprod, int l, const uint64_t* __restrict__ in,
                           uint64_t* __restrict__ out, DevCounters* __restrict__ ctr, int64_t out_cap, int want_bound,
                           unsigned* wave_tot, unsigned long long* block_base, unsigned long long* s_count) {
@@ -37,8 +38,8 @@ __device__ void cull_pass(const ProdDesc* __restrict__ desc, int nprod, int l, c
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int c = l - 1;  // child tier
-    const int64_t first = ONE_BLOCK ? 0 : (int64_t)blockIdx.x * kCullThreads;
-    const int64_t stride = ONE_BLOCK ? kCullThreads : (int64_t)gridDim.x * kCullThreads;
+    const int64_t first = ONE_BLOCK ? 0 : (int64_t)blockIdx.x * NT;
+    const int64_t stride = ONE_BLOCK ? NT : (int64_t)gridDim.x * NT;
 
     for (int64_t base = first; base < items; base += stride) {
         const int64_t idx = base + threadIdx.x;
@@ -121,7 +122,7 @@ __device__ void cull_pass(const ProdDesc* __restrict__ desc, int nprod, int l, c
         if (lane == kWave - 1) wave_tot[wid] = incl;
         __syncthreads();
         unsigned wave_off = 0, block_tot = 0;
-        for (int w = 0; w < kCullThreads / kWave; ++w) {
+        for (int w = 0; w < NT / kWave; ++w) {
             if (w < wid) wave_off += wave_tot[w];
             block_tot += wave_tot[w];
         }
@@ -157,18 +158,19 @@ __global__ void __launch_bounds__(kCullThreads)
     if (active && *active == 0) return;
     __shared__ unsigned wave_tot[kCullThreads / kWave];
     __shared__ unsigned long long block_base;
-    cull_pass<false>(desc, nprod, l, in, out, ctr, out_cap, want_bound, wave_tot, &block_base, nullptr);
+    cull_pass<false, kCullThreads>(desc, nprod, l, in, out, ctr, out_cap, want_bound, wave_tot, &block_base,
+                                   nullptr);
 }
 
 // Tiers top .. stop + 1 in one block (small frontiers): the frontier of tier l
 // lives in buffer (l & 1) as in the per-tier launches, and the sizes reach the
 // global counters for the launches that follow.
-__global__ void __launch_bounds__(kCullThreads)
+__global__ void __launch_bounds__(kTopThreads)
     k_cull_top(const ProdDesc* __restrict__ desc, int nprod, int top, int stop, uint64_t* __restrict__ front0,
                uint64_t* __restrict__ front1, DevCounters* __restrict__ ctr, int64_t out_cap, int want_bound,
                const int* __restrict__ active) {
     if (active && *active == 0) return;
-    __shared__ unsigned wave_tot[kCullThreads / kWave];
+    __shared__ unsigned wave_tot[kTopThreads / kWave];
     __shared__ unsigned long long block_base;
     __shared__ unsigned long long s_count[kMaxLevels];
     if (threadIdx.x < kMaxLevels) s_count[threadIdx.x] = 0;
@@ -176,7 +178,8 @@ __global__ void __launch_bounds__(kCullThreads)
     for (int l = top; l > stop; --l) {
         const uint64_t* in = (l & 1) ? front1 : front0;
         uint64_t* out = ((l - 1) & 1) ? front1 : front0;
-        cull_pass<true>(desc, nprod, l, in, out, ctr, out_cap, want_bound, wave_tot, &block_base, s_count);
+        cull_pass<true, kTopThreads>(desc, nprod, l, in, out, ctr, out_cap, want_bound, wave_tot, &block_base,
+                                     s_count);
         __syncthreads();  // this tier's stores are read by the next pass of the same block
     }
     if (threadIdx.x < kMaxLevels) ctr->front_count[threadIdx.x] = s_count[threadIdx.x];
@@ -239,12 +242,12 @@ hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t
     }
     const int top = plan.Lmax < 1 ? 1 : plan.Lmax;
     // tiers whose items fit a few passes of one block go to one launch
-    constexpr int64_t kOneBlockItems = 16 * kCullThreads;
+    constexpr int64_t kOneBlockItems = 4 * kTopThreads;
     int l = top;
     int stop = top;
     while (stop >= 1 && tier_items[stop] + plan.count <= kOneBlockItems) --stop;
     if (stop < top) {
-        hipLaunchKernelGGL(k_cull_top, dim3(1), dim3(kCullThreads), 0, s, d_desc, plan.count, top, stop, front0,
+        hipLaunchKernelGGL(k_cull_top, dim3(1), dim3(kTopThreads), 0, s, d_desc, plan.count, top, stop, front0,
                            front1, ctr, plan.front_cap, want_bound, active);
         l = stop;
     }
