@@ -131,6 +131,9 @@ spamm_status alloc_storage(spamm_matrix* M, hipStream_t s) {
     M->norms = (double*)dev_alloc(M, nbytes, s);
     M->texp = (int8_t*)dev_alloc(M, (size_t)(M->nb * M->nb), s);
     if (!M->tiles || !M->norms || !M->texp) return set_error(SPAMM_ENOMEM, "device allocation failed");
+    // exponent 0 = "tile not known to be zero": products skip rewriting only
+    // tiles a previous write left at zero (exponent -128)
+    SPAMM_HIP(hipMemsetAsync(M->texp, 0, (size_t)(M->nb * M->nb), s));
     int64_t* off = reinterpret_cast<int64_t*>(M->norms + M->norms_total);
     int* mm = reinterpret_cast<int*>(off + kMaxLevels);
     SPAMM_HIP(hipMemcpyAsync(off, M->lvl_off, sizeof(int64_t) * kMaxLevels, hipMemcpyHostToDevice, s));
@@ -747,16 +750,9 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
         cleanup();
         return r;
     };
-    const int kind = split_kind(prec);
-    for (int i = 0; i < 2 && kind >= 0 && r == SPAMM_OK; ++i) r = alloc_split(X[i], s);
-    if (r != SPAMM_OK) {
-        cleanup();
-        return r;
-    }
     hipError_t e = hipMemcpyAsync(st, &h, sizeof h, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_gershgorin(H, glo, ghi, st, s);
     if (e == hipSuccess) e = launch_sp2_init(H, X[0], part, st, s);
-    if (e == hipSuccess && kind >= 0) e = launch_split(X[0], kind, nullptr, s);
     // descriptors of the two directions X0 -> X1 and X1 -> X0
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
         spamm_matrix* src = X[i];
@@ -764,11 +760,6 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
         ProdDesc d = make_desc(src, src, dst, tau);
         d.sp2_part = part;
         d.X = src->tiles;
-        if (kind >= 0) {
-            // the epilogue writes X_{m+1}'s split tiles for the next step
-            d.C16 = dst->split;
-            d.c16_kind = kind;
-        }
         dst->ps->host_desc = d;
         dst->ps->desc_valid = false;  // differs from any plain product's descriptor
         e = hipMemcpyAsync(dst->ps->desc, &dst->ps->host_desc, sizeof d, hipMemcpyHostToDevice, s);
@@ -830,7 +821,6 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
     cs = nullptr;
     dev_free(owner, scratch, s);
     scratch = nullptr;
-    X[res]->gen++;  // its split tiles are not kept in step with the result
     *P = X[res];
     X[res] = nullptr;
     cleanup();

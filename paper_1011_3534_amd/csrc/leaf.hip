@@ -567,6 +567,26 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         __syncthreads();  // stage buffers and the list are free again
     }
 
+    // A C tile with no kept product is zero (SP2: when its X tile is zero as
+    // well).  If the result handle's exponent says the stored tile already
+    // holds zeros from an earlier write, only the zero norm (and SP2's zero
+    // partials) are stored.  Fresh handles start with exponents 0 ("not known
+    // zero"), so every tile is written at least once.  Static schedule only
+    // (one tile per block, so the early exit ends the block); the persistent
+    // kernel always runs the full epilogue.
+    const bool zero_kept =
+        __builtin_amdgcn_readfirstlane((int)(!counted && d.eC[local] == -128 && (!SP2 || d.eA[local] == -128))) != 0;
+    if (blocked && zero_kept) {
+        if (tid == 0) {
+            d.SC[local] = 0.0;
+            if constexpr (SP2) {
+                d.sp2_part[local] = 0.0;
+                if (I == J) d.sp2_part[(int64_t)nb * nb + I] = 0.0;
+            }
+        }
+        return;
+    }
+
     // ---------------------------------------------------------------- epilogue
     CT* Cs = reinterpret_cast<CT*>(smem);
 #pragma unroll
@@ -676,36 +696,8 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         }
         d.eC[local] = (int8_t)e;
         if constexpr (SP2) d.sp2_part[local] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
-        red[0][0] = (double)e;
     }
     __syncthreads();  // red and smem are reused by the next tile of a persistent block
-    if constexpr (P != kF64) {
-        if (d.C16) {
-            // split hi/lo tiles of the stored values (the next product reads
-            // them), with the tile exponent just computed
-            const int sh = d.c16_kind == kSplitF16 ? f16_shift((int)red[0][0]) : 0;
-            GLOBAL uint16_t* hi = (GLOBAL uint16_t*)d.C16 + local * TS;
-            GLOBAL uint16_t* lo = hi + lo16;
-            for (int u = tid; u < B * B / 4; u += 256) {
-                const int r = u / (B / 4), c = (u % (B / 4)) * 4;
-                uint16_t h[4], l[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float x = (float)Cs[r * G::SC + c + j];
-                    if (d.c16_kind == kSplitF16) split16<kSplitF16>(ldexpf(x, sh), h[j], l[j]);
-                    else split16<kSplitBF16>(x, h[j], l[j]);
-                }
-                u32x2 vh, vl;
-                vh.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-                vh.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
-                vl.x = (uint32_t)l[0] | ((uint32_t)l[1] << 16);
-                vl.y = (uint32_t)l[2] | ((uint32_t)l[3] << 16);
-                *(GLOBAL u32x2*)(hi + r * B + c) = vh;
-                *(GLOBAL u32x2*)(lo + r * B + c) = vl;
-            }
-            __syncthreads();
-        }
-    }
 }
 
 // Static schedule: one block per tile; block x runs on XCD x mod 8 and takes
@@ -767,11 +759,11 @@ hipError_t go(const ProdDesc* d_desc, const LeafPlan& p, hipStream_t s) {
     return hipGetLastError();
 }
 
-// 16-bit leaves: operands with split tiles (always in SP2, whose epilogue
-// writes them) or split on the fly from the FP32 tiles
+// 16-bit leaves: operands with current split tiles, or split on the fly from
+// the FP32 tiles (always in SP2, whose operands change every step)
 template <int B, int P>
 hipError_t go16(const ProdDesc* d_desc, const LeafPlan& p, hipStream_t s) {
-    if (p.sp2) return go<B, P, float, float, true, true>(d_desc, p, s);
+    if (p.sp2) return go<B, P, float, float, true, false>(d_desc, p, s);
     if (p.presplit) return go<B, P, float, float, false, true>(d_desc, p, s);
     return go<B, P, float, float, false, false>(d_desc, p, s);
 }

@@ -90,7 +90,6 @@ struct ProdDesc {
     const void* X;            // SP2: the operand tiles X_m (== A == B)
     const uint16_t* A16;      // split 16-bit tiles of A and B: hi tiles, then lo
     const uint16_t* B16;      //   tiles at +nb^2 b^2 elements (16-bit leaves only)
-    uint16_t* C16;            // optional: split tiles of C written by the epilogue
     unsigned long long* nonempty;  // count of C tiles with at least one kept product
     int64_t lvl_off[kMaxLevels];
     int32_t lvl_m[kMaxLevels];
@@ -98,7 +97,7 @@ struct ProdDesc {
     double tau2;
     int32_t nb, L, W;
     int32_t a_f64, b_f64;     // operand tile element types (1 = FP64)
-    int32_t c16_kind;         // kSplitF16 / kSplitBF16 when C16 is set
+    int32_t pad_;
 };
 
 // Device-side counters of one product launch sequence.

@@ -139,6 +139,25 @@ def test_presplit_operands_match_split_on_the_fly(n, leaf, prec):
     assert np.array_equal(C5.to_dense().cpu().numpy(), C1.to_dense().cpu().numpy())
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16x3"])
+def test_reused_output_with_changing_zero_tiles(prec):
+    # a result handle keeps zero tiles from earlier products unwritten; outputs
+    # whose kept sets differ (tiles turning empty and non-empty) must still
+    # equal a product into a fresh handle, bit for bit
+    _case(f"reused C, changing zero tiles, {prec}")
+    n, b = 1500, 64
+    a = si.algebraic_decay(n, 2.0, 2, np.float32)
+    e = si.exp_decay(n, 0.5, 3, np.float32)
+    A, E = sp.build(to_dev(a), b), sp.build(to_dev(e), b)
+    C = sp.multiply(E, E, 1e-3, prec)          # narrow band: most tiles zero
+    for X, tau in ((A, 1e-6), (E, 1e-3), (A, 1e-4), (E, 1e-9)):
+        sp.multiply(X, X, tau, prec, out=C)
+        ref = sp.multiply(X, X, tau, prec)
+        assert np.array_equal(C.to_dense().cpu().numpy(), ref.to_dense().cpu().numpy())
+        for lv in range(C.levels + 1):
+            assert np.array_equal(C.norms(lv), ref.norms(lv))
+
+
 def test_build_ex_rejects_16bit_split_of_fp64():
     _case("build_ex fp64 + f16x3")
     a = si.algebraic_decay(64, 2.0, 2, np.float64)
