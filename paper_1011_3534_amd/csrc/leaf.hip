@@ -32,8 +32,9 @@ struct Geo {
     static constexpr int NCH = B / KC;                                 // chunks per task
     // operand element in LDS
     using E = typename std::conditional<P == kF64, double, typename std::conditional<is16(P), uint16_t, float>::type>::type;
-    static constexpr int SA = (P == kF64) ? KC + 2 : (is16(P) ? KC + 8 : KC + 4);  // A row stride (elements)
-    static constexpr int SB = (P == kF64) ? B + 8 : (is16(P) ? KC + 8 : B + 16);   // B row stride
+    // row strides (elements); 16-bit rows are unpadded and swizzled (sw16)
+    static constexpr int SA = (P == kF64) ? KC + 2 : (is16(P) ? KC : KC + 4);
+    static constexpr int SB = (P == kF64) ? B + 8 : (is16(P) ? KC : B + 16);
     static constexpr int ROWS_B = is16(P) ? B : KC;                                // B^T rows for 16-bit
     static constexpr int NARR = isx3(P) ? 2 : 1;                                   // hi (+ lo)
     static constexpr int A_ELEMS = B * SA;
@@ -43,7 +44,15 @@ struct Geo {
     static constexpr int SC = B + (P == kF64 ? 2 : 4);                            // C staging stride
     static constexpr int C_BYTES = B * SC * (int)sizeof(CT);
     static constexpr int SMEM = (2 * BUF_BYTES > C_BYTES) ? 2 * BUF_BYTES : C_BYTES;
+    static_assert(!is16(P) || KC == 32, "the 16-bit LDS swizzle assumes 32-wide k-chunks");
 };
+
+// 16-bit LDS rows (A rows and B^T rows, 32 k = four 16-byte groups): group g
+// of row r sits at slot g ^ ((r >> 2) & 3).  Sixteen consecutive rows then
+// cover all 64 banks both for the MFMA fragment reads (16 rows, one group)
+// and for the stores (4 rows x 4 groups, or 16 rows x one group), with no
+// padding.
+__device__ inline int sw16(int r, int k) { return (((k >> 3) ^ ((r >> 2) & 3)) << 3) | (k & 7); }
 
 // Kept K of one segment of a tile's mask (four words), with the FP16 scale
 // exponents of A_IK and B_KJ.
@@ -161,7 +170,7 @@ __device__ inline void stage16_load(Stage16<B, P>& st, const __amdgpu_buffer_rsr
             const int cp = unit % (B / 2), k = (unit / (B / 2)) * 8;
 #pragma unroll
             for (int j = 0; j < 8; ++j)
-                st.b[h][u][j] = __builtin_amdgcn_raw_buffer_load_b32(rb[h], ((k + j) * (B / 2) + cp) * 4, 0, 0);
+                st.b[h][u][j] = __builtin_amdgcn_raw_buffer_load_b32(rb[h], (k * (B / 2) + cp) * 4, j * (B / 2) * 4, 0);
         }
     }
 }
@@ -182,7 +191,7 @@ __device__ inline void stage16_store(const Stage16<B, P>& st, char* buf, int tid
             const int unit = tid + u * 256;
             if (S::PA && unit >= S::NA) break;
             const int r = unit / (KC / 8), k = (unit % (KC / 8)) * 8;
-            *reinterpret_cast<u32x4*>(As + h * G::A_ELEMS + r * G::SA + k) = st.a[h][u];
+            *reinterpret_cast<u32x4*>(As + h * G::A_ELEMS + r * G::SA + sw16(r, k)) = st.a[h][u];
         }
 #pragma unroll
         for (int u = 0; u < S::UB; ++u) {
@@ -199,7 +208,8 @@ __device__ inline void stage16_store(const Stage16<B, P>& st, char* buf, int tid
             od.y = (w[2] >> 16) | (w[3] & 0xFFFF0000u);
             od.z = (w[4] >> 16) | (w[5] & 0xFFFF0000u);
             od.w = (w[6] >> 16) | (w[7] & 0xFFFF0000u);
-            uint16_t* dst = Bs + h * G::B_ELEMS + (2 * cp) * G::SB + k;
+            // columns 2cp and 2cp+1 share (row >> 2), hence the swizzle
+            uint16_t* dst = Bs + h * G::B_ELEMS + (2 * cp) * G::SB + sw16(2 * cp, k);
             *reinterpret_cast<u32x4*>(dst) = ev;
             *reinterpret_cast<u32x4*>(dst + G::SB) = od;
         }
@@ -230,8 +240,10 @@ __device__ inline void stage16c_load(Stage16c<B, P>& st, __amdgpu_buffer_rsrc_t 
         const int unit = tid + u * 256;
         if (S::PARTIAL && unit >= S::NU) break;
         const int r = unit / (KC / 8), k = (unit % (KC / 8)) * 8;
-        const f32x4 v0 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, (r * B + k) * 4, 0, 0));
-        const f32x4 v1 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, (r * B + k + 4) * 4, 0, 0));
+        // one lane offset per unit; the constant parts go in the scalar offset
+        const int vo = (r * B + k) * 4;
+        const f32x4 v0 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, vo, 0, 0));
+        const f32x4 v1 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, vo, 16, 0));
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             st.a[u][j] = v0[j];
@@ -245,7 +257,7 @@ __device__ inline void stage16c_load(Stage16c<B, P>& st, __amdgpu_buffer_rsrc_t 
         const int c = unit % B, k = (unit / B) * 8;
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-            st.b[u][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, ((k + j) * B + c) * 4, 0, 0));
+            st.b[u][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, (k * B + c) * 4, j * B * 4, 0));
     }
 }
 
@@ -275,14 +287,16 @@ __device__ inline void stage16c_store(const Stage16c<B, P>& st, char* buf, int t
         const int unit = tid + u * 256;
         if (S::PARTIAL && unit >= S::NU) break;
         const int r = unit / (KC / 8), k = (unit % (KC / 8)) * 8;
-        put(st.a[u], sa, As + r * G::SA + k, As + G::A_ELEMS + r * G::SA + k);
+        const int ka = sw16(r, k);
+        put(st.a[u], sa, As + r * G::SA + ka, As + G::A_ELEMS + r * G::SA + ka);
     }
 #pragma unroll
     for (int u = 0; u < S::U; ++u) {
         const int unit = tid + u * 256;
         if (S::PARTIAL && unit >= S::NU) break;
         const int c = unit % B, k = (unit / B) * 8;
-        put(st.b[u], sb, Bs + c * G::SB + k, Bs + G::B_ELEMS + c * G::SB + k);
+        const int kb = sw16(c, k);
+        put(st.b[u], sb, Bs + c * G::SB + kb, Bs + G::B_ELEMS + c * G::SB + kb);
     }
 }
 
@@ -305,11 +319,13 @@ __device__ inline void chunk_mma(const char* buf, Acc (&acc)[Geo<B, P>::R][Geo<B
             V8 ah[R], bh[R], al[R], bl[R];
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-                ah[i] = *reinterpret_cast<const V8*>(As + (row0 + 16 * i) * G::SA + k);
-                bh[i] = *reinterpret_cast<const V8*>(Bs + (col0 + 16 * i) * G::SB + k);
+                const int ra = row0 + 16 * i, rb = col0 + 16 * i;
+                const int oa = ra * G::SA + sw16(ra, k), ob = rb * G::SB + sw16(rb, k);
+                ah[i] = *reinterpret_cast<const V8*>(As + oa);
+                bh[i] = *reinterpret_cast<const V8*>(Bs + ob);
                 if constexpr (isx3(P)) {
-                    al[i] = *reinterpret_cast<const V8*>(As + G::A_ELEMS + (row0 + 16 * i) * G::SA + k);
-                    bl[i] = *reinterpret_cast<const V8*>(Bs + G::B_ELEMS + (col0 + 16 * i) * G::SB + k);
+                    al[i] = *reinterpret_cast<const V8*>(As + G::A_ELEMS + oa);
+                    bl[i] = *reinterpret_cast<const V8*>(Bs + G::B_ELEMS + ob);
                 }
             }
 #pragma unroll
@@ -700,10 +716,17 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
     __syncthreads();  // red and smem are reused by the next tile of a persistent block
 }
 
+// Static 16-bit leaves that split their operands while staging fit in 128
+// VGPRs, so four blocks share a CU (one wave per SIMD each); the other
+// variants, and the persistent kernel (whose tile loop needs more registers),
+// keep the compiler's register choice.
+template <int B, int P, bool PS>
+constexpr int leaf_min_waves() { return (is16(P) && !PS && B <= 64) ? 4 : 1; }
+
 // Static schedule: one block per tile; block x runs on XCD x mod 8 and takes
 // tile (x mod 8) * chunk + x / 8, so each XCD walks a contiguous tile range.
 template <int B, int P, typename TA, typename TC, bool SP2, bool PS>
-__global__ void __launch_bounds__(256) k_leaf(const ProdDesc* __restrict__ desc, int nprod, int64_t total,
+__global__ void __launch_bounds__(256, (leaf_min_waves<B, P, PS>())) k_leaf(const ProdDesc* __restrict__ desc, int nprod, int64_t total,
                                               int64_t chunk, const int* __restrict__ branch,
                                               const int* __restrict__ active) {
     __shared__ __attribute__((aligned(16))) char smem[Geo<B, P>::SMEM];
