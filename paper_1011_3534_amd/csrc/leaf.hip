@@ -47,12 +47,17 @@ struct Geo {
     static_assert(!is16(P) || KC == 32, "the 16-bit LDS swizzle assumes 32-wide k-chunks");
 };
 
-// 16-bit LDS rows (A rows and B^T rows, 32 k = four 16-byte groups): group g
-// of row r sits at slot g ^ ((r >> 2) & 3).  Sixteen consecutive rows then
-// cover all 64 banks both for the MFMA fragment reads (16 rows, one group)
-// and for the stores (4 rows x 4 groups, or 16 rows x one group), with no
-// padding.
-__device__ inline int sw16(int r, int k) { return (((k >> 3) ^ ((r >> 2) & 3)) << 3) | (k & 7); }
+// 16-bit LDS rows (A rows and B^T rows, 32 k = four 16-byte groups; two
+// rows per 128 bytes): group g of row r sits at slot g ^ q(r) with
+// q(r) = ((r >> 1) & 3) ^ ((r >> 3) & 1).  Eight consecutive rows at one
+// group fill 128 bytes of banks and sixteen fill 256, and so do two (four)
+// rows at all four groups, so the MFMA fragment reads (16 rows, one group)
+// and both stores (4 rows x 4 groups, or 64 rows x one group) are free of
+// bank conflicts whether the LDS serves 16-byte accesses 8 or 16 lanes at a
+// time, with no padding.
+__device__ inline int sw16(int r, int k) {
+    return (((k >> 3) ^ ((r >> 1) & 3) ^ ((r >> 3) & 1)) << 3) | (k & 7);
+}
 
 // Kept K of one segment of a tile's mask (four words), with the FP16 scale
 // exponents of A_IK and B_KJ.
@@ -443,14 +448,22 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         // step t = (list entry t / NCH, k-chunk t % NCH); T is uniform, and
         // the loop control stays in scalar registers
         const int T = __builtin_amdgcn_readfirstlane(nk * NCH);
-        // MFMA on the chunk of step t in LDS buffer bf; at the last chunk of a
-        // leaf product its fresh accumulator is added to the tile sum
-        // (two-level summation: the rounding error does not grow with the
-        // number of kept products)
-        auto compute = [&](int bf, int t) {
-            if constexpr (P != kF64) {
+        // MFMA on the chunk in LDS buffer bf.  No branches: the scheduler can
+        // interleave it with the split and store of the next chunk.
+        auto mma = [&](int bf) {
+            if constexpr (P != kF64)
                 chunk_mma<B, P, Acc>(smem + bf * G::BUF_BYTES, part, lane, wr, wc);
-                if (t % NCH == NCH - 1) {
+            else
+                chunk_mma<B, P, Acc>(smem + bf * G::BUF_BYTES, acc, lane, wr, wc);
+        };
+        // After the last chunk of a leaf product (step t; `odd`: t is odd, which
+        // decides it at compile time for one or two chunks per product) its
+        // fresh accumulator is added to the tile sum (two-level summation: the
+        // rounding error does not grow with the number of kept products).
+        auto fin = [&](int t, bool odd) {
+            if constexpr (P != kF64) {
+                const bool last = NCH == 1 || (NCH == 2 ? odd : t % NCH == NCH - 1);
+                if (last) {
                     const int un = isf16(P) ? __builtin_amdgcn_readfirstlane(
                                                   -((int)kl->sa[t / NCH] + (int)kl->sb[t / NCH]))
                                             : 0;
@@ -485,8 +498,6 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
 #pragma unroll
                         for (int j = 0; j < R; ++j) part[i][j] = Acc{0, 0, 0, 0};
                 }
-            } else {
-                chunk_mma<B, P, Acc>(smem + bf * G::BUF_BYTES, acc, lane, wr, wc);
             }
         };
         // Two register stages keep two chunks of loads in flight while LDS
@@ -525,12 +536,14 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
                                      rsrc((const TA*)d.B + tb + (int64_t)ch * KC * B, nbb), tid);
             }
         };
-        // (step t's FP16 scales apply when splitting on the fly)
+        // (step t's FP16 scales apply when splitting on the fly; a store past
+        // the last step stores the empty stage, with the last entry's scales)
         auto sto = [&](const St& st, int bf, int t) {
             if constexpr (is16(P) && !PRESPLIT) {
-                const int e = t / NCH;
-                stage16c_store<B, P>(st, smem + bf * G::BUF_BYTES, tid, isf16(P) ? (int)kl->sa[e] : 0,
-                                     isf16(P) ? (int)kl->sb[e] : 0);
+                const int e = min(t / NCH, nk - 1);
+                stage16c_store<B, P>(st, smem + bf * G::BUF_BYTES, tid,
+                                     isf16(P) ? __builtin_amdgcn_readfirstlane((int)kl->sa[e]) : 0,
+                                     isf16(P) ? __builtin_amdgcn_readfirstlane((int)kl->sb[e]) : 0);
             } else if constexpr (is16(P)) {
                 stage16_store<B, P>(st, smem + bf * G::BUF_BYTES, tid);
             } else {
@@ -554,23 +567,27 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         // (scheduling barriers keep each stage's loads ahead of the MFMA work
         // they overlap; no exit follows a refill of s0 before s1 is refilled,
         // so on every path s0's loads are older than s1's)
+        // (each half step runs the MFMA of one chunk, the split and store of
+        // the next, which no branch separates, and then the product's finish;
+        // the store in the first half runs also when it is past the end)
         for (int t = 0;; t += 2) {
             __builtin_amdgcn_sched_barrier(0);
-            compute(buf, t);
-            __builtin_amdgcn_sched_barrier(0);
-            if (t + 1 >= T) break;
+            mma(buf);
             sto(s0, buf ^ 1, t + 1);
+            fin(t, false);
+            if (t + 1 >= T) break;
             __syncthreads();
             buf ^= 1;
             if (t + 2 >= T) {
-                compute(buf, t + 1);
+                mma(buf);
+                fin(t + 1, true);
                 break;
             }
             ld(s0, t + 3);
             __builtin_amdgcn_sched_barrier(0);
-            compute(buf, t + 1);
-            __builtin_amdgcn_sched_barrier(0);
+            mma(buf);
             sto(s1, buf ^ 1, t + 2);
+            fin(t + 1, true);
             __syncthreads();
             buf ^= 1;
             ld(s1, t + 4);
