@@ -13,12 +13,12 @@ namespace {
 
 constexpr double kStagBelow = 0.1;
 
-// Fixed-order FP64 sum of x[0..count) by one block of 1024 threads.
+// Fixed-order FP64 sum of x[0..count) by one block of 1024 threads: thread t
+// adds x[t], x[t + 1024], ... (coalesced), then a pairwise tree.
 __device__ double block_sum_fixed(const double* x, int64_t count, double* red) {
     const int t = threadIdx.x;
-    const int64_t per = (count + blockDim.x - 1) / blockDim.x;
     double s = 0.0;
-    for (int64_t i = t * per; i < (t + 1) * per && i < count; ++i) s += x[i];
+    for (int64_t i = t; i < count; i += blockDim.x) s += x[i];
     red[t] = s;
     __syncthreads();
     for (int h = blockDim.x / 2; h >= 1; h >>= 1) {
@@ -31,17 +31,29 @@ __device__ double block_sum_fixed(const double* x, int64_t count, double* red) {
 }
 
 // One wave per row i: d_i = h_ii, r_i = sum_{j != i} |h_ij|  ->  lo = d - r, hi = d + r.
-__global__ void __launch_bounds__(256) k_gersh_rows(const float* __restrict__ H, int64_t n, int b, int64_t nb,
-                                                    double* __restrict__ lo, double* __restrict__ hi) {
+// Tiles of the row's tile row with squared norm 0 hold only zeros and are not
+// read: the wave tests 64 tile norms at a time and visits the others.
+__global__ void __launch_bounds__(256) k_gersh_rows(const float* __restrict__ H, const double* __restrict__ S,
+                                                    int64_t n, int b, int64_t nb, double* __restrict__ lo,
+                                                    double* __restrict__ hi) {
     const int lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
     const int64_t I = i / b, r = i % b;
     double acc = 0.0, d = 0.0;
-    for (int64_t c = lane; c < n; c += 64) {
-        const double v = (double)H[((I * nb + c / b) * b + r) * b + (c % b)];
-        if (c == i) d = v;
-        else acc += fabs(v);
+    for (int64_t base = 0; base < nb; base += 64) {
+        const int64_t kc = base + lane;
+        unsigned long long m = __ballot(kc < nb && S[I * nb + kc] != 0.0);
+        while (m) {
+            const int64_t K = base + __builtin_ctzll(m);
+            m &= m - 1;
+            const float* row = H + ((I * nb + K) * b + r) * b;
+            for (int c = lane; c < b; c += 64) {
+                const double v = (double)row[c];
+                if (K * b + c == i) d = v;
+                else acc += fabs(v);
+            }
+        }
     }
     for (int h = 32; h >= 1; h >>= 1) {
         acc += __shfl_down(acc, h, 64);
@@ -190,20 +202,36 @@ __global__ void __launch_bounds__(1024) k_sp2_finalize(const double* part, int64
     if (m + 1 >= st->max_iter) st->active = 0;
 }
 
-// E = tr(P H) = sum over tiles (I,K) of <P_IK, (H_KI)^T>, one wave per tile.
-__global__ void __launch_bounds__(64) k_energy_tiles(const float* __restrict__ P, const float* __restrict__ H, int b,
-                                                     int64_t nb, double* __restrict__ out) {
+// E = tr(P H) = sum over tiles (I,K) of <P_IK, (H_KI)^T>, one block per tile.
+// A pair with a zero tile (squared norm 0: every element is zero) adds
+// exactly 0 and is not read; otherwise H_KI is staged in LDS, so both tiles
+// are read along their rows, and the block adds the exact FP64 products.
+template <int B>
+__global__ void __launch_bounds__(256) k_energy_tiles(const float* __restrict__ P, const float* __restrict__ H,
+                                                      const double* __restrict__ SP, const double* __restrict__ SH,
+                                                      int64_t nb, double* __restrict__ out) {
+    __shared__ float hs[B][B + 1];
+    __shared__ double red[4];
     const int64_t tile = blockIdx.x;
     const int64_t I = tile / nb, K = tile % nb;
-    const float* p = P + tile * (int64_t)b * b;
-    const float* h = H + (K * nb + I) * (int64_t)b * b;
+    const int64_t th = K * nb + I;
+    if (SP[tile] == 0.0 || SH[th] == 0.0) {
+        if (threadIdx.x == 0) out[tile] = 0.0;
+        return;
+    }
+    const float* p = P + tile * (int64_t)B * B;
+    const float* h = H + th * (int64_t)B * B;
+    for (int e = threadIdx.x; e < B * B; e += 256) hs[e / B][e % B] = h[e];
+    __syncthreads();
     double s = 0.0;
-    for (int e = threadIdx.x; e < b * b; e += 64) {
-        const int r = e / b, c = e % b;
-        s += (double)p[r * b + c] * (double)h[c * b + r];
+    for (int e = threadIdx.x; e < B * B; e += 256) {
+        const int r = e / B, c = e % B;
+        s = __fma_rn((double)p[e], (double)hs[c][r], s);
     }
     for (int d = 32; d >= 1; d >>= 1) s += __shfl_down(s, d, 64);
-    if (threadIdx.x == 0) out[tile] = s;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[tile] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 __global__ void __launch_bounds__(1024) k_sum_to(const double* x, int64_t count, double* out) {
@@ -221,8 +249,8 @@ __global__ void k_trace_of(const double* part, int64_t nb, double* out) {
 }  // namespace
 
 hipError_t launch_gershgorin(const spamm_matrix* H, double* lo, double* hi, Sp2State* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_gersh_rows, dim3((unsigned)((H->n + 3) / 4)), dim3(256), 0, s, (const float*)H->tiles, H->n,
-                       H->b, H->nb, lo, hi);
+    hipLaunchKernelGGL(k_gersh_rows, dim3((unsigned)((H->n + 3) / 4)), dim3(256), 0, s, (const float*)H->tiles,
+                       H->norms, H->n, H->b, H->nb, lo, hi);
     hipLaunchKernelGGL(k_gersh_reduce, dim3(1), dim3(1024), 0, s, lo, hi, H->n, st);
     return hipGetLastError();
 }
@@ -255,8 +283,14 @@ hipError_t launch_sp2_finalize(const double* part, int64_t nb, const unsigned lo
 hipError_t launch_energy(const spamm_matrix* P, const spamm_matrix* H, double* tile_part, double* out,
                          hipStream_t s) {
     const int64_t tiles = P->nb * P->nb;
-    hipLaunchKernelGGL(k_energy_tiles, dim3((unsigned)tiles), dim3(64), 0, s, (const float*)P->tiles,
-                       (const float*)H->tiles, P->b, P->nb, tile_part);
+    const float* pt = (const float*)P->tiles;
+    const float* ht = (const float*)H->tiles;
+    switch (P->b) {
+        case 32: hipLaunchKernelGGL(k_energy_tiles<32>, dim3((unsigned)tiles), dim3(256), 0, s, pt, ht, P->norms, H->norms, P->nb, tile_part); break;
+        case 64: hipLaunchKernelGGL(k_energy_tiles<64>, dim3((unsigned)tiles), dim3(256), 0, s, pt, ht, P->norms, H->norms, P->nb, tile_part); break;
+        case 128: hipLaunchKernelGGL(k_energy_tiles<128>, dim3((unsigned)tiles), dim3(256), 0, s, pt, ht, P->norms, H->norms, P->nb, tile_part); break;
+        default: return hipErrorInvalidValue;
+    }
     hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(1024), 0, s, tile_part, tiles, out);
     return hipGetLastError();
 }
