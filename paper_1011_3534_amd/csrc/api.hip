@@ -274,7 +274,8 @@ static bool split_current(const spamm_matrix* M, int kind) {
 // Shared by multiply and SP2: cull + leaf products + C pyramid, all enqueued.
 spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C, double tau,
                              spamm_leaf_prec prec, hipStream_t s, int want_bound, int sp2, const int* d_branch,
-                             const int* d_active, ProdDesc* d_desc_override) {
+                             const int* d_active, ProdDesc* d_desc_override, uint32_t* sp2_list,
+                             Sp2State* sp2_state) {
     ProductScratch* ps = C->ps;
     ProdDesc* d_desc = d_desc_override;
     // 16-bit leaves read the operands' split tiles when both are current
@@ -312,6 +313,12 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
     lp.d_branch = d_branch;
     lp.d_active = d_active;
     lp.presplit = presplit;
+    if (sp2_list) {
+        // SP2: the leaf launch visits only the C tiles that need a write
+        SPAMM_HIP(launch_sp2_tiles(d_desc, C->nb, sp2_list, sp2_state, d_active, s));
+        lp.list = sp2_list;
+        lp.list_count = &sp2_state->list_count;
+    }
     if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[1], s));
     SPAMM_HIP(launch_leaf_typed(d_desc, lp, A->dt == SPAMM_F64, s));
     if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[2], s));
@@ -693,6 +700,7 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
     if (v != SPAMM_OK) return v;
     if (prec == SPAMM_LEAF_F64 || H->dt != SPAMM_F32)
         return set_error(SPAMM_EUNSUPPORTED, "SP2 runs on FP32 tiles with FP32 or split 16-bit leaves");
+    if (H->nb * H->nb > (int64_t)UINT32_MAX) return set_error(SPAMM_EUNSUPPORTED, "SP2 needs nb^2 < 2^32 tiles");
     hipStream_t s = (hipStream_t)stream;
     (void)num_cus();  // device query outside the capture
     spamm_matrix* X[2] = {nullptr, nullptr};
@@ -708,7 +716,8 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
     const size_t off_hi = off_lo + (((size_t)H->n * 8 + 255) & ~(size_t)255);
     const size_t off_st = off_hi + (((size_t)H->n * 8 + 255) & ~(size_t)255);
     const size_t off_e = off_st + ((sizeof(Sp2State) + 255) & ~(size_t)255);
-    const size_t total = off_e + (size_t)(nb * nb + 1) * 8;
+    const size_t off_list = off_e + (((size_t)(nb * nb + 1) * 8 + 255) & ~(size_t)255);
+    const size_t total = off_list + (size_t)nb * nb * 4;
     auto cleanup = [&]() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -739,6 +748,7 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
     double* ghi = (double*)(base + off_hi);
     Sp2State* st = (Sp2State*)(base + off_st);
     double* etile = (double*)(base + off_e);
+    uint32_t* tile_list = (uint32_t*)(base + off_list);
     double* eout = etile + nb * nb;
     static thread_local Sp2State h;
     std::memset(&h, 0, sizeof h);
@@ -773,7 +783,10 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
     for (int m = 0; m < max_iter && r == SPAMM_OK; ++m) {
         spamm_matrix* src = X[m & 1];
         spamm_matrix* dst = X[(m + 1) & 1];
-        r = enqueue_product(src, src, dst, tau, prec, cs, 0, 1, d_branch, d_active, dst->ps->desc);
+        // tau > 0: the leaf launch visits the listed tiles only; at tau = 0
+        // every tile has kept products and the static full grid is faster
+        r = enqueue_product(src, src, dst, tau, prec, cs, 0, 1, d_branch, d_active, dst->ps->desc,
+                            tau > 0.0 ? tile_list : nullptr, st);
         if (r == SPAMM_OK) {
             e = launch_sp2_finalize(part, nb, &dst->ps->ctr->survivors[0][0], st, m, cs);
             if (e != hipSuccess) r = hip_error(e, "sp2 finalize launch");

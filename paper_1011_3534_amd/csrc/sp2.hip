@@ -165,6 +165,7 @@ __global__ void __launch_bounds__(1024) k_sp2_start(const double* part, int64_t 
         st->converged = 0;
         st->stagnated = 0;
         st->result_step = 0;
+        st->list_count = 0;
     }
 }
 
@@ -183,6 +184,7 @@ __global__ void __launch_bounds__(1024) k_sp2_finalize(const double* part, int64
     st->br[m] = st->branch;
     st->tasks[m] = *survivors0;
     st->iter = m + 1;
+    st->list_count = 0;  // the next step lists its tiles afresh
     if (e <= st->tol) {
         st->converged = 1;
         st->result_step = m + 1;
@@ -234,6 +236,36 @@ __global__ void __launch_bounds__(256) k_energy_tiles(const float* __restrict__ 
     if (threadIdx.x == 0) out[tile] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// The C tiles step m must write: those with a kept product, those whose X
+// tile is non-zero (2X - X^2 needs it), and those whose stored values are
+// not already known to be zero (exponent -128).  Every other tile keeps its
+// zeros and zero norm, and gets zero SP2 partials here.  The list order
+// depends on the atomics; each tile's result does not.
+__global__ void __launch_bounds__(256) k_sp2_tiles(const ProdDesc* __restrict__ desc, uint32_t* __restrict__ list,
+                                                   Sp2State* st, const int* active) {
+    if (active && *active == 0) return;
+    const ProdDesc& d = *desc;
+    const int64_t nb = d.nb, tiles = nb * nb;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool need = false;
+    if (t < tiles) {
+        uint64_t any = 0;
+        for (int k = 0; k < d.W; ++k) any |= d.mask[t * d.W + k];
+        need = any != 0 || d.SA[t] != 0.0 || d.eC[t] != -128;
+        if (!need) {
+            d.sp2_part[t] = 0.0;
+            if (t / nb == t % nb) d.sp2_part[tiles + t / nb] = 0.0;
+        }
+    }
+    const unsigned long long m = __ballot(need);
+    if (m == 0) return;
+    const int lane = threadIdx.x & 63;
+    unsigned base = 0;
+    if (lane == 0) base = atomicAdd(&st->list_count, (unsigned)__popcll(m));
+    base = (unsigned)__shfl((int)base, 0, 64);
+    if (need) list[base + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)t;
+}
+
 __global__ void __launch_bounds__(1024) k_sum_to(const double* x, int64_t count, double* out) {
     __shared__ double red[1024];
     const double s = block_sum_fixed(x, count, red);
@@ -247,6 +279,13 @@ __global__ void k_trace_of(const double* part, int64_t nb, double* out) {
 }
 
 }  // namespace
+
+hipError_t launch_sp2_tiles(const ProdDesc* d_desc, int64_t nb, uint32_t* list, Sp2State* st, const int* active,
+                            hipStream_t s) {
+    const int64_t tiles = nb * nb;
+    hipLaunchKernelGGL(k_sp2_tiles, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, s, d_desc, list, st, active);
+    return hipGetLastError();
+}
 
 hipError_t launch_gershgorin(const spamm_matrix* H, double* lo, double* hi, Sp2State* st, hipStream_t s) {
     hipLaunchKernelGGL(k_gersh_rows, dim3((unsigned)((H->n + 3) / 4)), dim3(256), 0, s, (const float*)H->tiles,

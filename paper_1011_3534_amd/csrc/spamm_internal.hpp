@@ -205,6 +205,8 @@ struct LeafPlan {
     const uint32_t* order = nullptr;       // persistent launch: tile order (NULL = identity)
     unsigned long long* queue = nullptr;   // persistent launch: zeroed queue counter (NULL = static grid)
     bool presplit = false;                 // 16-bit leaves: every operand has current split tiles
+    const uint32_t* list = nullptr;        // SP2: C tiles to visit (persistent launch over the list)
+    const unsigned* list_count = nullptr;  //   and their device-side count
 };
 hipError_t launch_lpt_order(const ProdDesc* d_desc, int nprod, int64_t total, int maxc, uint32_t* counts,
                             uint32_t* hist, uint32_t* offs, uint32_t* order, unsigned long long* queue,
@@ -225,6 +227,8 @@ struct Sp2State {
     double idem[SPAMM_SP2_MAX_ITER];
     int br[SPAMM_SP2_MAX_ITER];
     unsigned long long tasks[SPAMM_SP2_MAX_ITER];
+    unsigned list_count;  // C tiles of the current step that the leaf launch visits
+    unsigned pad2_;
 };
 hipError_t launch_gershgorin(const spamm_matrix* H, double* lo, double* hi, Sp2State* st, hipStream_t s);
 hipError_t launch_sp2_init(const spamm_matrix* H, spamm_matrix* X, double* part, Sp2State* st, hipStream_t s);
@@ -232,10 +236,13 @@ hipError_t launch_sp2_finalize(const double* part, int64_t nb, const unsigned lo
                                int m, hipStream_t s);
 hipError_t launch_energy(const spamm_matrix* P, const spamm_matrix* H, double* tile_part, double* out,
                          hipStream_t s);
+hipError_t launch_sp2_tiles(const ProdDesc* d_desc, int64_t nb, uint32_t* list, Sp2State* st, const int* active,
+                            hipStream_t s);
 
 // api.hip: cull + leaf products + result pyramid of one product, enqueued
 spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C, double tau,
                              spamm_leaf_prec prec, hipStream_t s, int want_bound, int sp2, const int* d_branch,
-                             const int* d_active, ProdDesc* d_desc_override);
+                             const int* d_active, ProdDesc* d_desc_override, uint32_t* sp2_list = nullptr,
+                             Sp2State* sp2_state = nullptr);
 
 }  // namespace spamm
