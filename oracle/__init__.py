@@ -52,14 +52,14 @@ def _load():
     lib.orc_norm_parent.restype = None
     lib.orc_num_levels.argtypes = [i64]
     lib.orc_num_levels.restype = i32
-    lib.orc_spamm_recursive.argtypes = [_DP, _DP, i64, i32, dbl, _DP, _U64P, i64, _I64P]
+    lib.orc_spamm_recursive.argtypes = [_DP, _DP, i64, i32, dbl, i32, _DP, _U64P, i64, _I64P]
     lib.orc_spamm_recursive.restype = i64
     lib.orc_spamm_flat.argtypes = [_DP, _DP, i64, i32, dbl, i64, i64, _DP]
     lib.orc_spamm_flat.restype = i64
     lib.orc_tasks_flat.argtypes = [_DP, _DP, i64, dbl, _U64P, i64, _DP]
     lib.orc_tasks_flat.restype = i64
-    lib.orc_count_hierarchical.argtypes = [_DP, _DP, i64, dbl, _I64P]
-    lib.orc_count_hierarchical.restype = i64
+    lib.orc_tasks_hierarchical.argtypes = [_DP, _DP, i64, dbl, i32, _U64P, i64, _I64P]
+    lib.orc_tasks_hierarchical.restype = i64
     lib.orc_dense_matmul.argtypes = [_DP, _DP, i64, _DP]
     lib.orc_dense_matmul.restype = None
     lib.orc_num_threads.argtypes = []
@@ -114,8 +114,11 @@ def norm_pyramid(a, b: int) -> list[np.ndarray]:
     return levels
 
 
-def spamm_recursive(a, bm, b: int, tau: float, want_keys: bool = False):
-    """Eq. (4) literally.  Returns (C, T, keys-or-None, kept-per-tier)."""
+def spamm_recursive(a, bm, b: int, tau: float, want_keys: bool = False, depth_scaled: bool = False):
+    """Eq. (4) literally.  Returns (C, T, keys-or-None, kept-per-tier).
+
+    depth_scaled: the threshold of a sub-product is its parent's divided by 8
+    (tau at the root), the rigorous variant discussed in section 2."""
     a, bm = _f64(a), _f64(bm)
     n = a.shape[0]
     nb = -(-n // b)
@@ -124,7 +127,7 @@ def spamm_recursive(a, bm, b: int, tau: float, want_keys: bool = False):
     kept = np.zeros(L + 1, dtype=np.int64)
     cap = nb ** 3 if want_keys else 0
     keys = np.empty(max(cap, 1), dtype=np.uint64)
-    t = _load().orc_spamm_recursive(_p(a), _p(bm), n, b, float(tau), _p(c),
+    t = _load().orc_spamm_recursive(_p(a), _p(bm), n, b, float(tau), int(bool(depth_scaled)), _p(c),
                                     _p(keys, _U64P) if want_keys else None, cap, _p(kept, _I64P))
     if t < 0:
         raise ValueError(f"orc_spamm_recursive failed ({t})")
@@ -159,13 +162,30 @@ def tasks_flat(SA, SB, tau: float, want_keys: bool = True):
     return (keys[:t].copy() if want_keys else int(t)), float(bound.value)
 
 
-def count_hierarchical(SA, SB, tau: float):
+def count_hierarchical(SA, SB, tau: float, depth_scaled: bool = False):
     """Kept octree nodes per tier (tier 0 = leaf triples) from leaf norms."""
     SA, SB = _f64(SA), _f64(SB)
     nb = SA.shape[0]
     kept = np.zeros(num_levels(nb) + 1, dtype=np.int64)
-    t = _load().orc_count_hierarchical(_p(SA), _p(SB), nb, float(tau), _p(kept, _I64P))
+    t = _load().orc_tasks_hierarchical(_p(SA), _p(SB), nb, float(tau), int(bool(depth_scaled)), None, 0,
+                                       _p(kept, _I64P))
     return int(t), kept
+
+
+def tasks_hierarchical(SA, SB, tau: float, depth_scaled: bool = False):
+    """Kept leaf triples of the recursion (Eq. 4, products left out) from leaf
+    norms, as sorted keys, with the kept nodes per tier."""
+    SA, SB = _f64(SA), _f64(SB)
+    nb = SA.shape[0]
+    kept = np.zeros(num_levels(nb) + 1, dtype=np.int64)
+    lib = _load()
+    t = lib.orc_tasks_hierarchical(_p(SA), _p(SB), nb, float(tau), int(bool(depth_scaled)), None, 0,
+                                   _p(kept, _I64P))
+    keys = np.empty(max(t, 1), dtype=np.uint64)
+    t2 = lib.orc_tasks_hierarchical(_p(SA), _p(SB), nb, float(tau), int(bool(depth_scaled)), _p(keys, _U64P), t,
+                                    _p(kept, _I64P))
+    assert t2 == t
+    return np.sort(keys[:t]), kept
 
 
 def dense_matmul(a, bm) -> np.ndarray:

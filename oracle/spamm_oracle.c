@@ -159,7 +159,7 @@ typedef struct {
     const double *a, *bm;
     int64_t n;
     int32_t b;
-    double tau2;
+    int32_t depth_scaled;  /* 1: tau_{k+1} = tau_k / 8 below the root (section 2) */
     const pyramid *pa, *pb;
     double* c;
     double* P;
@@ -168,13 +168,15 @@ typedef struct {
     int64_t* level_kept;
 } rec_ctx;
 
-/* Eq. (4), literally: test the pair, multiply densely at the finest tier,
- * otherwise recurse into the 8 sub-products (k2 innermost, so every C tile
- * receives its contributions in ascending K). */
-static void spamm_rec(rec_ctx* x, int32_t l, int64_t I, int64_t J, int64_t K) {
+/* Eq. (4), literally: test the pair against the threshold tau of its depth,
+ * multiply densely at the finest tier, otherwise recurse into the 8
+ * sub-products (k2 innermost, so every C tile receives its contributions in
+ * ascending K).  With the depth-scaled schedule the sub-products are tested
+ * against tau / 8 (the rigorous variant of section 2); otherwise tau stays. */
+static void spamm_rec(rec_ctx* x, int32_t l, int64_t I, int64_t J, int64_t K, double tau) {
     double sa = x->pa->S[l][I * x->pa->m[l] + K];
     double sb = x->pb->S[l][K * x->pb->m[l] + J];
-    if (sa * sb < x->tau2) return;
+    if (sa * sb < tau * tau) return;
     if (x->level_kept) x->level_kept[l] += 1;
     if (l == 0) {
         leaf_product_add(x->a, x->bm, x->n, x->b, I, J, K, x->c, x->P);
@@ -183,11 +185,12 @@ static void spamm_rec(rec_ctx* x, int32_t l, int64_t I, int64_t J, int64_t K) {
         return;
     }
     int64_t mc = x->pa->m[l - 1];
+    double tau_child = x->depth_scaled ? tau / 8.0 : tau;
     for (int i2 = 0; i2 < 2; ++i2)
         for (int j2 = 0; j2 < 2; ++j2)
             for (int k2 = 0; k2 < 2; ++k2) {
                 int64_t Ic = 2 * I + i2, Jc = 2 * J + j2, Kc = 2 * K + k2;
-                if (Ic < mc && Jc < mc && Kc < mc) spamm_rec(x, l - 1, Ic, Jc, Kc);
+                if (Ic < mc && Jc < mc && Kc < mc) spamm_rec(x, l - 1, Ic, Jc, Kc, tau_child);
             }
 }
 
@@ -196,7 +199,8 @@ static void spamm_rec(rec_ctx* x, int32_t l, int64_t I, int64_t J, int64_t K) {
  * (optional, L+1 entries) counts the kept nodes per tier (0 = leaf).
  * Returns the number of leaf products, or a negative error. */
 int64_t orc_spamm_recursive(const double* a, const double* bm, int64_t n, int32_t b, double tau,
-                            double* c, uint64_t* keys, int64_t keys_cap, int64_t* level_kept) {
+                            int32_t depth_scaled, double* c, uint64_t* keys, int64_t keys_cap,
+                            int64_t* level_kept) {
     if (n < 1 || !is_pow2(b) || !(tau >= 0.0) || isinf(tau)) return -1;
     pyramid pa, pb;
     memset(&pa, 0, sizeof pa);
@@ -207,10 +211,10 @@ int64_t orc_spamm_recursive(const double* a, const double* bm, int64_t n, int32_
         return -2;
     }
     memset(c, 0, sizeof(double) * (size_t)(n * n));
-    rec_ctx x = {a, bm, n, b, tau * tau, &pa, &pb, c, NULL, keys, keys_cap, 0, level_kept};
+    rec_ctx x = {a, bm, n, b, depth_scaled, &pa, &pb, c, NULL, keys, keys_cap, 0, level_kept};
     x.P = (double*)malloc(sizeof(double) * (size_t)b * (size_t)b);
     if (level_kept) memset(level_kept, 0, sizeof(int64_t) * (size_t)(pa.L + 1));
-    spamm_rec(&x, pa.L, 0, 0, 0);
+    spamm_rec(&x, pa.L, 0, 0, 0, tau);
     free(x.P);
     free_pyramid(&pa);
     free_pyramid(&pb);
@@ -278,30 +282,43 @@ int64_t orc_tasks_flat(const double* SA, const double* SB, int64_t nb, double ta
     return count;
 }
 
-/* Per-tier kept counts of the hierarchical test alone (no products): the
- * number of product-space octree nodes that pass at every tier.  level_kept
- * has L+1 entries.  Returns the leaf count. */
-static int64_t count_rec(const pyramid* pa, const pyramid* pb, double tau2, int32_t l,
-                         int64_t I, int64_t J, int64_t K, int64_t* level_kept) {
-    double sa = pa->S[l][I * pa->m[l] + K];
-    double sb = pb->S[l][K * pb->m[l] + J];
-    if (sa * sb < tau2) return 0;
-    level_kept[l] += 1;
-    if (l == 0) return 1;
-    int64_t mc = pa->m[l - 1], t = 0;
+/* The hierarchical test alone (no products): the product-space octree nodes
+ * that pass at every tier, with the threshold schedule of spamm_rec.
+ * level_kept has L+1 entries; keys (optional) receives the kept leaf triples
+ * in visit order.  Returns the leaf count. */
+typedef struct {
+    const pyramid *pa, *pb;
+    int32_t depth_scaled;
+    int64_t* level_kept;
+    uint64_t* keys;
+    int64_t cap, count;
+} count_ctx;
+
+static void count_rec(count_ctx* x, int32_t l, int64_t I, int64_t J, int64_t K, double tau) {
+    double sa = x->pa->S[l][I * x->pa->m[l] + K];
+    double sb = x->pb->S[l][K * x->pb->m[l] + J];
+    if (sa * sb < tau * tau) return;
+    x->level_kept[l] += 1;
+    if (l == 0) {
+        if (x->keys && x->count < x->cap) x->keys[x->count] = pack_key(I, J, K);
+        x->count += 1;
+        return;
+    }
+    int64_t mc = x->pa->m[l - 1];
+    double tau_child = x->depth_scaled ? tau / 8.0 : tau;
     for (int i2 = 0; i2 < 2; ++i2)
         for (int j2 = 0; j2 < 2; ++j2)
             for (int k2 = 0; k2 < 2; ++k2) {
                 int64_t Ic = 2 * I + i2, Jc = 2 * J + j2, Kc = 2 * K + k2;
-                if (Ic < mc && Jc < mc && Kc < mc) t += count_rec(pa, pb, tau2, l - 1, Ic, Jc, Kc, level_kept);
+                if (Ic < mc && Jc < mc && Kc < mc) count_rec(x, l - 1, Ic, Jc, Kc, tau_child);
             }
-    return t;
 }
 
-/* Hierarchical task count from leaf norms only (the recursion of Eq. 4 with
- * the products left out).  level_kept: L+1 entries, tier 0 = leaves. */
-int64_t orc_count_hierarchical(const double* SA, const double* SB, int64_t nb, double tau,
-                               int64_t* level_kept) {
+/* Hierarchical kept leaf triples from leaf norms only (the recursion of
+ * Eq. 4 with the products left out).  level_kept: L+1 entries, tier 0 =
+ * leaves; keys optional (up to cap). */
+int64_t orc_tasks_hierarchical(const double* SA, const double* SB, int64_t nb, double tau,
+                               int32_t depth_scaled, uint64_t* keys, int64_t cap, int64_t* level_kept) {
     pyramid pa, pb;
     memset(&pa, 0, sizeof pa);
     memset(&pb, 0, sizeof pb);
@@ -321,10 +338,11 @@ int64_t orc_count_hierarchical(const double* SA, const double* SB, int64_t nb, d
         m = ceil_div(m, 2);
     }
     memset(level_kept, 0, sizeof(int64_t) * (size_t)(pa.L + 1));
-    int64_t t = count_rec(&pa, &pb, tau * tau, pa.L, 0, 0, 0, level_kept);
+    count_ctx x = {&pa, &pb, depth_scaled, level_kept, keys, cap, 0};
+    count_rec(&x, pa.L, 0, 0, 0, tau);
     free_pyramid(&pa);
     free_pyramid(&pb);
-    return t;
+    return x.count;
 }
 
 /* Plain dense product C = A B (i, k, j loop order), the tau = 0 limit. */

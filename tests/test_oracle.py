@@ -300,3 +300,95 @@ def test_ragged_sizes_flat_equals_recursive():
         c1, t1, _, _ = oracle.spamm_recursive(a, a.T.copy(), 16, 0.05)
         c2, t2 = oracle.spamm_flat(a, a.T.copy(), 16, 0.05)
         assert t1 == t2 and np.array_equal(c1, c2)
+
+
+# ---------------------------------------------------------------- depth-scaled threshold (section 2)
+# The paper's rigorous variant lowers tau by a factor 8 per level below the
+# root: a node at depth k is tested against tau / 8^k and kept only if every
+# ancestor was kept.  These pins do not use the recursion's code.
+
+def _ancestor_chain_keys(a, bm, b, tau):
+    """Brute force: a leaf triple is kept iff, at every depth k from the root,
+    its ancestor (I >> l, J >> l, K >> l) on tier l = L - k passes against
+    tau / 8^k, with tier norms summed directly from the matrix (numpy)."""
+    n = a.shape[0]
+    nb = -(-n // b)
+    L = oracle.num_levels(nb)
+    keys = set()
+    for I in range(nb):
+        for J in range(nb):
+            for K in range(nb):
+                ok = True
+                for l in range(L, -1, -1):
+                    s = b << l                     # side of a tier-l block
+                    i, j, k = (I >> l) * s, (J >> l) * s, (K >> l) * s
+                    na = float(np.sum(a[i:i + s, k:k + s] ** 2))
+                    nbm = float(np.sum(bm[k:k + s, j:j + s] ** 2))
+                    t = tau / 8.0 ** (L - l)
+                    if na * nbm < t * t:
+                        ok = False
+                        break
+                if ok:
+                    keys.add((I, J, K))
+    return keys
+
+
+@pytest.mark.parametrize("n,b,tau", [(32, 4, 3e-2), (40, 4, 1e-2), (64, 8, 1e-3)])
+def test_depth_scaled_matches_ancestor_brute_force(n, b, tau):
+    # catches: the wrong depth for the divisor (tier instead of depth), dividing
+    # by 4 or 64 instead of 8 per level, a child tested against its parent's
+    # threshold, padding blocks kept or lost
+    a = si.exp_decay(n, 0.7, 5)
+    bm = si.algebraic_decay(n, 2.0, 6, np.float64)
+    want = _ancestor_chain_keys(a, bm, b, tau)
+    _, T, keys, _ = oracle.spamm_recursive(a, bm, b, tau, want_keys=True, depth_scaled=True)
+    got = set(zip(*oracle.unpack_keys(keys)))
+    # the norms of numpy's sums and the canonical ones differ by rounding: only
+    # triples whose decisive test is within 1e-12 of its threshold may differ
+    assert T == len(got)
+    assert len(got ^ want) <= max(1, len(want) // 1000)
+    assert len(got) > 0
+
+
+@pytest.mark.parametrize("tau", [1e-2, 1e-4, 1e-6])
+def test_depth_scaled_sandwich(tau):
+    # every test is looser than tau (tau / 8^k <= tau) and at least as strict as
+    # the leaf's tau / 8^L, and tier norms dominate their leaves', so
+    # flat(tau) <= depth(tau) <= flat(tau / 8^L) as sets of leaf triples
+    a = si.exp_decay(512, 0.9, 8)
+    b = 16
+    S = oracle.tile_sqnorms(a, b)
+    L = oracle.num_levels(S.shape[0])
+    d, _ = oracle.tasks_hierarchical(S, S, tau, depth_scaled=True)
+    lo, _ = oracle.tasks_flat(S, S, tau)
+    hi, _ = oracle.tasks_flat(S, S, tau / 8.0 ** L)
+    ds, los, his = set(d.tolist()), set(lo.tolist()), set(hi.tolist())
+    assert los <= ds <= his
+    assert len(los) < len(ds) < len(his)       # the schedules really differ here
+
+
+@pytest.mark.parametrize("tau", [3e-3, 1e-4, 1e-6])
+def test_depth_scaled_error_bound(tau):
+    # each culled node at depth k omits a product of norm < tau / 8^k, and depth
+    # k has at most 8^k nodes, so ||C~ - C||_F < (L + 1) tau (the rigorous bound)
+    a = si.exp_decay(384, 0.92, 9)
+    bm = si.exp_decay(384, 0.88, 10)
+    b = 16
+    c, T, _, _ = oracle.spamm_recursive(a, bm, b, tau, depth_scaled=True)
+    L = oracle.num_levels(-(-384 // b))
+    err = np.linalg.norm(c - a @ bm)
+    assert 0 < err < (L + 1) * tau
+    assert T < (384 // b) ** 3                  # something was culled
+
+
+def test_depth_scaled_single_tile_and_zero_tau():
+    # one tile (L = 0): the only test is at the root, with tau itself; tau = 0
+    # keeps every triple under either schedule
+    a = _rand(16, 3)
+    for tau in (0.0, 1.0, 1e3):
+        _, t1, _, _ = oracle.spamm_recursive(a, a, 16, tau)
+        _, t2, _, _ = oracle.spamm_recursive(a, a, 16, tau, depth_scaled=True)
+        assert t1 == t2
+    a = si.exp_decay(200, 0.8, 11)
+    c, T, _, _ = oracle.spamm_recursive(a, a, 8, 0.0, depth_scaled=True)
+    assert T == 25 ** 3 and np.allclose(c, a @ a, rtol=0, atol=1e-12)
