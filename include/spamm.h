@@ -164,6 +164,33 @@ spamm_status spamm_multiply(const spamm_matrix* A, const spamm_matrix* B, double
                             spamm_leaf_prec prec, void* stream, spamm_matrix** C,
                             spamm_stats* st);
 
+/* Threshold schedules of spamm_multiply_ex. */
+#define SPAMM_TAU_FLAT 0          /* tau at every tier: Eq. (4) (spamm_multiply)  */
+#define SPAMM_TAU_DEPTH_SCALED 1  /* tau / 8^k at depth k below the root          */
+
+/* spamm_multiply with a threshold schedule.  SPAMM_TAU_DEPTH_SCALED is the
+ * rigorous variant section 2 mentions beside its round-off comparison: the
+ * threshold is divided by 8 at every level of the recursion, so a node of
+ * the product octree at depth k (the root is depth 0, the leaf triples
+ * depth L) is kept iff !(S_A * S_B < fl(tau_k * tau_k)) with tau_k =
+ * tau / 8^k, and every ancestor was kept.  (S are the FP64 squared norms of
+ * the node's blocks; fl(tau_k * tau_k) = fl(tau * tau) 2^-6k exactly.)  The
+ * kept leaf triples then contain those of the flat rule at tau and lie within
+ * those of the flat rule at tau / 8^L, and the omitted part of the product is
+ * below (L + 1) tau in Frobenius norm.  The flat rule at tau equals its own
+ * leaf-level test; the depth-scaled one does not, so its cull is truly
+ * tier-by-tier.
+ *   tau_schedule : SPAMM_TAU_FLAT or SPAMM_TAU_DEPTH_SCALED
+ *   tau          : as spamm_multiply; for the depth-scaled schedule also
+ *                  tau == 0 or tau / 8^L >= 1e-150, so that every tier's tau^2
+ *                  is a normal FP64 number
+ * Other arguments, ownership and results as spamm_multiply.
+ * Errors: as spamm_multiply; EINVAL for an unknown schedule or a tau below
+ * the depth-scaled limit. */
+spamm_status spamm_multiply_ex(const spamm_matrix* A, const spamm_matrix* B, double tau,
+                               spamm_leaf_prec prec, int32_t tau_schedule, void* stream,
+                               spamm_matrix** C, spamm_stats* st);
+
 /* Phase durations of one product, from HIP events on the caller's stream. */
 typedef struct {
     double ms_cull;    /* counter reset, mask clear and every cull tier      */

@@ -125,6 +125,7 @@ def lib():
         "spamm_build": ([_VP, i64, i64, i32, i32, _VP, PP], i32),
         "spamm_build_ex": ([_VP, i64, i64, i32, i32, i32, _VP, PP], i32),
         "spamm_multiply": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Stats)], i32),
+        "spamm_multiply_ex": ([_VP, _VP, dbl, i32, i32, _VP, PP, ctypes.POINTER(Stats)], i32),
         "spamm_multiply_timed": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Timing)], i32),
         "spamm_multiply_batched": ([i32, PP, PP, ctypes.POINTER(dbl), i32, ctypes.POINTER(Tune), _VP, PP,
                                     ctypes.POINTER(Stats)], i32),
@@ -289,13 +290,22 @@ def build(a, leaf: int, out: Matrix | None = None, stream=None, prec: str | None
     return out if out is not None else Matrix(h)
 
 
+TAU_FLAT, TAU_DEPTH_SCALED = 0, 1
+
+
 def multiply(A: Matrix, B: Matrix, tau: float, prec: str = "f32", out: Matrix | None = None,
-             stats: bool = False, stream=None):
-    """C ~= A B by the SpAMM recursion (Eq. 4).  Returns C, or (C, stats dict)."""
+             stats: bool = False, stream=None, depth_scaled: bool = False):
+    """C ~= A B by the SpAMM recursion (Eq. 4).  Returns C, or (C, stats dict).
+
+    depth_scaled: tau / 8^k at depth k below the root (spamm_multiply_ex)."""
     h = ctypes.c_void_p(out.handle.value if out is not None else None)
     st = Stats() if stats else None
-    _check(lib().spamm_multiply(A.handle, B.handle, float(tau), LEAF[prec], _stream(stream), ctypes.byref(h),
-                                ctypes.byref(st) if st is not None else None))
+    if depth_scaled:
+        _check(lib().spamm_multiply_ex(A.handle, B.handle, float(tau), LEAF[prec], TAU_DEPTH_SCALED,
+                                       _stream(stream), ctypes.byref(h), ctypes.byref(st) if st is not None else None))
+    else:
+        _check(lib().spamm_multiply(A.handle, B.handle, float(tau), LEAF[prec], _stream(stream), ctypes.byref(h),
+                                    ctypes.byref(st) if st is not None else None))
     C = out if out is not None else Matrix(h)
     return (C, st.to_dict()) if stats else C
 

@@ -275,7 +275,7 @@ static bool split_current(const spamm_matrix* M, int kind) {
 spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C, double tau,
                              spamm_leaf_prec prec, hipStream_t s, int want_bound, int sp2, const int* d_branch,
                              const int* d_active, ProdDesc* d_desc_override, uint32_t* sp2_list,
-                             Sp2State* sp2_state) {
+                             Sp2State* sp2_state, int depth_tau) {
     ProductScratch* ps = C->ps;
     ProdDesc* d_desc = d_desc_override;
     // 16-bit leaves read the operands' split tiles when both are current
@@ -286,6 +286,7 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
     C->gen++;
     if (!d_desc) {
         ProdDesc d = make_desc(A, B, C, tau);
+        d.depth_tau = depth_tau;
         if (!ps->desc_valid || std::memcmp(&d, &ps->host_desc, sizeof d) != 0) {
             ps->host_desc = d;
             SPAMM_HIP(hipMemcpyAsync(ps->desc, &ps->host_desc, sizeof(ProdDesc), hipMemcpyHostToDevice, s));
@@ -386,11 +387,16 @@ spamm_status spamm_build(const void* dev_a, int64_t n, int64_t lda, spamm_dtype 
     return spamm_build_ex(dev_a, n, lda, dt, leaf, dt == SPAMM_F64 ? SPAMM_LEAF_F64 : SPAMM_LEAF_F32, stream, out);
 }
 
-spamm_status spamm_multiply(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,
-                            void* stream, spamm_matrix** C, spamm_stats* st) {
+spamm_status spamm_multiply_ex(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,
+                               int32_t tau_schedule, void* stream, spamm_matrix** C, spamm_stats* st) {
     if (!C) return set_error(SPAMM_EINVAL, "C is null");
+    if (tau_schedule != SPAMM_TAU_FLAT && tau_schedule != SPAMM_TAU_DEPTH_SCALED)
+        return set_error(SPAMM_EINVAL, "unknown tau schedule");
     spamm_status v = check_operands(A, B, tau, prec);
     if (v != SPAMM_OK) return v;
+    // every tier's tau^2 must stay a normal FP64 number: tau / 8^L >= 1e-150
+    if (tau_schedule == SPAMM_TAU_DEPTH_SCALED && tau > 0.0 && !(std::ldexp(tau, -3 * A->L) >= 1e-150))
+        return set_error(SPAMM_EINVAL, "depth-scaled schedule needs tau / 8^L >= 1e-150");
     const spamm_dtype cdt = prec == SPAMM_LEAF_F64 ? SPAMM_F64 : SPAMM_F32;
     spamm_matrix* Cm = *C;
     if (Cm) {
@@ -411,7 +417,9 @@ spamm_status spamm_multiply(const spamm_matrix* A, const spamm_matrix* B, double
     }
     Cm->last_stream = s;
     spamm_status r = ensure_scratch(Cm, s);
-    if (r == SPAMM_OK) r = enqueue_product(A, B, Cm, tau, prec, s, st != nullptr, 0, nullptr, nullptr, nullptr);
+    if (r == SPAMM_OK)
+        r = enqueue_product(A, B, Cm, tau, prec, s, st != nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                            tau_schedule == SPAMM_TAU_DEPTH_SCALED);
     if (r != SPAMM_OK) {
         if (fresh) release(Cm);
         return r;
@@ -419,6 +427,11 @@ spamm_status spamm_multiply(const spamm_matrix* A, const spamm_matrix* B, double
     *C = Cm;
     if (st) return read_stats(Cm, s, st, tau);
     return SPAMM_OK;
+}
+
+spamm_status spamm_multiply(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,
+                            void* stream, spamm_matrix** C, spamm_stats* st) {
+    return spamm_multiply_ex(A, B, tau, prec, SPAMM_TAU_FLAT, stream, C, st);
 }
 
 spamm_status spamm_multiply_timed(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,

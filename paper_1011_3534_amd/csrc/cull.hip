@@ -3,7 +3,9 @@
 //
 // The frontier of tier l holds the kept octree nodes (m, I, J, K) of every
 // product in the batch.  One launch per tier expands each node into its 8
-// children and keeps a child iff !(S_A[l-1][I',K'] * S_B[l-1][K',J'] < tau^2);
+// children and keeps a child iff !(S_A[l-1][I',K'] * S_B[l-1][K',J'] < tau^2)
+// (with the depth-scaled schedule of section 2, tau / 8^k at depth k below
+// the root: tau^2 scaled by 2^-6k, exact in FP64);
 // survivors are compacted with a block-wide exclusive prefix scan and one
 // atomic reservation per block.  Children at the leaf tier are not
 // compacted: they set bit K of the C tile (I, J) in a bitmask, which gives
@@ -78,7 +80,8 @@ __device__ void cull_pass(const ProdDesc* __restrict__ desc, int nprod, int l, c
             const int mc = d.lvl_m[c];
             const double* SA = d.SA + d.lvl_off[c];
             const double* SB = d.SB + d.lvl_off[c];
-            const double t2 = d.tau2;
+            // tau^2 of the children's depth L - c (the root, depth 0, uses tau^2)
+            const double t2 = d.depth_tau ? ldexp(d.tau2, -6 * (d.L - c)) : d.tau2;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const uint32_t Ic = 2 * I + (q >> 2), Jc = 2 * J + ((q >> 1) & 1), Kc = 2 * K + (q & 1);

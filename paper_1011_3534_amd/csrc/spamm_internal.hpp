@@ -97,7 +97,7 @@ struct ProdDesc {
     double tau2;
     int32_t nb, L, W;
     int32_t a_f64, b_f64;     // operand tile element types (1 = FP64)
-    int32_t pad_;
+    int32_t depth_tau;        // 1: a node at depth k below the root is tested against tau / 8^k
 };
 
 // Device-side counters of one product launch sequence.
@@ -243,6 +243,6 @@ hipError_t launch_sp2_tiles(const ProdDesc* d_desc, int64_t nb, uint32_t* list, 
 spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C, double tau,
                              spamm_leaf_prec prec, hipStream_t s, int want_bound, int sp2, const int* d_branch,
                              const int* d_active, ProdDesc* d_desc_override, uint32_t* sp2_list = nullptr,
-                             Sp2State* sp2_state = nullptr);
+                             Sp2State* sp2_state = nullptr, int depth_tau = 0);
 
 }  // namespace spamm

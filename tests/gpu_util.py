@@ -28,14 +28,17 @@ def gamma(k, u):
     return k * u / (1 - k * u)
 
 
-def elementwise_bound(a64, b64, leaf, tau, prec):
+def elementwise_bound(a64, b64, leaf, tau, prec, depth_scaled=False):
     """Bound on |C_gpu - C_oracle| for the same kept triples.
 
     (|A||B|)_kept is the oracle SpAMM of |A|, |B| (same squares -> same norms
     -> same kept set).  Terms: operand representation error, accumulation in
     the leaf's accumulator over at most n terms, rounding of the stored result."""
     n = a64.shape[0]
-    absprod, _ = oracle.spamm_flat(np.abs(a64), np.abs(b64), leaf, tau)
+    if depth_scaled:
+        absprod, _, _, _ = oracle.spamm_recursive(np.abs(a64), np.abs(b64), leaf, tau, depth_scaled=True)
+    else:
+        absprod, _ = oracle.spamm_flat(np.abs(a64), np.abs(b64), leaf, tau)
     u = ACC_U.get(prec, U32)
     rel = INPUT_REL[prec] * (1 + gamma(n, u)) + gamma(n + 2, u) + (U32 if prec != "f64" else 2 ** -53)
     slack = 2.0 ** -36 * np.max(np.abs(a64)) * np.max(np.abs(b64)) * n if prec.startswith("f16") else 0.0

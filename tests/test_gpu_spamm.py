@@ -281,3 +281,81 @@ def test_invalid_arguments_on_device_handles():
     A64 = sp.build(to_dev(a.astype(np.float64)), 64)
     with pytest.raises(sp.SpammError, match="EUNSUPPORTED"):
         sp.multiply(A64, A64, 1e-6, "f32")
+
+
+# ------------------------------------------------------------------ depth-scaled threshold
+
+DEPTH_CASES = [
+    (1024, 32, 1e-4, "f64", "exp"),
+    (1000, 64, 1e-4, "f32", "alg"),
+    (900, 64, 1e-3, "f16x3", "alg"),
+    (700, 128, 1e-3, "f32", "alg"),
+    (450, 32, 1e-3, "bf16x3", "alg"),
+]
+
+
+@pytest.mark.parametrize("n,b,tau,prec,fam", DEPTH_CASES)
+def test_depth_scaled_matches_oracle(n, b, tau, prec, fam):
+    # tau / 8^k at depth k: the kept triples equal the oracle recursion's bit for
+    # bit (hierarchical, not the flat rule), C within the precision's bound
+    _case(f"depth-scaled n={n} b={b} tau={tau} prec={prec} fam={fam}")
+    a, bm = _operands(n, fam, prec == "f64" and fam == "exp")
+    A, B = sp.build(to_dev(a), b), sp.build(to_dev(bm), b)
+    C, st = sp.multiply(A, B, tau, prec, stats=True, depth_scaled=True)
+    a64, b64 = a.astype(np.float64), bm.astype(np.float64)
+    SA, SB = oracle.tile_sqnorms(a64, b), oracle.tile_sqnorms(b64, b)
+    keys, kept = oracle.tasks_hierarchical(SA, SB, tau, depth_scaled=True)
+    flat, _ = oracle.tasks_flat(SA, SB, tau)
+    got = C.task_list()
+    assert np.array_equal(got, keys)
+    assert len(keys) > len(flat)               # the schedule changes the kept set here
+    assert st["tasks"] == len(keys) and st["survivors"] == kept.tolist()
+    ref, _, _, _ = oracle.spamm_recursive(a64, b64, b, tau, depth_scaled=True)
+    out = C.to_dense().cpu().numpy().astype(np.float64)
+    bound = elementwise_bound(a64, b64, b, tau, prec, depth_scaled=True)
+    excess = np.abs(out - ref) - bound
+    assert np.all(excess <= 0), f"max excess {excess.max():.3e}"
+    print(f"  T={len(keys)} (flat {len(flat)}) relerr_vs_oracle={oracle.rel_err(out, ref):.3e}", flush=True)
+
+
+def test_depth_scaled_8192_task_list_and_bound():
+    # the algebraic workload n = 8192, leaf 64 (L = 7): full kept-triple list
+    # against the oracle's hierarchical enumeration, and the omitted part of
+    # the product below (L + 1) tau against the exact FP64 product
+    _case("depth-scaled n=8192 b=64 tau=1e-3 f32")
+    n, b, tau = 8192, 64, 1e-3
+    a = si.algebraic_workload(n)
+    A = sp.build(to_dev(a), b)
+    C, st = sp.multiply(A, A, tau, "f32", stats=True, depth_scaled=True)
+    S = oracle.tile_sqnorms(a.astype(np.float64), b)
+    keys, kept = oracle.tasks_hierarchical(S, S, tau, depth_scaled=True)
+    assert np.array_equal(C.task_list(), keys)
+    assert st["survivors"] == kept.tolist()
+    E = sp.multiply(A, A, 0.0, "f64")
+    diff = sp.rel_err(C, E) * float(np.sqrt(E.norms(E.levels)[0, 0]))
+    assert diff < (A.levels + 1) * tau
+    print(f"  T={len(keys)} omitted={diff:.3e} bound={(A.levels + 1) * tau:.1e}", flush=True)
+
+
+def test_depth_scaled_and_flat_alternate_on_one_output():
+    # the product descriptor cached in the result handle carries the schedule:
+    # flat, depth-scaled and flat again into one C equal fresh products
+    _case("flat/depth/flat into one C")
+    a = si.algebraic_decay(640, 2.0, 31, np.float32)
+    A = sp.build(to_dev(a), 64)
+    C = None
+    for depth in (False, True, False, True):
+        C = sp.multiply(A, A, 1e-4, "f32", out=C, depth_scaled=depth)
+        fresh = sp.multiply(A, A, 1e-4, "f32", depth_scaled=depth)
+        assert np.array_equal(C.task_list(), fresh.task_list())
+        assert np.array_equal(C.to_dense().cpu().numpy(), fresh.to_dense().cpu().numpy())
+
+
+def test_depth_scaled_rejects_small_tau():
+    _case("depth-scaled EINVAL")
+    a = si.algebraic_decay(512, 2.0, 7, np.float32)
+    A = sp.build(to_dev(a), 32)                # nb = 16, L = 4: tau / 8^4 >= 1e-150
+    with pytest.raises(sp.SpammError, match="EINVAL"):
+        sp.multiply(A, A, 1e-147, depth_scaled=True)
+    sp.multiply(A, A, 1e-146, depth_scaled=True)
+    sp.multiply(A, A, 0.0, depth_scaled=True)
