@@ -111,7 +111,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 256 MiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--workload", default="algebraic8192",
-                    choices=["algebraic8192", "exp1024", "batched64", "sp2", "learned-tau"],
+                    choices=["algebraic8192", "exp1024", "batched64", "sp2", "learned-tau", "depth-tau"],
                     help="algebraic8192 (default): the headline line; the others measure the remaining "
                          "hot-path rows and print their own JSON line")
     ap.add_argument("--sp2-n", type=int, default=16384)
@@ -124,7 +124,7 @@ def main():
         sys.exit(2)
     if args.workload != "algebraic8192":
         {"exp1024": run_exp1024, "batched64": run_batched64, "sp2": run_sp2,
-         "learned-tau": run_learned_tau}[args.workload](args)
+         "learned-tau": run_learned_tau, "depth-tau": run_depth_tau}[args.workload](args)
         return
 
     import torch
@@ -292,6 +292,45 @@ def run_exp1024(args):
                                "rel_err_vs_dense_fp64": sp.rel_err(C, Dh)}
     dense_ms = _time(torch, lambda: torch.matmul(A_d, A_d), 50, 3)
     out["dense_fp64_gemm_ms"] = dense_ms
+    print(json.dumps(out), flush=True)
+
+
+def run_depth_tau(args):
+    """Flat vs depth-scaled threshold (tau / 8^k at depth k, the rigorous variant of section 2) on the
+    algebraic workload (n = 8192, leaf 64): kept triples, error and product time over a tau sweep,
+    and each schedule at the largest tau that meets the target error."""
+    torch, sp = _setup()
+    import spamm_inputs as si
+    n, b = args.n, args.leaf
+    a = si.algebraic_workload(n)
+    A_d = torch.from_numpy(a).cuda()
+    A = sp.build(A_d, b)
+    E = sp.multiply(A, A, 0.0, "f64")
+    norm_c = float(np.sqrt(E.norms(E.levels)[0, 0]))
+    out = {"metric": METRIC, "workload": "depth-tau", "n": n, "leaf": b, "levels": A.levels,
+           "target": args.target, "config": {
+               "workload": f"algebraic decay u/(|i-j|^2+1), u~U(0.5,1.5), n={n}, leaf {b}, FP32 storage, "
+                           f"C=A*A, flat vs depth-scaled tau"}}
+    for prec in ("f32", "f16x3"):
+        rows = {}
+        for depth in (False, True):
+            key = "depth" if depth else "flat"
+            C = None
+            sweep = []
+            best = None
+            for tau in tau_grid(hi=10.0, lo=1e-8):
+                C, st = sp.multiply(A, A, tau, prec, out=C, stats=True, depth_scaled=depth)
+                err = sp.rel_err(C, E)
+                ms = _time(torch, lambda: sp.multiply(A, A, tau, prec, out=C, depth_scaled=depth), 10, 2)
+                sweep.append({"tau": tau, "tasks": st["tasks"], "rel_err": err, "ms": ms,
+                              "bound_rel": (A.levels + 1) * tau / norm_c if depth else None})
+                if err <= args.target:
+                    best = sweep[-1]
+                    break
+            rows[key] = {"sweep": sweep, "at_target": best}
+            log(f"depth-tau {prec} {key}: " + (f"tau={best['tau']:g} T={best['tasks']} err={best['rel_err']:.2e} "
+                                               f"{best['ms']:.3f} ms" if best else "misses the target"))
+        out[prec] = rows
     print(json.dumps(out), flush=True)
 
 
