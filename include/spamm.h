@@ -210,8 +210,13 @@ spamm_status spamm_multiply_timed(const spamm_matrix* A, const spamm_matrix* B, 
 typedef enum {
     SPAMM_SCHED_STATIC = 0,  /* one block per C tile, tiles split into 8 contiguous
                                 ranges, one per XCD (the default of spamm_multiply) */
-    SPAMM_SCHED_LPT = 1      /* persistent blocks pull tiles from a device queue in
+    SPAMM_SCHED_LPT = 1,     /* persistent blocks pull tiles from a device queue in
                                 order of decreasing kept-K count (largest first)     */
+    SPAMM_SCHED_LIST = 2     /* one pass lists the C tiles that need a write (a kept
+                                product, or stored values not known to be zero);
+                                persistent blocks take the list in a static stride,
+                                so the many empty tiles of banded products cost no
+                                block at all                                         */
 } spamm_schedule;
 
 typedef struct {
@@ -241,7 +246,7 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
 /* ------------------------------------------------------------------ autotuner */
 
 #define SPAMM_TUNE_MAX_LEAVES 3
-#define SPAMM_TUNE_MAX_TRIALS 8
+#define SPAMM_TUNE_MAX_TRIALS 12
 typedef struct {
     int32_t trials;                              /* candidates timed (0 if from cache)     */
     int32_t from_cache;                          /* 1: answer read from the cache file     */
@@ -256,8 +261,8 @@ typedef struct {
 /* Autotuner of spamm_multiply_batched for the products C_m = A_m A_m of the
  * caller's dense operands (dev_a[m]: n[m] x n[m] row-major, leading
  * dimension n[m], element type dt).  For every leaf size in leaves[] (each
- * 32, 64 or 128; at most 3) the operands are built and both schedules are
- * timed (median of reps products, HIP events on `stream`).  Because the leaf
+ * 32, 64 or 128; at most 3) the operands are built and the three schedules
+ * are timed (median of reps products, HIP events on `stream`).  Because the leaf
  * size changes which block products are kept, a candidate qualifies only if
  * every product stays within max_rel_err (relative Frobenius error) of the
  * exact product, formed once with FP64 leaves at tau = 0.  The fastest

@@ -43,7 +43,7 @@ class Stats(ctypes.Structure):
                 "flops": float(self.flops), "culled_bound": float(self.culled_bound)}
 
 
-SCHEDULE = {"static": 0, "lpt": 1}
+SCHEDULE = {"static": 0, "lpt": 1, "list": 2}
 
 
 class Tune(ctypes.Structure):
@@ -51,9 +51,9 @@ class Tune(ctypes.Structure):
 
 
 class TuneReport(ctypes.Structure):
-    _fields_ = [("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("leaf", ctypes.c_int32 * 8),
-                ("schedule", ctypes.c_int32 * 8), ("qualified", ctypes.c_int32 * 8), ("ms", ctypes.c_double * 8),
-                ("max_rel_err", ctypes.c_double * 8), ("best_ms", ctypes.c_double)]
+    _fields_ = [("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("leaf", ctypes.c_int32 * 12),
+                ("schedule", ctypes.c_int32 * 12), ("qualified", ctypes.c_int32 * 12), ("ms", ctypes.c_double * 12),
+                ("max_rel_err", ctypes.c_double * 12), ("best_ms", ctypes.c_double)]
 
     def to_dict(self):
         sched = {v: k for k, v in SCHEDULE.items()}
@@ -325,7 +325,8 @@ def multiply_batched(As, Bs, taus, prec: str = "f32", outs=None, stats: bool = F
                      schedule: str | None = None, stream=None):
     """Independent products C_m ~= A_m B_m in one cull pass and one leaf launch.
 
-    schedule: None/"lpt" (persistent, largest first) or "static"."""
+    schedule: None/"lpt" (persistent, largest first), "static" or "list" (persistent over the
+    tiles that need a write)."""
     count = len(As)
     PA = (ctypes.c_void_p * count)(*[a.handle.value for a in As])
     PB = (ctypes.c_void_p * count)(*[b.handle.value for b in Bs])

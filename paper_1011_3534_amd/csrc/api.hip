@@ -563,7 +563,8 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
     if (!A[0]) return set_error(SPAMM_EINVAL, "null operand");
     const int32_t b = A[0]->b;
     const int sched = tune ? tune->schedule : SPAMM_SCHED_LPT;
-    if (sched != SPAMM_SCHED_STATIC && sched != SPAMM_SCHED_LPT) return set_error(SPAMM_EINVAL, "unknown schedule");
+    if (sched != SPAMM_SCHED_STATIC && sched != SPAMM_SCHED_LPT && sched != SPAMM_SCHED_LIST)
+        return set_error(SPAMM_EINVAL, "unknown schedule");
     if (tune && tune->leaf && tune->leaf != b) return set_error(SPAMM_EINVAL, "tune->leaf differs from the operands");
     const spamm_dtype cdt = prec == SPAMM_LEAF_F64 ? SPAMM_F64 : SPAMM_F32;
     for (int m = 0; m < count; ++m) {
@@ -660,6 +661,9 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
     if (sched == SPAMM_SCHED_LPT) {
         lp.order = (uint32_t*)(ws + o_ord);
         lp.queue = (unsigned long long*)(ws + o_q);
+    } else if (sched == SPAMM_SCHED_LIST) {
+        lp.list = (uint32_t*)(ws + o_ord);  // the order array holds the list
+        lp.list_count = (unsigned*)(ws + o_q);
     }
     hipError_t e = hipMemcpyAsync(d_desc, hd.data(), sizeof(ProdDesc) * count, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_clear_masks(d_desc, count, s);
@@ -669,6 +673,8 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
     if (e == hipSuccess && sched == SPAMM_SCHED_LPT)
         e = launch_lpt_order(d_desc, count, total, maxc, (uint32_t*)(ws + o_cnt), (uint32_t*)(ws + o_hist),
                              (uint32_t*)(ws + o_offs), (uint32_t*)(ws + o_ord), lp.queue, s);
+    if (e == hipSuccess && sched == SPAMM_SCHED_LIST)
+        e = launch_tile_list(d_desc, count, total, (uint32_t*)(ws + o_ord), (unsigned*)(ws + o_q), s);
     if (e == hipSuccess) e = launch_leaf_typed(d_desc, lp, A[0]->dt == SPAMM_F64, s);
     for (int m = 0; m < count && e == hipSuccess; ++m) e = launch_upper_norms(out[m], s, nullptr);
     if (e == hipSuccess && st) {

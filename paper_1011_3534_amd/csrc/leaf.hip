@@ -780,36 +780,35 @@ __global__ void __launch_bounds__(256) k_leaf_queue(const ProdDesc* __restrict__
     }
 }
 
-// SP2: resident blocks take the listed C tiles in a static stride (the list
-// and its count come from the step's tile-list kernel).  Leaf 64 is
-// compiled for three blocks per CU (no spills) and launched with that many.
+// Resident blocks take the listed C tiles (global tile indices) in a static
+// stride; the list and its count come from a tile-list kernel (SP2 steps,
+// the list schedule).  Leaf 64 is compiled for three blocks per CU (no
+// spills) and launched with that many.
 template <int B>
 constexpr int list_blocks_per_cu() { return B == 32 ? 4 : (B == 64 ? 3 : 1); }
 
 template <int B, int P, typename TA, typename TC, bool SP2, bool PS>
-__global__ void __launch_bounds__(256, (B == 64 ? list_blocks_per_cu<B>() : 1)) k_leaf_list(const ProdDesc* __restrict__ desc, const uint32_t* __restrict__ list,
-                                                   const unsigned* __restrict__ count, const int* __restrict__ branch,
-                                                   const int* __restrict__ active) {
+__global__ void __launch_bounds__(256, (B == 64 ? list_blocks_per_cu<B>() : 1))
+    k_leaf_list(const ProdDesc* __restrict__ desc, int nprod, const uint32_t* __restrict__ list,
+                const unsigned* __restrict__ count, const int* __restrict__ branch, const int* __restrict__ active) {
     __shared__ __attribute__((aligned(16))) char smem[Geo<B, P>::SMEM];
     __shared__ KList kl;
     __shared__ double red[2][4];
     if (active && *active == 0) return;
     const int64_t n = (int64_t)*count;
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x)
-        leaf_tile<B, P, TA, TC, SP2, PS>(desc, 1, (int64_t)list[i], smem, &kl, red, branch, false);
+        leaf_tile<B, P, TA, TC, SP2, PS>(desc, nprod, (int64_t)list[i], smem, &kl, red, branch, false);
 }
 
 template <int B, int P, typename TA, typename TC, bool SP2, bool PS = false>
 hipError_t go(const ProdDesc* d_desc, const LeafPlan& p, hipStream_t s) {
-    if constexpr (SP2) {
-        if (p.list) {
-            // a grid of the resident blocks; the stride loop is correct for any grid
-            int64_t grid = (int64_t)num_cus() * list_blocks_per_cu<B>();
-            if (grid > p.total_tiles) grid = p.total_tiles < 1 ? 1 : p.total_tiles;
-            hipLaunchKernelGGL((k_leaf_list<B, P, TA, TC, SP2, PS>), dim3((unsigned)grid), dim3(256), 0, s, d_desc,
-                               p.list, p.list_count, p.d_branch, p.d_active);
-            return hipGetLastError();
-        }
+    if (p.list) {
+        // a grid of the resident blocks; the stride loop is correct for any grid
+        int64_t grid = (int64_t)num_cus() * list_blocks_per_cu<B>();
+        if (grid > p.total_tiles) grid = p.total_tiles < 1 ? 1 : p.total_tiles;
+        hipLaunchKernelGGL((k_leaf_list<B, P, TA, TC, SP2, PS>), dim3((unsigned)grid), dim3(256), 0, s, d_desc,
+                           p.count, p.list, p.list_count, p.d_branch, p.d_active);
+        return hipGetLastError();
     }
     if (p.queue) {
         int per_cu = 0;

@@ -16,16 +16,28 @@ __device__ inline int product_of(const ProdDesc* desc, int nprod, int64_t t) {
     return lo;
 }
 
+// Kept-K count of global C tile t (0 past the end).
+__device__ inline uint32_t tile_count(const ProdDesc* desc, int nprod, int64_t total, int64_t t) {
+    if (t >= total) return 0;
+    const ProdDesc& d = desc[product_of(desc, nprod, t)];
+    const uint64_t* w = d.mask + (t - d.tile_base) * d.W;
+    uint32_t c = 0;
+    for (int i = 0; i < d.W; ++i) c += (uint32_t)__popcll(w[i]);
+    return c;
+}
+
+// Empty tiles (count 0) are usually the majority: each wave adds them to
+// hist[0] with one atomic instead of one per tile.
 __global__ void k_tile_counts(const ProdDesc* __restrict__ desc, int nprod, int64_t total, uint32_t* __restrict__ counts,
                               uint32_t* __restrict__ hist) {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const ProdDesc& d = desc[product_of(desc, nprod, t)];
-        const int64_t local = t - d.tile_base;
-        const uint64_t* w = d.mask + local * d.W;
-        uint32_t c = 0;
-        for (int i = 0; i < d.W; ++i) c += (uint32_t)__popcll(w[i]);
-        counts[t] = c;
-        atomicAdd(&hist[c], 1u);
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = base + threadIdx.x;
+        const uint32_t c = tile_count(desc, nprod, total, t);
+        if (t < total) counts[t] = c;
+        const unsigned long long zero = __ballot(t < total && c == 0);
+        if (lane == 0 && zero) atomicAdd(&hist[0], (unsigned)__popcll(zero));
+        if (t < total && c > 0) atomicAdd(&hist[c], 1u);
     }
 }
 
@@ -57,11 +69,47 @@ __global__ void __launch_bounds__(1024) k_hist_scan_desc(const uint32_t* hist, i
     }
 }
 
+// Positions in the LPT order; a wave reserves the slots of its empty tiles
+// with one atomic (the order among equal counts is arbitrary either way).
 __global__ void k_scatter_order(const uint32_t* __restrict__ counts, int64_t total, uint32_t* __restrict__ offs,
                                 uint32_t* __restrict__ order) {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t pos = atomicAdd(&offs[counts[t]], 1u);
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = base + threadIdx.x;
+        const uint32_t c = t < total ? counts[t] : 1u;
+        const unsigned long long zero = __ballot(t < total && c == 0);
+        unsigned zbase = 0;
+        if (lane == 0 && zero) zbase = atomicAdd(&offs[0], (unsigned)__popcll(zero));
+        zbase = (unsigned)__shfl((int)zbase, 0, 64);
+        if (t >= total) continue;
+        const uint32_t pos = c == 0 ? zbase + (unsigned)__popcll(zero & ((1ull << lane) - 1ull)) : atomicAdd(&offs[c], 1u);
         order[pos] = (uint32_t)t;
+    }
+}
+
+// The C tiles of a product launch that need a write: a kept product, or
+// stored values not known to be zero (exponent -128 marks an all-zero tile,
+// whose norm is zero too).  The list order depends on the atomics; each
+// tile's result does not.
+__global__ void k_tile_list(const ProdDesc* __restrict__ desc, int nprod, int64_t total, uint32_t* __restrict__ list,
+                            unsigned* __restrict__ count) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = base + threadIdx.x;
+        bool need = false;
+        if (t < total) {
+            const ProdDesc& d = desc[product_of(desc, nprod, t)];
+            const int64_t local = t - d.tile_base;
+            uint64_t any = 0;
+            for (int i = 0; i < d.W; ++i) any |= d.mask[local * d.W + i];
+            need = any != 0 || d.eC[local] != -128;
+        }
+        const unsigned long long m = __ballot(need);
+        if (m == 0) continue;
+        unsigned lbase = 0;
+        if (lane == 0) lbase = atomicAdd(count, (unsigned)__popcll(m));
+        lbase = (unsigned)__shfl((int)lbase, 0, 64);
+        if (need) list[lbase + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)t;
     }
 }
 
@@ -71,7 +119,20 @@ __global__ void k_zero_u32(uint32_t* p, int64_t count, unsigned long long* queue
     if (blockIdx.x == 0 && threadIdx.x == 0 && queue) *queue = 0ull;
 }
 
+__global__ void k_zero_one(unsigned* p) { *p = 0u; }
+
 }  // namespace
+
+// list: total entries; count is zeroed first (a kernel, so the sequence can
+// be captured in a graph).
+hipError_t launch_tile_list(const ProdDesc* d_desc, int nprod, int64_t total, uint32_t* list, unsigned* count,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_one, dim3(1), dim3(1), 0, s, count);
+    int64_t blocks = (total + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
+    hipLaunchKernelGGL(k_tile_list, dim3((unsigned)blocks), dim3(256), 0, s, d_desc, nprod, total, list, count);
+    return hipGetLastError();
+}
 
 // counts/order: total entries; hist/offs: maxc + 1 entries each; queue zeroed.
 hipError_t launch_lpt_order(const ProdDesc* d_desc, int nprod, int64_t total, int maxc, uint32_t* counts,

@@ -119,7 +119,7 @@ extern "C" spamm_status spamm_autotune_batched(int32_t count, const void* const*
     SPAMM_HIP(hipEventCreate(&e1));
     double best_ms = INFINITY;
     int trials = 0;
-    const int scheds[2] = {SPAMM_SCHED_STATIC, SPAMM_SCHED_LPT};
+    const int scheds[3] = {SPAMM_SCHED_STATIC, SPAMM_SCHED_LPT, SPAMM_SCHED_LIST};
     for (int li = 0; li < n_leaves; ++li) {
         Handles hA, hC;
         hC.h.assign(count, nullptr);
@@ -128,7 +128,7 @@ extern "C" spamm_status spamm_autotune_batched(int32_t count, const void* const*
             if ((r = spamm_build(dev_a[m], n[m], n[m], dt, leaves[li], stream, &a)) != SPAMM_OK) return r;
             hA.h.push_back(a);
         }
-        for (int si = 0; si < 2; ++si) {
+        for (int si = 0; si < 3; ++si) {
             spamm_tune t;
             std::memset(&t, 0, sizeof t);
             t.leaf = leaves[li];

@@ -32,7 +32,8 @@ def _batch(leaf, seed=0):
     return mats, taus
 
 
-@pytest.mark.parametrize("leaf,prec,schedule", [(64, "f32", "lpt"), (32, "f16x3", "lpt"), (64, "bf16x3", "static")])
+@pytest.mark.parametrize("leaf,prec,schedule", [(64, "f32", "lpt"), (32, "f16x3", "lpt"), (64, "bf16x3", "static"),
+                                                (64, "f32", "list"), (32, "f16x3", "list"), (128, "f32", "list")])
 def test_batched_matches_oracle(leaf, prec, schedule):
     print(f"[case] batched leaf={leaf} prec={prec} schedule={schedule}", flush=True)
     mats, taus = _batch(leaf)
@@ -58,12 +59,33 @@ def test_batched_equals_single_products_bitwise():
     hs = [sp.build(to_dev(a), 64) for a in mats]
     lpt = sp.multiply_batched(hs, hs, taus, "f16x3", schedule="lpt")
     static = sp.multiply_batched(hs, hs, taus, "f16x3", schedule="static")
-    for h, tau, c1, c2 in zip(hs, taus, lpt, static):
+    lst = sp.multiply_batched(hs, hs, taus, "f16x3", schedule="list")
+    for h, tau, c1, c2, c3 in zip(hs, taus, lpt, static, lst):
         single = sp.multiply(h, h, tau, "f16x3")
         a = single.to_dense().cpu().numpy()
         assert np.array_equal(c1.to_dense().cpu().numpy(), a)
         assert np.array_equal(c2.to_dense().cpu().numpy(), a)
+        assert np.array_equal(c3.to_dense().cpu().numpy(), a)
         assert np.array_equal(c1.task_list(), single.task_list())
+        assert np.array_equal(c3.norms(0), single.norms(0))
+
+
+def test_list_schedule_reused_outputs_with_changing_kept_sets():
+    # the list skips tiles with no kept product whose stored values are known
+    # zero; a reused output whose kept set shrinks or grows must still equal
+    # fresh products (tiles that became empty are listed and zeroed)
+    print("[case] list schedule, reused outputs", flush=True)
+    mats, _ = _batch(64, seed=4)
+    hs = [sp.build(to_dev(a), 64) for a in mats]
+    outs = None
+    for tau in (1e-7, 1e-3, 1e-3, 1e-8, 0.0, 1e-5):
+        taus = [tau] * len(hs)
+        outs = sp.multiply_batched(hs, hs, taus, "f32", outs=outs, schedule="list")
+        fresh = sp.multiply_batched(hs, hs, taus, "f32", schedule="static")
+        for c, f in zip(outs, fresh):
+            assert np.array_equal(c.to_dense().cpu().numpy(), f.to_dense().cpu().numpy())
+            assert np.array_equal(c.norms(0), f.norms(0))
+            assert np.array_equal(c.task_list(), f.task_list())
 
 
 def test_batched_output_reuse_and_errors():

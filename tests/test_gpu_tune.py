@@ -33,7 +33,8 @@ def test_autotune_picks_fastest_qualifying_and_caches(tmp_path):
     cache = str(tmp_path / "tune.txt")
     tune, rep = sp.autotune_batched(dense, taus, "f32", leaves=(32, 64), max_rel_err=1e-5, reps=2, cache_path=cache)
     print("  ", tune, rep, flush=True)
-    assert not rep["from_cache"] and len(rep["trials"]) == 4
+    assert not rep["from_cache"] and len(rep["trials"]) == 6   # 2 leaf sizes x 3 schedules
+    assert {t["schedule"] for t in rep["trials"]} == {"static", "lpt", "list"}
     ok = [t for t in rep["trials"] if t["qualified"]]
     assert ok
     fastest = min(ok, key=lambda t: t["ms"])
