@@ -348,27 +348,34 @@ def run_batched64(args):
     tune_s = time.perf_counter() - t0
     log(f"autotune: {tune} in {tune_s:.1f} s")
     b = tune["leaf"]
-    hs = [sp.build(d, b) for d in dense]
+    hs = sp.build_batched(dense, b)
     Cs, sts = sp.multiply_batched(hs, hs, taus, "f32", stats=True, schedule=tune["schedule"])
     T = sum(s["tasks"] for s in sts)
     flops = 2.0 * b ** 3 * T
 
     def step():
-        for d, h in zip(dense, hs):
-            sp.build(d, b, out=h)
+        # the 64 operands built in one batched pass, then one batched product
+        sp.build_batched(dense, b, outs=hs)
         sp.multiply_batched(hs, hs, taus, "f32", outs=Cs, schedule=tune["schedule"])
 
     step_ms = _time(torch, step, args.steps, args.warmup)
+    build_ms = _time(torch, lambda: sp.build_batched(dense, b, outs=hs), args.steps, args.warmup)
+    build_single_ms = _time(torch, lambda: [sp.build(d, b, out=h) for d, h in zip(dense, hs)], args.steps,
+                            args.warmup)
     mult_ms = _time(torch, lambda: sp.multiply_batched(hs, hs, taus, "f32", outs=Cs, schedule=tune["schedule"]),
                     args.steps, args.warmup)
-    other = "static" if tune["schedule"] == "lpt" else "lpt"
-    other_ms = _time(torch, lambda: sp.multiply_batched(hs, hs, taus, "f32", outs=Cs, schedule=other),
-                     args.steps, args.warmup)
+    others = {}
+    for other in ("static", "lpt", "list"):
+        if other != tune["schedule"]:
+            others[f"multiply_ms_{other}"] = _time(
+                torch, lambda: sp.multiply_batched(hs, hs, taus, "f32", outs=Cs, schedule=other), args.steps,
+                args.warmup)
     dense_ms = _time(torch, lambda: [torch.matmul(d, d) for d in dense], 3, 1)
     dense_flops = sum(2.0 * d.shape[0] ** 3 for d in dense)
     print(json.dumps({"metric": METRIC, "workload": "batched64", "tune": tune, "tune_report": rep,
                       "tune_seconds": tune_s, "tasks": T, "leaf_flops": flops, "step_ms": step_ms,
-                      "multiply_ms": mult_ms, f"multiply_ms_{other}": other_ms,
+                      "build_ms": build_ms, "build_ms_one_call_per_matrix": build_single_ms,
+                      "multiply_ms": mult_ms, **others,
                       "step_tflops": flops / step_ms / 1e9, "dense_fp32_gemm_ms": dense_ms,
                       "dense_flops": dense_flops, "speedup_vs_dense_fp32": dense_ms / step_ms,
                       "config": {"workload": "64 exp-decay matrices lam~U(0.8,0.97), n~U{512..8192 step 64}, "

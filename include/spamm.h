@@ -129,6 +129,23 @@ typedef struct {
 spamm_status spamm_build(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf,
                          void* stream, spamm_matrix** out);
 
+/* spamm_build of count matrices in one pass (the concatenated tile pools of
+ * a batch): one launch packs every matrix's tiles and leaf norms, and each
+ * upper tier is formed for all matrices by one launch, so a batch of small
+ * matrices costs a few launches instead of a few per matrix.  Results are
+ * the same bits as count calls of spamm_build.
+ *   dev_a[m], n[m], lda[m] : as spamm_build, per matrix (host arrays)
+ *   dt, leaf               : shared by the batch
+ *   out[m]                 : in/out as for spamm_build (NULL entries are
+ *                            allocated; existing handles must match n[m],
+ *                            leaf and dt, and be distinct)
+ * Errors: EINVAL (count outside [1, 128], null pointers, bad n/lda/leaf,
+ * mismatched or repeated handles), ENOMEM, EHIP.  On error no handle of
+ * out[] is changed. */
+spamm_status spamm_build_batched(int32_t count, const void* const* dev_a, const int64_t* n,
+                                 const int64_t* lda, spamm_dtype dt, int32_t leaf, void* stream,
+                                 spamm_matrix** out);
+
 /* spamm_build for operands of products with leaf precision `prec`.  For the
  * 16-bit precisions (FP32 input only) the same pass also writes the handle's
  * split tiles: x = hi + lo per element in FP16 (tile scaled by a power of two

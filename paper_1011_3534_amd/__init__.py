@@ -124,6 +124,7 @@ def lib():
     sig = {
         "spamm_build": ([_VP, i64, i64, i32, i32, _VP, PP], i32),
         "spamm_build_ex": ([_VP, i64, i64, i32, i32, i32, _VP, PP], i32),
+        "spamm_build_batched": ([i32, _VP, _VP, _VP, i32, i32, _VP, _VP], i32),
         "spamm_multiply": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Stats)], i32),
         "spamm_multiply_ex": ([_VP, _VP, dbl, i32, i32, _VP, PP, ctypes.POINTER(Stats)], i32),
         "spamm_multiply_timed": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Timing)], i32),
@@ -288,6 +289,27 @@ def build(a, leaf: int, out: Matrix | None = None, stream=None, prec: str | None
         _check(lib().spamm_build_ex(ctypes.c_void_p(a.data_ptr()), a.shape[0], a.stride(0), dt, leaf, LEAF[prec],
                                     _stream(stream), ctypes.byref(h)))
     return out if out is not None else Matrix(h)
+
+
+def build_batched(tensors, leaf: int, outs=None, stream=None) -> list:
+    """Quadtrees of several dense CUDA tensors of one dtype in one pass
+    (spamm_build_batched).  outs: None or a list of handles/None to rebuild."""
+    import torch
+    count = len(tensors)
+    dts = {a.dtype for a in tensors}
+    if len(dts) > 1 or (dts and dts.pop() not in (torch.float32, torch.float64)):
+        raise ValueError("build_batched expects float32 or float64 tensors of one dtype")
+    for a in tensors:
+        if not (a.is_cuda and a.dim() == 2 and a.shape[0] == a.shape[1] and a.stride(1) == 1):
+            raise ValueError("build_batched expects square CUDA tensors with unit column stride")
+    dt = 0 if count and tensors[0].dtype == torch.float64 else 1
+    PA = (ctypes.c_void_p * count)(*[a.data_ptr() for a in tensors])
+    N = (ctypes.c_int64 * count)(*[a.shape[0] for a in tensors])
+    LD = (ctypes.c_int64 * count)(*[a.stride(0) for a in tensors])
+    outs = outs or [None] * count
+    PO = (ctypes.c_void_p * count)(*[(o.handle.value if o is not None else None) for o in outs])
+    _check(lib().spamm_build_batched(count, PA, N, LD, dt, leaf, _stream(stream), PO))
+    return [o if o is not None else Matrix(ctypes.c_void_p(PO[m])) for m, o in enumerate(outs)]
 
 
 TAU_FLAT, TAU_DEPTH_SCALED = 0, 1

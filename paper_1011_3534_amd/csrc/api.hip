@@ -382,6 +382,76 @@ spamm_status spamm_build_ex(const void* dev_a, int64_t n, int64_t lda, spamm_dty
     return SPAMM_OK;
 }
 
+spamm_status spamm_build_batched(int32_t count, const void* const* dev_a, const int64_t* n, const int64_t* lda,
+                                 spamm_dtype dt, int32_t leaf, void* stream, spamm_matrix** out) {
+    if (count < 1 || count > kMaxBatch) return set_error(SPAMM_EINVAL, "count outside [1, 128]");
+    if (!dev_a || !n || !lda || !out) return set_error(SPAMM_EINVAL, "null argument");
+    if (dt != SPAMM_F32 && dt != SPAMM_F64) return set_error(SPAMM_EINVAL, "unknown dtype");
+    if (!leaf_ok(leaf)) return set_error(SPAMM_EINVAL, "leaf must be 32, 64 or 128");
+    for (int m = 0; m < count; ++m) {
+        if (!dev_a[m]) return set_error(SPAMM_EINVAL, "dev_a[m] is null");
+        if (n[m] < 1 || lda[m] < n[m]) return set_error(SPAMM_EINVAL, "need n >= 1 and lda >= n");
+        if (ceil_div(n[m], leaf) > kMaxNb) return set_error(SPAMM_EINVAL, "n / leaf exceeds 2^19 leaves");
+        if (out[m] && (out[m]->n != n[m] || out[m]->b != leaf || out[m]->dt != dt))
+            return set_error(SPAMM_EINVAL, "existing handle differs in n, leaf or dtype");
+        for (int q = 0; q < m; ++q)
+            if (out[m] && out[m] == out[q]) return set_error(SPAMM_EINVAL, "out handles must be distinct");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<spamm_matrix*> M(count, nullptr);
+    std::vector<bool> fresh(count, false);
+    auto release_fresh = [&]() {
+        for (int m = 0; m < count; ++m)
+            if (fresh[m] && M[m]) release(M[m]);
+    };
+    spamm_status st = SPAMM_OK;
+    for (int m = 0; m < count && st == SPAMM_OK; ++m) {
+        M[m] = out[m];
+        if (!M[m]) {
+            M[m] = new_handle(n[m], leaf, dt);
+            fresh[m] = true;
+            st = alloc_storage(M[m], s);
+        }
+    }
+    if (st != SPAMM_OK) {
+        release_fresh();
+        return st;
+    }
+    static thread_local std::vector<PackDesc> hp;
+    static thread_local std::vector<NormTable> ht;
+    hp.resize(count);
+    ht.resize(count);
+    int64_t waves = 0;
+    for (int m = 0; m < count; ++m) {
+        M[m]->last_stream = s;
+        M[m]->gen++;
+        hp[m] = pack_desc(dev_a[m], n[m], lda[m], M[m], status_word(M[m]), waves);
+        waves += hp[m].nb * hp[m].nstrips;
+        ht[m] = norm_table(M[m]);
+    }
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_tab = al(sizeof(PackDesc) * count), bytes = o_tab + al(sizeof(NormTable) * count);
+    char* ws = (char*)dev_alloc(M[0], bytes, s);
+    if (!ws) {
+        release_fresh();
+        return set_error(SPAMM_ENOMEM, "batch scratch allocation failed");
+    }
+    const PackDesc* d_pd = (const PackDesc*)ws;
+    const NormTable* d_tab = (const NormTable*)(ws + o_tab);
+    hipError_t e = hipMemcpyAsync(ws, hp.data(), sizeof(PackDesc) * count, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + o_tab, ht.data(), sizeof(NormTable) * count, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_pack_norm_batched(d_pd, count, waves, dt, leaf, s);
+    if (e == hipSuccess) e = launch_upper_norms_batched(M.data(), count, d_tab, s);
+    dev_free(M[0], ws, s);
+    if (e != hipSuccess) {
+        st = hip_error(e, "spamm_build_batched kernels");
+        release_fresh();
+        return st;
+    }
+    for (int m = 0; m < count; ++m) out[m] = M[m];
+    return SPAMM_OK;
+}
+
 spamm_status spamm_build(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf, void* stream,
                          spamm_matrix** out) {
     return spamm_build_ex(dev_a, n, lda, dt, leaf, dt == SPAMM_F64 ? SPAMM_LEAF_F64 : SPAMM_LEAF_F32, stream, out);
@@ -629,7 +699,7 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
                  o_ctr = o_f1 + al((size_t)cap * 8), o_cnt = o_ctr + al(sizeof(DevCounters) + 16 * kMaxBatch),
                  o_ord = o_cnt + al((size_t)total * 4), o_hist = o_ord + al((size_t)total * 4),
                  o_offs = o_hist + al((size_t)(maxc + 1) * 4), o_q = o_offs + al((size_t)(maxc + 1) * 4),
-                 bytes = o_q + 256;
+                 o_tab = o_q + 256, bytes = o_tab + al(sizeof(NormTable) * count);
     spamm_matrix* owner = out[0];
     char* ws = (char*)dev_alloc(owner, bytes, s);
     if (!ws) {
@@ -665,7 +735,12 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
         lp.list = (uint32_t*)(ws + o_ord);  // the order array holds the list
         lp.list_count = (unsigned*)(ws + o_q);
     }
+    static thread_local std::vector<NormTable> htab;
+    htab.resize(count);
+    for (int m = 0; m < count; ++m) htab[m] = norm_table(out[m]);
+    NormTable* d_tab = (NormTable*)(ws + o_tab);
     hipError_t e = hipMemcpyAsync(d_desc, hd.data(), sizeof(ProdDesc) * count, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_tab, htab.data(), sizeof(NormTable) * count, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_clear_masks(d_desc, count, s);
     if (e == hipSuccess)
         e = launch_cull_ex(d_desc, cp, nullptr, (uint64_t*)(ws + o_f0), (uint64_t*)(ws + o_f1), ctr, st != nullptr,
@@ -676,7 +751,7 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
     if (e == hipSuccess && sched == SPAMM_SCHED_LIST)
         e = launch_tile_list(d_desc, count, total, (uint32_t*)(ws + o_ord), (unsigned*)(ws + o_q), s);
     if (e == hipSuccess) e = launch_leaf_typed(d_desc, lp, A[0]->dt == SPAMM_F64, s);
-    for (int m = 0; m < count && e == hipSuccess; ++m) e = launch_upper_norms(out[m], s, nullptr);
+    if (e == hipSuccess) e = launch_upper_norms_batched(out.data(), count, d_tab, s);
     if (e == hipSuccess && st) {
         static thread_local DevCounters h;
         unsigned long long ne[kMaxBatch];

@@ -8,6 +8,9 @@
 // fused multiply-add in FP64 (exact for FP32 inputs).  The column sums of a
 // tile are then combined by the pairwise tree s_c += s_{c+h}, h = b/2 .. 1,
 // across lanes (shuffles) and finally inside a lane.
+#include <algorithm>
+#include <cstring>
+
 #include "spamm_internal.hpp"
 
 namespace spamm {
@@ -37,16 +40,15 @@ __device__ inline int8_t tile_exponent(double mx) {
     return (int8_t)e;
 }
 
+// Wave gw of one matrix: tile row I = gw / nstrips, column strip gw % nstrips.
 template <typename T, int B>
-__global__ void __launch_bounds__(256) k_pack_norm(const T* __restrict__ a, int64_t n, int64_t lda,
-                                                   int64_t nb, int64_t nstrips, T* __restrict__ tiles,
-                                                   double* __restrict__ S0, int8_t* __restrict__ texp,
-                                                   unsigned* status, int vec) {
+__device__ __forceinline__ void pack_wave(const T* __restrict__ a, int64_t n, int64_t lda, int64_t nb,
+                                          int64_t nstrips, T* __restrict__ tiles, double* __restrict__ S0,
+                                          int8_t* __restrict__ texp, unsigned* status, int vec, int64_t gw) {
     constexpr int V = Vec16<T>::V;
     constexpr int LPT = B / V;  // lanes per tile
     using VT = typename Vec16<T>::type;
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (gw >= nb * nstrips) return;
     const int64_t I = gw / nstrips;
     const int64_t s = gw % nstrips;
@@ -119,6 +121,35 @@ __global__ void __launch_bounds__(256) k_pack_norm(const T* __restrict__ a, int6
     }
 }
 
+template <typename T, int B>
+__global__ void __launch_bounds__(256) k_pack_norm(const T* __restrict__ a, int64_t n, int64_t lda,
+                                                   int64_t nb, int64_t nstrips, T* __restrict__ tiles,
+                                                   double* __restrict__ S0, int8_t* __restrict__ texp,
+                                                   unsigned* status, int vec) {
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    pack_wave<T, B>(a, n, lda, nb, nstrips, tiles, S0, texp, status, vec, gw);
+}
+
+// Batch: the waves of all matrices in one launch; wave_base is the first
+// global wave of each matrix (ascending), so a binary search finds the matrix.
+template <typename T, int B>
+__global__ void __launch_bounds__(256) k_pack_norm_batched(const PackDesc* __restrict__ pd, int count) {
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pd[mid].wave_base <= gw) lo = mid; else hi = mid - 1;
+    }
+    const PackDesc& d = pd[lo];
+    pack_wave<T, B>((const T*)d.a, d.n, d.lda, d.nb, d.nstrips, (T*)d.tiles, d.S0, d.texp, d.status, d.vec,
+                    gw - d.wave_base);
+}
+
+__global__ void k_zero_status_batched(const PackDesc* __restrict__ pd, int count) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < count) *pd[m].status = 0u;
+}
+
 // One tier up: P[I,K] = (S[2I,2K] + S[2I,2K+1]) + (S[2I+1,2K] + S[2I+1,2K+1]).
 __global__ void k_norm_parent(const double* __restrict__ S, int m, double* __restrict__ P, int mp,
                               const int* active) {
@@ -133,6 +164,50 @@ __global__ void k_norm_parent(const double* __restrict__ S, int m, double* __res
         c[q] = (i < m && k < m) ? S[(int64_t)i * m + k] : 0.0;
     }
     P[t] = (c[0] + c[1]) + (c[2] + c[3]);
+}
+
+constexpr int kSmallTier = 64;  // tiers with m_l <= kSmallTier go to the single-block kernels
+
+// Batch, one large tier l for every matrix (blockIdx.y) that has it.
+__global__ void k_norm_parent_batched(const NormTable* __restrict__ tab, int l) {
+    const NormTable& t = tab[blockIdx.y];
+    if (l > t.L) return;
+    const int m = t.m[l - 1], mp = t.m[l];
+    if (mp <= kSmallTier) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)mp * mp) return;
+    const double* S = t.norms + t.off[l - 1];
+    const int I = (int)(i / mp), K = (int)(i % mp);
+    double c[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = 2 * I + (q >> 1), k = 2 * K + (q & 1);
+        c[q] = (r < m && k < m) ? S[(int64_t)r * m + k] : 0.0;
+    }
+    t.norms[t.off[l] + i] = (c[0] + c[1]) + (c[2] + c[3]);
+}
+
+// Batch, the small tiers of matrix blockIdx.x in one block, tier by tier.
+__global__ void __launch_bounds__(1024) k_norm_small_tiers_batched(const NormTable* __restrict__ tab) {
+    const NormTable& t = tab[blockIdx.x];
+    int l0 = 1;
+    while (l0 <= t.L && t.m[l0] > kSmallTier) ++l0;
+    for (int l = l0; l <= t.L; ++l) {
+        const double* S = t.norms + t.off[l - 1];
+        double* P = t.norms + t.off[l];
+        const int m = t.m[l - 1], mp = t.m[l];
+        for (int i = threadIdx.x; i < mp * mp; i += blockDim.x) {
+            const int I = i / mp, K = i % mp;
+            double c[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = 2 * I + (q >> 1), k = 2 * K + (q & 1);
+                c[q] = (r < m && k < m) ? S[(int64_t)r * m + k] : 0.0;
+            }
+            P[i] = (c[0] + c[1]) + (c[2] + c[3]);
+        }
+        __syncthreads();
+    }
 }
 
 // The small upper tiers in one block, tier by tier.
@@ -285,7 +360,7 @@ hipError_t launch_pack_norm(const void* a, int64_t n, int64_t lda, spamm_dtype d
 
 // Upper tiers: one launch per large tier, then the small ones in one block.
 hipError_t launch_upper_norms(spamm_matrix* M, hipStream_t s, const int* active) {
-    constexpr int kSmall = 64;  // tiers with m_l <= kSmall go to the single-block kernel
+    constexpr int kSmall = kSmallTier;
     int l = 1;
     for (; l <= M->L && M->lvl_m[l] > kSmall; ++l) {
         const int m = M->lvl_m[l - 1], mp = M->lvl_m[l];
@@ -301,6 +376,84 @@ hipError_t launch_upper_norms(spamm_matrix* M, hipStream_t s, const int* active)
         hipLaunchKernelGGL(k_norm_small_tiers, dim3(1), dim3(1024), 0, s, M->norms, off, mm, l, M->L, active);
     }
     return hipGetLastError();
+}
+
+NormTable norm_table(const spamm_matrix* M) {
+    NormTable t;
+    std::memset(&t, 0, sizeof t);
+    t.norms = M->norms;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        t.off[l] = M->lvl_off[l];
+        t.m[l] = M->lvl_m[l];
+    }
+    t.L = M->L;
+    return t;
+}
+
+// Upper tiers of count handles: one launch per large tier for all of them,
+// then one block per handle for its small tiers.  d_tab: count device tables
+// (filled by the caller from norm_table).
+hipError_t launch_upper_norms_batched(spamm_matrix* const* M, int count, const NormTable* d_tab, hipStream_t s) {
+    int Lmax = 0;
+    for (int m = 0; m < count; ++m) Lmax = std::max(Lmax, M[m]->L);
+    for (int l = 1; l <= Lmax; ++l) {
+        int64_t cells = 0;
+        for (int m = 0; m < count; ++m)
+            if (l <= M[m]->L && M[m]->lvl_m[l] > kSmallTier)
+                cells = std::max<int64_t>(cells, (int64_t)M[m]->lvl_m[l] * M[m]->lvl_m[l]);
+        if (cells == 0) break;
+        hipLaunchKernelGGL(k_norm_parent_batched, dim3((unsigned)((cells + 255) / 256), (unsigned)count), dim3(256), 0,
+                           s, d_tab, l);
+    }
+    hipLaunchKernelGGL(k_norm_small_tiers_batched, dim3((unsigned)count), dim3(1024), 0, s, d_tab);
+    return hipGetLastError();
+}
+
+// One pack launch for count matrices of one element type and leaf size;
+// d_pd: count device descriptors (filled by the caller from pack_desc, in
+// order, so wave_base ascends).
+hipError_t launch_pack_norm_batched(const PackDesc* d_pd, int count, int64_t waves, spamm_dtype dt, int b,
+                                    hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_status_batched, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, d_pd, count);
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+#define SPAMM_PACK_B(T, BB) \
+    hipLaunchKernelGGL((k_pack_norm_batched<T, BB>), dim3(blocks), dim3(256), 0, s, d_pd, count)
+    if (dt == SPAMM_F32) {
+        switch (b) {
+            case 32: SPAMM_PACK_B(float, 32); break;
+            case 64: SPAMM_PACK_B(float, 64); break;
+            case 128: SPAMM_PACK_B(float, 128); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (b) {
+            case 32: SPAMM_PACK_B(double, 32); break;
+            case 64: SPAMM_PACK_B(double, 64); break;
+            case 128: SPAMM_PACK_B(double, 128); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+#undef SPAMM_PACK_B
+    return hipGetLastError();
+}
+
+// Descriptor of one matrix of a batched pack; wave_base as laid out by the caller.
+PackDesc pack_desc(const void* a, int64_t n, int64_t lda, spamm_matrix* M, unsigned* status, int64_t wave_base) {
+    PackDesc d;
+    std::memset(&d, 0, sizeof d);
+    const int V = M->dt == SPAMM_F32 ? 4 : 2;
+    d.a = a;
+    d.n = n;
+    d.lda = lda;
+    d.nb = M->nb;
+    d.nstrips = (M->nb * M->b + kWave * V - 1) / (kWave * V);
+    d.wave_base = wave_base;
+    d.tiles = M->tiles;
+    d.S0 = M->norms;
+    d.texp = M->texp;
+    d.status = status;
+    d.vec = ((uintptr_t)a % 16 == 0) && (lda % V == 0) && (n % V == 0);
+    return d;
 }
 
 hipError_t launch_to_dense(const spamm_matrix* M, void* out, int64_t ldo, hipStream_t s) {

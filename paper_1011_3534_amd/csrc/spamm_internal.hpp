@@ -171,6 +171,29 @@ int num_cus();
 hipError_t launch_pack_norm(const void* a, int64_t n, int64_t lda, spamm_dtype dt, spamm_matrix* M,
                             unsigned* status, int split_kind, hipStream_t s);
 hipError_t launch_upper_norms(spamm_matrix* M, hipStream_t s, const int* active);
+
+// Batched builds and result pyramids (norms.hip).
+struct PackDesc {
+    const void* a;            // dense row-major input
+    int64_t n, lda, nb, nstrips;
+    int64_t wave_base;        // first global wave of this matrix
+    void* tiles;
+    double* S0;               // leaf tier of the pyramid
+    int8_t* texp;
+    unsigned* status;
+    int32_t vec, pad_;
+};
+struct NormTable {
+    double* norms;
+    int64_t off[kMaxLevels];
+    int32_t m[kMaxLevels];
+    int32_t L, pad_;
+};
+PackDesc pack_desc(const void* a, int64_t n, int64_t lda, spamm_matrix* M, unsigned* status, int64_t wave_base);
+NormTable norm_table(const spamm_matrix* M);
+hipError_t launch_pack_norm_batched(const PackDesc* d_pd, int count, int64_t waves, spamm_dtype dt, int b,
+                                    hipStream_t s);
+hipError_t launch_upper_norms_batched(spamm_matrix* const* M, int count, const NormTable* d_tab, hipStream_t s);
 hipError_t launch_to_dense(const spamm_matrix* M, void* out, int64_t ldo, hipStream_t s);
 hipError_t launch_diff_norms(const spamm_matrix* X, const spamm_matrix* Y, double* d_out, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s);

@@ -102,3 +102,50 @@ def test_batched_output_reuse_and_errors():
         sp.multiply_batched([hs[0], h32], [hs[0], h32], [1e-6, 1e-6])
     with pytest.raises(sp.SpammError, match="EINVAL"):
         sp.multiply_batched([hs[0]], [hs[0]], [1e-6], outs=[hs[0]])
+
+
+@pytest.mark.parametrize("leaf,dtype", [(64, np.float32), (32, np.float64), (128, np.float32)])
+def test_build_batched_equals_single_builds(leaf, dtype):
+    # one pack launch and one launch per upper tier for the whole batch: the
+    # same pyramids (bit-exact, also against the oracle), tiles and tile
+    # exponents (through an FP16x3 product, which scales by them) as one
+    # spamm_build per matrix; ragged sizes, one smaller than a tile
+    print(f"[case] build_batched leaf={leaf} {np.dtype(dtype).name}", flush=True)
+    sizes = [1, 31, leaf, leaf + 1, 200, 513, 1000, 130]
+    mats = [si.exp_decay(n, 0.85, 400 + i, dtype) for i, n in enumerate(sizes)]
+    Hs = sp.build_batched([to_dev(a) for a in mats], leaf)
+    for a, H in zip(mats, Hs):
+        S = sp.build(to_dev(a), leaf)
+        assert H.levels == S.levels
+        ref = oracle.norm_pyramid(a.astype(np.float64), leaf)
+        for lv in range(S.levels + 1):
+            assert np.array_equal(H.norms(lv), S.norms(lv)) and np.array_equal(H.norms(lv), ref[lv])
+        assert np.array_equal(H.to_dense().cpu().numpy(), a)
+        if dtype == np.float32:
+            c1 = sp.multiply(H, H, 1e-6, "f16x3").to_dense().cpu().numpy()
+            c2 = sp.multiply(S, S, 1e-6, "f16x3").to_dense().cpu().numpy()
+            assert np.array_equal(c1, c2)
+    # rebuilt in place from other values
+    mats2 = [si.algebraic_decay(n, 2.0, 500 + i, dtype) for i, n in enumerate(sizes)]
+    Hs2 = sp.build_batched([to_dev(a) for a in mats2], leaf, outs=Hs)
+    assert all(x is y for x, y in zip(Hs, Hs2))
+    for a, H in zip(mats2, Hs2):
+        assert np.array_equal(H.norms(0), oracle.tile_sqnorms(a.astype(np.float64), leaf))
+        assert np.array_equal(H.to_dense().cpu().numpy(), a)
+
+
+def test_build_batched_errors():
+    print("[case] build_batched errors", flush=True)
+    a = to_dev(si.exp_decay(100, 0.85, 1, np.float32))
+    b = to_dev(si.exp_decay(200, 0.85, 2, np.float32))
+    with pytest.raises(sp.SpammError, match="EINVAL"):
+        sp.build_batched([], 64)
+    H = sp.build(a, 64)
+    with pytest.raises(sp.SpammError, match="EINVAL"):
+        sp.build_batched([a, b], 64, outs=[None, H])        # H has n = 100, not 200
+    with pytest.raises(sp.SpammError, match="EINVAL"):
+        sp.build_batched([a, a], 64, outs=[H, H])           # repeated handle
+    with pytest.raises(sp.SpammError, match="EINVAL"):
+        sp.build_batched([a, b], 48)                         # leaf size
+    Hs = sp.build_batched([a, b], 64)
+    assert [h.n for h in Hs] == [100, 200]
