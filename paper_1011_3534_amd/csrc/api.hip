@@ -300,6 +300,16 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
     cp.front_cap = ps->front_cap;
     cp.mask_words = C->nb * C->nb * ceil_div(C->nb, 64);
     cp.nonempty = nonempty_ctr(ps->ctr);
+    if (!depth_tau && !want_bound && C->L >= 2) {
+        // flat threshold, no per-tier statistics: start at the first tier of
+        // at most 64^3 nodes (the tiers above are implied by the flat rule);
+        // with L >= 2 that tier lies below the root, which the tier passes
+        // then never expand again
+        int fs = 1;
+        while (fs < C->L && C->lvl_m[fs] > 64) ++fs;
+        cp.flat_start = fs;
+        cp.flat_m = C->lvl_m[fs];
+    }
     int64_t items[kMaxLevels];
     tier_items(C, ps->front_cap, items);
     if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[0], s));

@@ -188,6 +188,56 @@ __global__ void __launch_bounds__(kTopThreads)
     if (threadIdx.x < kMaxLevels) ctr->front_count[threadIdx.x] = s_count[threadIdx.x];
 }
 
+// The frontier of tier s of a single product straight from the flat rule:
+// node (I,J,K) passes iff !(S_A[s][I,K] * S_B[s][K,J] < tau^2).  Tier norms
+// are FP64 sums of their children's non-negative norms (rounding is
+// monotone), so every ancestor of a passing node passes too and the descent
+// from the root keeps exactly this set; only the depth-scaled schedule, whose
+// thresholds differ per tier, needs the descent.  Kept nodes are compacted
+// per block (wave ballots, one atomic per block) into the tier-s buffer.
+__global__ void __launch_bounds__(kCullThreads)
+    k_cull_enum(const ProdDesc* __restrict__ desc, int s, int ms, uint64_t* __restrict__ out,
+                DevCounters* __restrict__ ctr, int64_t out_cap, const int* __restrict__ active) {
+    if (active && *active == 0) return;
+    __shared__ unsigned wave_tot[kCullThreads / kWave];
+    __shared__ unsigned long long block_base;
+    const ProdDesc& d = desc[0];
+    const double* SA = d.SA + d.lvl_off[s];
+    const double* SB = d.SB + d.lvl_off[s];
+    const int64_t total = (int64_t)ms * ms * ms;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    for (int64_t base = (int64_t)blockIdx.x * kCullThreads; base < total; base += (int64_t)gridDim.x * kCullThreads) {
+        const int64_t idx = base + threadIdx.x;
+        uint32_t I = 0, J = 0, K = 0;
+        bool keep = false;
+        if (idx < total) {
+            I = (uint32_t)(idx / ((int64_t)ms * ms));
+            J = (uint32_t)((idx / ms) % ms);
+            K = (uint32_t)(idx % ms);
+            keep = !(SA[(int64_t)I * ms + K] * SB[(int64_t)K * ms + J] < d.tau2);
+        }
+        const unsigned long long bal = __ballot(keep);
+        if (lane == 0) wave_tot[wid] = (unsigned)__popcll(bal);
+        __syncthreads();
+        unsigned wave_off = 0, block_tot = 0;
+        for (int w = 0; w < kCullThreads / kWave; ++w) {
+            if (w < wid) wave_off += wave_tot[w];
+            block_tot += wave_tot[w];
+        }
+        if (threadIdx.x == 0) {
+            block_base = block_tot ? atomicAdd(&ctr->front_count[s], (unsigned long long)block_tot) : 0ull;
+            if (block_tot) atomicAdd(&ctr->survivors[0][s], (unsigned long long)block_tot);
+        }
+        __syncthreads();
+        if (keep) {
+            const int64_t pos = (int64_t)block_base + wave_off + __popcll(bal & ((1ull << lane) - 1ull));
+            if (pos >= out_cap) atomicOr(&ctr->status, kDevCapacity);
+            else out[pos] = node_key(0, I, J, K);
+        }
+        __syncthreads();
+    }
+}
+
 // Counters, per-product non-empty tile counts and (single product) the leaf
 // bitmask, zeroed in one launch.
 __global__ void k_cull_prep(DevCounters* ctr, unsigned long long* nonempty, int nprod, uint64_t* mask,
@@ -244,15 +294,27 @@ hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t
                            words, active);
     }
     const int top = plan.Lmax < 1 ? 1 : plan.Lmax;
-    // tiers whose items fit a few passes of one block go to one launch
-    constexpr int64_t kOneBlockItems = 4 * kTopThreads;
     int l = top;
-    int stop = top;
-    while (stop >= 1 && tier_items[stop] + plan.count <= kOneBlockItems) --stop;
-    if (stop < top) {
-        hipLaunchKernelGGL(k_cull_top, dim3(1), dim3(kTopThreads), 0, s, d_desc, plan.count, top, stop, front0,
-                           front1, ctr, plan.front_cap, want_bound, active);
-        l = stop;
+    if (plan.flat_start >= 1) {
+        // tier flat_start enumerated directly; its frontier lives in buffer (flat_start & 1)
+        const int fs = plan.flat_start;
+        const int64_t cells = (int64_t)plan.flat_m * plan.flat_m * plan.flat_m;
+        int64_t blocks = (cells + kCullThreads - 1) / kCullThreads;
+        const int64_t maxb = (int64_t)num_cus() * 8;
+        blocks = blocks < 1 ? 1 : (blocks > maxb ? maxb : blocks);
+        hipLaunchKernelGGL(k_cull_enum, dim3((unsigned)blocks), dim3(kCullThreads), 0, s, d_desc, fs, plan.flat_m,
+                           (fs & 1) ? front1 : front0, ctr, plan.front_cap, active);
+        l = fs;
+    } else {
+        // tiers whose items fit a few passes of one block go to one launch
+        constexpr int64_t kOneBlockItems = 4 * kTopThreads;
+        int stop = top;
+        while (stop >= 1 && tier_items[stop] + plan.count <= kOneBlockItems) --stop;
+        if (stop < top) {
+            hipLaunchKernelGGL(k_cull_top, dim3(1), dim3(kTopThreads), 0, s, d_desc, plan.count, top, stop, front0,
+                               front1, ctr, plan.front_cap, want_bound, active);
+            l = stop;
+        }
     }
     for (; l >= 1; --l) {
         // frontier of tier l lives in buffer (l & 1); children go to ((l-1) & 1)

@@ -208,6 +208,8 @@ struct CullPlan {
     int64_t front_cap;      // capacity of each frontier buffer (keys)
     int64_t mask_words;     // total leaf-bitmask words
     unsigned long long* nonempty = nullptr;  // per-product non-empty tile counters (zeroed with the rest)
+    int flat_start = 0;     // single product, flat threshold: enumerate tier flat_start (>= 1) directly
+    int flat_m = 0;         //   its size m; the tiers above it are not visited (nor counted)
 };
 hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t* mask, uint64_t* front0,
                           uint64_t* front1, DevCounters* ctr, int want_bound, const int* active,

@@ -359,3 +359,24 @@ def test_depth_scaled_rejects_small_tau():
         sp.multiply(A, A, 1e-147, depth_scaled=True)
     sp.multiply(A, A, 1e-146, depth_scaled=True)
     sp.multiply(A, A, 0.0, depth_scaled=True)
+
+
+@pytest.mark.parametrize("n,b,tau", [(8192, 64, 1e-6), (4000, 32, 1e-6), (900, 64, 1e-5), (130, 64, 1e-6),
+                                     (100, 64, 1e-6), (700, 16 * 2, 0.0)])
+def test_flat_start_cull_matches_full_descent(n, b, tau):
+    # without statistics a single flat-threshold product enumerates the first
+    # tier of at most 64^3 nodes directly (the tiers above are implied by the
+    # flat rule): the kept triples equal the oracle's, and C equals the product
+    # culled by the full descent from the root (taken when statistics are on)
+    _case(f"flat-start cull n={n} b={b} tau={tau}")
+    a = si.algebraic_workload(n) if n == 8192 else si.algebraic_decay(n, 2.0, 41, np.float32)
+    A = sp.build(to_dev(a), b)
+    C1 = sp.multiply(A, A, tau, "f32")
+    C2, st = sp.multiply(A, A, tau, "f32", stats=True)
+    S = oracle.tile_sqnorms(a.astype(np.float64), b)
+    keys, _ = oracle.tasks_flat(S, S, tau)
+    assert np.array_equal(C1.task_list(), keys)
+    assert np.array_equal(C2.task_list(), keys) and st["tasks"] == len(keys)
+    assert np.array_equal(C1.to_dense().cpu().numpy(), C2.to_dense().cpu().numpy())
+    for lv in range(C1.levels + 1):
+        assert np.array_equal(C1.norms(lv), C2.norms(lv))
