@@ -166,18 +166,58 @@ __global__ void __launch_bounds__(1024) k_sp2_start(const double* part, int64_t 
         st->stagnated = 0;
         st->result_step = 0;
         st->list_count = 0;
+        st->fin_ticket = 0;
     }
 }
 
 // After step m: e_m from the per-tile partials, tr(X_{m+1}) from the diagonal
-// partials, the stop rules, and the branch of step m+1.
-__global__ void __launch_bounds__(1024) k_sp2_finalize(const double* part, int64_t nb,
-                                                       const unsigned long long* survivors0, Sp2State* st, int m) {
-    if (st->active == 0) return;
-    __shared__ double red[1024];
-    const double e2 = block_sum_fixed(part, nb * nb, red);
-    const double tr_next = block_sum_fixed(part + nb * nb, nb, red);
-    if (threadIdx.x != 0) return;
+// partials, the stop rules, and the branch of step m+1.  kFinBlocks blocks
+// each add a fixed contiguous range of the nb^2 partials in a fixed order;
+// the last block to finish (device-scope fence, then a ticket it resets)
+// adds the block sums in a fixed order, so the sums do not depend on timing.
+constexpr int kFinBlocks = 64;
+constexpr int kFinThreads = 256;
+
+__device__ double block_tree_sum(double v, double* red) {
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int h = kFinThreads / 2; h >= 1; h >>= 1) {
+        if (t < h) red[t] = red[t] + red[t + h];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(kFinThreads) k_sp2_finalize(const double* part, int64_t nb,
+                                                              const unsigned long long* survivors0, Sp2State* st,
+                                                              int m, double* bsum, unsigned* ticket) {
+    if (st->active == 0) return;  // read by every block before the last one writes it
+    __shared__ double red[kFinThreads];
+    __shared__ int s_last;
+    const int t = threadIdx.x;
+    const int64_t cnt = nb * nb;
+    const int64_t per = (cnt + kFinBlocks - 1) / kFinBlocks;
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < cnt ? lo + per : cnt;
+    double s = 0.0;
+    for (int64_t i = lo + t; i < hi; i += kFinThreads) s += part[i];
+    s = block_tree_sum(s, red);
+    if (t == 0) {
+        bsum[blockIdx.x] = s;
+        __threadfence();
+        s_last = atomicAdd(ticket, 1u) == kFinBlocks - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    const double e2 = block_tree_sum(t < kFinBlocks ? bsum[t] : 0.0, red);
+    double d = 0.0;
+    for (int64_t i = t; i < nb; i += kFinThreads) d += part[cnt + i];
+    const double tr_next = block_tree_sum(d, red);
+    if (t != 0) return;
+    *ticket = 0u;
     const double e = sqrt(e2);
     st->trace[m] = st->cur_trace;
     st->idem[m] = e;
@@ -315,7 +355,8 @@ hipError_t launch_sp2_init(const spamm_matrix* H, spamm_matrix* X, double* part,
 
 hipError_t launch_sp2_finalize(const double* part, int64_t nb, const unsigned long long* survivors0, Sp2State* st,
                                int m, hipStream_t s) {
-    hipLaunchKernelGGL(k_sp2_finalize, dim3(1), dim3(1024), 0, s, part, nb, survivors0, st, m);
+    hipLaunchKernelGGL(k_sp2_finalize, dim3(kFinBlocks), dim3(kFinThreads), 0, s, part, nb, survivors0, st, m,
+                       st->fin_bsum, &st->fin_ticket);
     return hipGetLastError();
 }
 

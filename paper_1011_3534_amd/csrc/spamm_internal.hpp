@@ -255,7 +255,8 @@ struct Sp2State {
     int br[SPAMM_SP2_MAX_ITER];
     unsigned long long tasks[SPAMM_SP2_MAX_ITER];
     unsigned list_count;  // C tiles of the current step that the leaf launch visits
-    unsigned pad2_;
+    unsigned fin_ticket;  // blocks of the per-step finalize that are done (reset by the last)
+    double fin_bsum[64];  // their partial sums
 };
 hipError_t launch_gershgorin(const spamm_matrix* H, double* lo, double* hi, Sp2State* st, hipStream_t s);
 hipError_t launch_sp2_init(const spamm_matrix* H, spamm_matrix* X, double* part, Sp2State* st, hipStream_t s);
