@@ -54,7 +54,7 @@ def _load():
     lib.orc_num_levels.restype = i32
     lib.orc_spamm_recursive.argtypes = [_DP, _DP, i64, i32, dbl, i32, _DP, _U64P, i64, _I64P]
     lib.orc_spamm_recursive.restype = i64
-    lib.orc_spamm_flat.argtypes = [_DP, _DP, i64, i32, dbl, i64, i64, _DP]
+    lib.orc_spamm_flat.argtypes = [_DP, _DP, i64, i32, dbl, i64, i64, i32, _DP]
     lib.orc_spamm_flat.restype = i64
     lib.orc_tasks_flat.argtypes = [_DP, _DP, i64, dbl, _U64P, i64, _DP]
     lib.orc_tasks_flat.restype = i64
@@ -134,17 +134,18 @@ def spamm_recursive(a, bm, b: int, tau: float, want_keys: bool = False, depth_sc
     return c, int(t), (keys[:t].copy() if want_keys else None), kept
 
 
-def spamm_flat(a, bm, b: int, tau: float, rows: tuple[int, int] | None = None):
+def spamm_flat(a, bm, b: int, tau: float, rows: tuple[int, int] | None = None, sym_upper: bool = False):
     """Flat enumeration of kept leaf triples; returns (C, T).
 
     rows = (I0, I1) restricts the work to C tile rows [I0, I1); the other rows
-    of the returned C are zero."""
+    of the returned C are zero.  sym_upper: symmetric squaring (A = B
+    symmetric): tiles I <= J by the rule, C_JI = C_IJ^T; T counts those."""
     a, bm = _f64(a), _f64(bm)
     n = a.shape[0]
     nb = -(-n // b)
     I0, I1 = rows if rows is not None else (0, nb)
     c = np.zeros((n, n), dtype=np.float64)
-    t = _load().orc_spamm_flat(_p(a), _p(bm), n, b, float(tau), I0, I1, _p(c))
+    t = _load().orc_spamm_flat(_p(a), _p(bm), n, b, float(tau), I0, I1, int(bool(sym_upper)), _p(c))
     if t < 0:
         raise ValueError(f"orc_spamm_flat failed ({t})")
     return c, int(t)

@@ -46,10 +46,12 @@ def initial_x(h) -> np.ndarray:
     return x / (hi - lo)
 
 
-def step(x, n_occ: int, b: int, tau: float):
-    """One TC2 step from X (FP64).  Returns (X_next, trace, idem, branch, T)."""
+def step(x, n_occ: int, b: int, tau: float, symmetric: bool = False):
+    """One TC2 step from X (FP64).  Returns (X_next, trace, idem, branch, T).
+
+    symmetric: the squaring forms the tiles I <= J and mirrors the others."""
     x = np.asarray(x, dtype=np.float64)
-    y, t_count = spamm_flat(x, x, b, tau)
+    y, t_count = spamm_flat(x, x, b, tau, sym_upper=symmetric)
     tr = float(np.trace(x))
     idem = float(np.linalg.norm(y - x))
     branch = 0 if tr > n_occ else 1          # 0: X <- X^2 ; 1: X <- 2X - X^2
@@ -57,13 +59,13 @@ def step(x, n_occ: int, b: int, tau: float):
     return x_next, tr, idem, branch, t_count
 
 
-def sp2(h, n_occ: int, b: int, tau: float, max_iter: int = 60, tol: float = 1e-8):
-    """TC2 purification; returns (P, log dict)."""
+def sp2(h, n_occ: int, b: int, tau: float, max_iter: int = 60, tol: float = 1e-8, symmetric: bool = False):
+    """TC2 purification; returns (P, log dict).  symmetric: symmetric squarings."""
     x = initial_x(h)
     log = {"trace": [], "idem": [], "branch": [], "tasks": [], "converged": False,
            "stagnated": False}
     for m in range(max_iter):
-        x_next, tr, idem, br, t = step(x, n_occ, b, tau)
+        x_next, tr, idem, br, t = step(x, n_occ, b, tau, symmetric)
         log["trace"].append(tr)
         log["idem"].append(idem)
         log["branch"].append(br)

@@ -223,13 +223,16 @@ int64_t orc_spamm_recursive(const double* a, const double* bm, int64_t n, int32_
 
 /* Flat SpAMM over the C tile rows [I0, I1): keep(I,J,K) <=> !(S_A[I,K] S_B[K,J] < tau^2)
  * on the leaf norms; every C tile sums its kept products in ascending K.
- * Rows of C outside [I0*b, I1*b) are left untouched.  Returns the number of
- * leaf products taken. */
+ * Rows of C outside [I0*b, I1*b) are left untouched.  sym_upper (the
+ * symmetric squaring of a symmetric A = B, all rows): only the tiles with
+ * I <= J are formed by the rule, and C_JI is set to the transpose of C_IJ.
+ * Returns the number of leaf products taken. */
 int64_t orc_spamm_flat(const double* a, const double* bm, int64_t n, int32_t b, double tau,
-                       int64_t I0, int64_t I1, double* c) {
+                       int64_t I0, int64_t I1, int32_t sym_upper, double* c) {
     if (n < 1 || !is_pow2(b) || !(tau >= 0.0) || isinf(tau)) return -1;
     int64_t nb = ceil_div(n, b);
     if (I0 < 0 || I1 > nb || I0 > I1) return -1;
+    if (sym_upper && (I0 != 0 || I1 != nb)) return -1;
     double* SA = (double*)malloc(sizeof(double) * (size_t)(nb * nb));
     double* SB = (double*)malloc(sizeof(double) * (size_t)(nb * nb));
     orc_tile_sqnorms(a, n, n, b, SA);
@@ -244,6 +247,7 @@ int64_t orc_spamm_flat(const double* a, const double* bm, int64_t n, int32_t b, 
 #pragma omp for schedule(dynamic, 1)
         for (int64_t t = 0; t < ntiles; ++t) {
             int64_t I = I0 + t / nb, J = t % nb;
+            if (sym_upper && J < I) continue;
             for (int64_t K = 0; K < nb; ++K) {
                 if (SA[I * nb + K] * SB[K * nb + J] < tau2) continue;
                 leaf_product_add(a, bm, n, b, I, J, K, c, P);
@@ -252,6 +256,10 @@ int64_t orc_spamm_flat(const double* a, const double* bm, int64_t n, int32_t b, 
         }
         free(P);
     }
+    if (sym_upper)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                if (j / b < i / b) c[i * n + j] = c[j * n + i];
     free(SA);
     free(SB);
     return total;

@@ -76,3 +76,61 @@ def test_sp2_stagnation_stops_divergence():
     P, log = sp2.sp2(h, 128, 16, 1e-6, 80, 1e-12)
     assert log["stagnated"] and log["iterations"] < 80
     assert np.linalg.norm(P @ P - P) < 1e-4
+
+
+# ---------------------------------------------------------------- symmetric squaring
+# For X = X^T the squaring can form the tiles I <= J by the flat rule and
+# mirror the rest (C_JI = C_IJ^T).  These pins do not use that code path.
+
+def _int_sym(n, seed):
+    # small-integer symmetric decaying matrix: every tile norm and every product
+    # is an exact FP64 integer, so keep sets and products are exactly symmetric
+    rng = np.random.default_rng(seed)
+    i = np.arange(n)
+    base = np.round(40.0 * 0.8 ** np.abs(i[:, None] - i[None, :]))
+    u = rng.integers(1, 4, (n, n)).astype(np.float64)
+    u = np.triu(u) + np.triu(u, 1).T
+    return base * u
+
+
+@pytest.mark.parametrize("n,b,tau", [(96, 8, 50.0), (130, 16, 300.0), (64, 16, 0.0)])
+def test_sym_square_equals_general_rule_on_exact_inputs(n, b, tau):
+    # catches: lower tiles formed instead of mirrored (T too big), a missed
+    # upper tile or the diagonal tiles left out, the transpose of the mirror
+    # taken the wrong way round (wrong values below the diagonal)
+    from oracle import spamm_flat, tasks_flat, tile_sqnorms, unpack_keys
+    x = _int_sym(n, 7)
+    c_sym, t_sym = spamm_flat(x, x, b, tau, sym_upper=True)
+    c_gen, t_gen = spamm_flat(x, x, b, tau)
+    assert np.array_equal(c_sym, c_gen)
+    S = tile_sqnorms(x, b)
+    keys, _ = tasks_flat(S, S, tau)
+    I, J, _ = unpack_keys(keys)
+    assert t_sym == int(np.sum(I <= J)) and t_gen == len(keys)
+    if tau == 0.0:
+        assert np.array_equal(c_sym, x @ x)        # integers: exact either way
+
+
+def test_sym_square_result_is_symmetric_and_near_the_general_rule():
+    from oracle import spamm_flat
+    x = si.exp_decay(300, 0.9, 3)                   # symmetric FP64
+    for tau in (1e-3, 1e-6):
+        c_sym, _ = spamm_flat(x, x, 32, tau, sym_upper=True)
+        c_gen, _ = spamm_flat(x, x, 32, tau)
+        i = np.arange(300)
+        lower = (i[:, None] // 32) > (i[None, :] // 32)      # elements of tiles I > J
+        assert np.array_equal(c_sym[lower], c_sym.T[lower])
+        absx = np.abs(x)
+        assert np.all(np.abs(c_sym - c_gen) <= 64 * 2.0 ** -53 * (absx @ absx) + 1e-300)
+
+
+def test_sp2_symmetric_squarings_match_eigh_projector():
+    n, n_occ = 256, 128
+    h = si.sp2_hamiltonian(n, 0.85, 4, np.float64, gap=4.0)
+    P, log = sp2.sp2(h, n_occ, 16, 0.0, max_iter=100, tol=1e-9, symmetric=True)
+    w, v = np.linalg.eigh(h)
+    pe = v[:, :n_occ] @ v[:, :n_occ].T
+    assert log["converged"]
+    assert np.max(np.abs(P - pe)) < 1e-8
+    assert abs(log["energy"] - w[:n_occ].sum()) < 1e-8 * abs(w[:n_occ].sum())
+    assert log["tasks"][0] < (n // 16) ** 3        # only the upper tiles are formed
