@@ -317,6 +317,19 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
                        double idem_tol, spamm_leaf_prec prec, void* stream, spamm_matrix** P,
                        spamm_sp2_log* log);
 
+/* spamm_sp2 with options.  SPAMM_SP2_SYMMETRIC: every squaring is a
+ * symmetric squaring, the TC2 iteration's X being symmetric: only the C
+ * tiles with I <= J are formed by Eq. (4) (kept K of tile (I, J) by the flat
+ * rule), and tile (J, I) is written as the transpose of tile (I, J), with the
+ * norm of the stored values in the canonical order; X stays exactly
+ * symmetric off the diagonal tiles and the leaf work about halves.  H must be
+ * exactly symmetric (checked: EINVAL otherwise).  Other arguments, results
+ * and errors as spamm_sp2; the per-step task counts are those formed. */
+#define SPAMM_SP2_SYMMETRIC 1
+spamm_status spamm_sp2_ex(const spamm_matrix* H, int64_t n_occ, double tau, int32_t max_iter,
+                          double idem_tol, spamm_leaf_prec prec, int32_t flags, void* stream,
+                          spamm_matrix** P, spamm_sp2_log* log);
+
 /* ------------------------------------------------------------------ learned tau */
 
 /* The paper sets tau by hand to match energy errors (section 3).  The

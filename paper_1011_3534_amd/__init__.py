@@ -130,6 +130,7 @@ def lib():
         "spamm_multiply_timed": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Timing)], i32),
         "spamm_multiply_batched": ([i32, PP, PP, ctypes.POINTER(dbl), i32, ctypes.POINTER(Tune), _VP, PP,
                                     ctypes.POINTER(Stats)], i32),
+        "spamm_sp2_ex": ([_VP, i64, dbl, i32, dbl, i32, i32, _VP, PP, ctypes.POINTER(Sp2Log)], i32),
         "spamm_sp2": ([_VP, i64, dbl, i32, dbl, i32, _VP, PP, ctypes.POINTER(Sp2Log)], i32),
         "spamm_autotune_batched": ([i32, PP, ctypes.POINTER(i64), i32, ctypes.POINTER(dbl), i32,
                                     ctypes.POINTER(i32), i32, dbl, i32, ctypes.c_char_p, _VP,
@@ -394,12 +395,14 @@ def autotune_batched(dense, taus, prec: str = "f32", leaves=(32, 64, 128), max_r
 
 
 def sp2(H: Matrix, n_occ: int, tau: float, max_iter: int = 60, idem_tol: float = 1e-6,
-        prec: str = "f32", stream=None):
-    """TC2 purification (section 3) with SpAMM squarings; returns (P, log dict)."""
+        prec: str = "f32", stream=None, symmetric: bool = False):
+    """TC2 purification (section 3) with SpAMM squarings; returns (P, log dict).
+
+    symmetric: symmetric squarings (tiles I <= J formed, the others mirrored)."""
     h = ctypes.c_void_p()
     log = Sp2Log()
-    code = lib().spamm_sp2(H.handle, int(n_occ), float(tau), int(max_iter), float(idem_tol), LEAF[prec],
-                           _stream(stream), ctypes.byref(h), ctypes.byref(log))
+    code = lib().spamm_sp2_ex(H.handle, int(n_occ), float(tau), int(max_iter), float(idem_tol), LEAF[prec],
+                              1 if symmetric else 0, _stream(stream), ctypes.byref(h), ctypes.byref(log))
     if code not in (0, 6):
         _check(code)
     d = log.to_dict()

@@ -795,8 +795,16 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
 
 spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t max_iter, double idem_tol,
                        spamm_leaf_prec prec, void* stream, spamm_matrix** P, spamm_sp2_log* log) {
+    return spamm_sp2_ex(H, n_occ, tau, max_iter, idem_tol, prec, 0, stream, P, log);
+}
+
+spamm_status spamm_sp2_ex(const spamm_matrix* H, int64_t n_occ, double tau, int32_t max_iter, double idem_tol,
+                          spamm_leaf_prec prec, int32_t flags, void* stream, spamm_matrix** P,
+                          spamm_sp2_log* log) {
     using namespace spamm;
     if (!H || !P) return set_error(SPAMM_EINVAL, "null argument");
+    if (flags & ~SPAMM_SP2_SYMMETRIC) return set_error(SPAMM_EINVAL, "unknown SP2 flags");
+    const bool symmetric = (flags & SPAMM_SP2_SYMMETRIC) != 0;
     if (n_occ < 0 || n_occ > H->n) return set_error(SPAMM_EINVAL, "n_occ outside [0, n]");
     if (max_iter < 1 || max_iter > SPAMM_SP2_MAX_ITER) return set_error(SPAMM_EINVAL, "max_iter outside [1, 256]");
     if (!(idem_tol >= 0.0) || !std::isfinite(idem_tol)) return set_error(SPAMM_EINVAL, "idem_tol must be >= 0");
@@ -865,6 +873,18 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
         return r;
     };
     hipError_t e = hipMemcpyAsync(st, &h, sizeof h, hipMemcpyHostToDevice, s);
+    if (symmetric) {
+        // symmetric squarings mirror every tile below the diagonal: H must be
+        // exactly symmetric (then X_0 and every X_m are)
+        unsigned bad = 0;
+        if (e == hipSuccess) e = launch_check_symmetric(H, &st->sym_bad, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&bad, &st->sym_bad, 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess && bad) {
+            cleanup();
+            return set_error(SPAMM_EINVAL, "symmetric SP2 needs an exactly symmetric H");
+        }
+    }
     if (e == hipSuccess) e = launch_gershgorin(H, glo, ghi, st, s);
     if (e == hipSuccess) e = launch_sp2_init(H, X[0], part, st, s);
     // descriptors of the two directions X0 -> X1 and X1 -> X0
@@ -872,6 +892,7 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
         spamm_matrix* src = X[i];
         spamm_matrix* dst = X[1 - i];
         ProdDesc d = make_desc(src, src, dst, tau);
+        d.sym_upper = symmetric;
         d.sp2_part = part;
         d.X = src->tiles;
         dst->ps->host_desc = d;
@@ -889,8 +910,10 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
         spamm_matrix* dst = X[(m + 1) & 1];
         // tau > 0: the leaf launch visits the listed tiles only; at tau = 0
         // every tile has kept products and the static full grid is faster
+        // (symmetric squarings always list: tiles below the diagonal are
+        // written by their mirrors, never by a block of their own)
         r = enqueue_product(src, src, dst, tau, prec, cs, 0, 1, d_branch, d_active, dst->ps->desc,
-                            tau > 0.0 ? tile_list : nullptr, st);
+                            (tau > 0.0 || symmetric) ? tile_list : nullptr, st);
         if (r == SPAMM_OK) {
             e = launch_sp2_finalize(part, nb, &dst->ps->ctr->survivors[0][0], st, m, cs);
             if (e != hipSuccess) r = hip_error(e, "sp2 finalize launch");

@@ -86,6 +86,9 @@ __device__ void cull_pass(const ProdDesc* __restrict__ desc, int nprod, int l, c
             for (int q = 0; q < 8; ++q) {
                 const uint32_t Ic = 2 * I + (q >> 2), Jc = 2 * J + ((q >> 1) & 1), Kc = 2 * K + (q & 1);
                 if ((int)Ic >= mc || (int)Jc >= mc || (int)Kc >= mc) continue;
+                // symmetric squaring: a node with I > J holds only tiles below
+                // the diagonal, which are mirrored, not formed
+                if (d.sym_upper && Ic > Jc) continue;
                 const double sa = SA[(int64_t)Ic * mc + Kc];
                 const double sb = SB[(int64_t)Kc * mc + Jc];
                 if (sa * sb < t2) {
@@ -214,7 +217,7 @@ __global__ void __launch_bounds__(kCullThreads)
             I = (uint32_t)(idx / ((int64_t)ms * ms));
             J = (uint32_t)((idx / ms) % ms);
             K = (uint32_t)(idx % ms);
-            keep = !(SA[(int64_t)I * ms + K] * SB[(int64_t)K * ms + J] < d.tau2);
+            keep = !(SA[(int64_t)I * ms + K] * SB[(int64_t)K * ms + J] < d.tau2) && !(d.sym_upper && I > J);
         }
         const unsigned long long bal = __ballot(keep);
         if (lane == 0) wave_tot[wid] = (unsigned)__popcll(bal);

@@ -662,7 +662,22 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             Cg[r * B + c + j] = v[j];
         }
     }
-    if constexpr (SP2) __syncthreads();
+    // symmetric squaring: tile (J, I) below the diagonal is the transpose of
+    // this one (rows of C_JI from the columns of the staged tile; lanes walk
+    // the rows so the LDS reads are conflict-free)
+    const bool mirror = d.sym_upper && I < J;
+    if (SP2 || mirror) __syncthreads();
+    if (mirror) {
+        GLOBAL TC* Mg = (GLOBAL TC*)d.C + ((int64_t)J * nb + I) * TS;
+        for (int u = tid; u < B * B / VC; u += 256) {
+            const int r = u % B, c = (u / B) * VC;
+            TC v[VC];
+#pragma unroll
+            for (int j = 0; j < VC; ++j) v[j] = (TC)Cs[(c + j) * G::SC + r];
+#pragma unroll
+            for (int j = 0; j < VC; ++j) Mg[r * B + c + j] = v[j];
+        }
+    }
 
     // block reductions in a fixed order (deterministic)
     for (int dd = 32; dd >= 1; dd >>= 1) {
@@ -718,6 +733,33 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
                 if (I == J) d.sp2_part[(int64_t)nb * nb + I] = tr;
             }
         }
+    } else if (w == 1 && mirror) {
+        // canonical squared norm of the mirrored tile: its column c is row c
+        // of the staged tile, summed over its rows in ascending order
+        double s = 0.0;
+        if (lane < B) {
+            if constexpr (B == 128) {
+                double s2 = 0.0;
+                for (int r = 0; r < B; ++r) {
+                    const double a0 = (double)(TC)Cs[lane * G::SC + r];
+                    const double a1 = (double)(TC)Cs[(lane + 64) * G::SC + r];
+                    s = __fma_rn(a0, a0, s);
+                    s2 = __fma_rn(a1, a1, s2);
+                }
+                s = s + s2;
+            } else {
+                for (int r = 0; r < B; ++r) {
+                    const double a0 = (double)(TC)Cs[lane * G::SC + r];
+                    s = __fma_rn(a0, a0, s);
+                }
+            }
+        }
+        constexpr int H0 = (B == 128 ? 64 : B) / 2;
+        for (int h = H0; h >= 1; h >>= 1) {
+            const double o = __shfl_down(s, h, 64);
+            if (lane < h) s = s + o;
+        }
+        if (lane == 0) d.SC[(int64_t)J * nb + I] = s;
     }
     __syncthreads();
     if (tid == 0) {
@@ -729,6 +771,10 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         }
         d.eC[local] = (int8_t)e;
         if constexpr (SP2) d.sp2_part[local] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        if (mirror) {
+            d.eC[(int64_t)J * nb + I] = (int8_t)e;
+            if constexpr (SP2) d.sp2_part[(int64_t)J * nb + I] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        }
     }
     __syncthreads();  // red and smem are reused by the next tile of a persistent block
 }

@@ -288,13 +288,18 @@ __global__ void __launch_bounds__(256) k_sp2_tiles(const ProdDesc* __restrict__ 
     const int64_t nb = d.nb, tiles = nb * nb;
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     bool need = false;
-    if (t < tiles) {
+    // symmetric squaring: a tile below the diagonal is written (values,
+    // norm, exponent, partial) by its mirror above, so it is never listed
+    const int64_t I = t / nb, J = t % nb;
+    if (t < tiles && !(d.sym_upper && I > J)) {
+        const int64_t mirror = J * nb + I;
         uint64_t any = 0;
         for (int k = 0; k < d.W; ++k) any |= d.mask[t * d.W + k];
-        need = any != 0 || d.SA[t] != 0.0 || d.eC[t] != -128;
+        need = any != 0 || d.SA[t] != 0.0 || d.eC[t] != -128 || (d.sym_upper && I < J && d.eC[mirror] != -128);
         if (!need) {
             d.sp2_part[t] = 0.0;
-            if (t / nb == t % nb) d.sp2_part[tiles + t / nb] = 0.0;
+            if (I == J) d.sp2_part[tiles + I] = 0.0;
+            if (d.sym_upper && I < J) d.sp2_part[mirror] = 0.0;
         }
     }
     const unsigned long long m = __ballot(need);
@@ -304,6 +309,26 @@ __global__ void __launch_bounds__(256) k_sp2_tiles(const ProdDesc* __restrict__ 
     if (lane == 0) base = atomicAdd(&st->list_count, (unsigned)__popcll(m));
     base = (unsigned)__shfl((int)base, 0, 64);
     if (need) list[base + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)t;
+}
+
+// Exact symmetry of H, one block per tile pair (I <= J): element (r, c) of
+// tile (I, J) equals element (c, r) of tile (J, I).  Pairs of zero tiles
+// (both squared norms 0) are not read.
+__global__ void __launch_bounds__(256) k_check_symmetric(const float* __restrict__ T, const double* __restrict__ S,
+                                                         int64_t nb, int b, unsigned* flag) {
+    const int64_t t = blockIdx.x;
+    const int64_t I = t / nb, J = t % nb;
+    if (I > J) return;
+    if (S[I * nb + J] == 0.0 && S[J * nb + I] == 0.0) return;
+    const int64_t ts = (int64_t)b * b;
+    const float* a = T + (I * nb + J) * ts;
+    const float* m = T + (J * nb + I) * ts;
+    bool bad = false;
+    for (int e = threadIdx.x; e < b * b; e += 256) {
+        const int r = e / b, c = e % b;
+        bad |= !(a[e] == m[c * b + r]) && !(a[e] != a[e] && m[c * b + r] != m[c * b + r]);
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
 }
 
 __global__ void __launch_bounds__(1024) k_sum_to(const double* x, int64_t count, double* out) {
@@ -324,6 +349,13 @@ hipError_t launch_sp2_tiles(const ProdDesc* d_desc, int64_t nb, uint32_t* list, 
                             hipStream_t s) {
     const int64_t tiles = nb * nb;
     hipLaunchKernelGGL(k_sp2_tiles, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, s, d_desc, list, st, active);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_symmetric(const spamm_matrix* H, unsigned* flag, hipStream_t s) {
+    if (H->dt != SPAMM_F32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_check_symmetric, dim3((unsigned)(H->nb * H->nb)), dim3(256), 0, s, (const float*)H->tiles,
+                       H->norms, H->nb, H->b, flag);
     return hipGetLastError();
 }
 

@@ -98,6 +98,8 @@ struct ProdDesc {
     int32_t nb, L, W;
     int32_t a_f64, b_f64;     // operand tile element types (1 = FP64)
     int32_t depth_tau;        // 1: a node at depth k below the root is tested against tau / 8^k
+    int32_t sym_upper;        // 1: symmetric squaring: only tiles I <= J are formed, C_JI = C_IJ^T
+    int32_t pad_;
 };
 
 // Device-side counters of one product launch sequence.
@@ -257,6 +259,8 @@ struct Sp2State {
     unsigned list_count;  // C tiles of the current step that the leaf launch visits
     unsigned fin_ticket;  // blocks of the per-step finalize that are done (reset by the last)
     double fin_bsum[64];  // their partial sums
+    unsigned sym_bad;     // symmetric SP2: set when H is not exactly symmetric
+    unsigned pad3_;
 };
 hipError_t launch_gershgorin(const spamm_matrix* H, double* lo, double* hi, Sp2State* st, hipStream_t s);
 hipError_t launch_sp2_init(const spamm_matrix* H, spamm_matrix* X, double* part, Sp2State* st, hipStream_t s);
@@ -266,6 +270,7 @@ hipError_t launch_energy(const spamm_matrix* P, const spamm_matrix* H, double* t
                          hipStream_t s);
 hipError_t launch_sp2_tiles(const ProdDesc* d_desc, int64_t nb, uint32_t* list, Sp2State* st, const int* active,
                             hipStream_t s);
+hipError_t launch_check_symmetric(const spamm_matrix* H, unsigned* flag, hipStream_t s);
 
 // api.hip: cull + leaf products + result pyramid of one product, enqueued
 spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C, double tau,

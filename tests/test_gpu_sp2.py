@@ -102,3 +102,61 @@ def test_sp2_truncated_energy_close_to_exact():
     print(f"[case] sp2 tau=1e-5 dE={rel:.2e} iters={log1['iterations']} vs {log0['iterations']}", flush=True)
     assert rel < 1e-5
     assert sum(log1["tasks"]) < 0.7 * sum(log0["tasks"])
+
+
+# ------------------------------------------------------------------ symmetric squarings
+
+def test_sp2_symmetric_step_replay_matches_oracle():
+    # symmetric squarings: tiles I <= J formed, the others mirrored.  The GPU's
+    # stored X_k fed to the oracle's symmetric step gives the same task count
+    # and branch; trace, idempotency and X_{k+1} agree
+    n, b, n_occ, tau = 384, 32, 192, 1e-5
+    h = si.sp2_hamiltonian(n, 0.85, 7, np.float32)
+    H = sp.build(to_dev(h), b)
+    for k in (1, 6, 15):
+        print(f"[case] symmetric sp2 replay k={k}", flush=True)
+        Pk, logk = sp.sp2(H, n_occ, tau, max_iter=k, idem_tol=0.0, symmetric=True)
+        assert logk["status"] == "ENOCONV" and logk["result_step"] == k
+        xk = Pk.to_dense().cpu().numpy().astype(np.float64)
+        Pk1, logk1 = sp.sp2(H, n_occ, tau, max_iter=k + 1, idem_tol=0.0, symmetric=True)
+        x_next, tr, idem, br, T = osp2.step(xk, n_occ, b, tau, symmetric=True)
+        assert logk1["tasks"][k] == T
+        assert logk1["branch"][k] == br
+        assert abs(logk1["trace"][k] - tr) < 1e-9 * n
+        assert abs(logk1["idem"][k] - idem) < 1e-5 * max(idem, 1.0)
+        x1 = Pk1.to_dense().cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(x1 - x_next)) < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16x3"])
+def test_sp2_symmetric_projector_exact_mirror(prec):
+    print(f"[case] symmetric sp2 vs eigh prec={prec}", flush=True)
+    n, b, n_occ = 512, 32, 256
+    h = si.sp2_hamiltonian(n, 0.85, 4, np.float32, gap=4.0)
+    H = sp.build(to_dev(h), b)
+    P, log = sp.sp2(H, n_occ, 1e-7, max_iter=100, idem_tol=1e-6, prec=prec, symmetric=True)
+    _, log_g = sp.sp2(H, n_occ, 1e-7, max_iter=100, idem_tol=1e-6, prec=prec)
+    assert log["status"] == "OK" and (log["converged"] or log["stagnated"])
+    w, v = np.linalg.eigh(h.astype(np.float64))
+    pe = v[:, :n_occ] @ v[:, :n_occ].T
+    pd = P.to_dense().cpu().numpy()
+    assert np.max(np.abs(pd.astype(np.float64) - pe)) < 5e-5
+    assert abs(log["energy"] - w[:n_occ].sum()) < 1e-5 * abs(w[:n_occ].sum())
+    i = np.arange(n)
+    lower = (i[:, None] // b) > (i[None, :] // b)
+    assert np.array_equal(pd[lower], pd.T[lower])          # mirrored tiles, bit for bit
+    # the stored pyramid is that of the stored values, mirrored tiles included
+    for lv, r in enumerate(oracle.norm_pyramid(pd.astype(np.float64), b)):
+        assert np.array_equal(P.norms(lv), r)
+    assert log["tasks"][0] < 0.6 * log_g["tasks"][0]       # about half the products
+
+
+def test_sp2_symmetric_rejects_unsymmetric_h():
+    print("[case] symmetric sp2 EINVAL", flush=True)
+    h = si.sp2_hamiltonian(256, 0.85, 4, np.float32)
+    h[3, 70] += 1e-3
+    H = sp.build(to_dev(h), 32)
+    with pytest.raises(sp.SpammError, match="EINVAL"):
+        sp.sp2(H, 128, 1e-6, max_iter=5, symmetric=True)
+    P, log = sp.sp2(H, 128, 1e-6, max_iter=5)              # the general squaring still runs
+    assert log["iterations"] == 5
