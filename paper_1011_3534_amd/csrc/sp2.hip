@@ -89,28 +89,47 @@ __global__ void __launch_bounds__(1024) k_gersh_reduce(const double* lo, const d
 }
 
 // X_0 = (eps_max I - H) / (eps_max - eps_min) over the padded tile storage
-// (padding stays zero).
-__global__ void k_sp2_init_x(const float* __restrict__ H, float* __restrict__ X, int64_t n, int b, int64_t nb,
-                             const Sp2State* st) {
-    const int64_t total = nb * nb * (int64_t)b * b;
+// (padding stays zero), one block per tile.  An off-diagonal tile of H with
+// squared norm 0 is all zero, so its X_0 tile is written as zeros without
+// reading H.
+template <int B>
+__global__ void __launch_bounds__(256) k_sp2_init_x(const float* __restrict__ H, const double* __restrict__ SH,
+                                                    float* __restrict__ X, int64_t n, int64_t nb,
+                                                    const Sp2State* st) {
+    const int64_t tile = blockIdx.x;
+    const int64_t I = tile / nb, K = tile % nb;
+    constexpr int64_t TS = (int64_t)B * B;
+    float* x = X + tile * TS;
+    if (I != K && SH[tile] == 0.0) {
+        for (int e = threadIdx.x * 4; e < B * B; e += 256 * 4)
+            *reinterpret_cast<float4*>(x + e) = make_float4(0.f, 0.f, 0.f, 0.f);
+        return;
+    }
     const double emax = st->eps_max, den = st->eps_max - st->eps_min;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t tile = e / ((int64_t)b * b), in = e % ((int64_t)b * b);
-        const int64_t row = (tile / nb) * b + in / b, col = (tile % nb) * b + in % b;
-        double x = 0.0;
-        if (row < n && col < n) x = ((row == col ? emax : 0.0) - (double)H[e]) / den;
-        X[e] = (float)x;
+    const float* h = H + tile * TS;
+    for (int e = threadIdx.x; e < B * B; e += 256) {
+        const int64_t row = I * B + e / B, col = K * B + e % B;
+        double v = 0.0;
+        if (row < n && col < n) v = ((row == col ? emax : 0.0) - (double)h[e]) / den;
+        x[e] = (float)v;
     }
 }
 
 // One wave per tile: squared norm in the fixed order (per column over rows
 // with FMA, then the pairwise column tree), tile exponent, diagonal sum.
 template <int B>
-__global__ void __launch_bounds__(64) k_tile_stats(const float* __restrict__ T, int64_t nb, double* __restrict__ S,
-                                                   int8_t* __restrict__ texp, double* __restrict__ diag) {
+__global__ void __launch_bounds__(64) k_tile_stats(const float* __restrict__ T, const double* __restrict__ SH,
+                                                   int64_t nb, double* __restrict__ S, int8_t* __restrict__ texp,
+                                                   double* __restrict__ diag) {
     const int64_t tile = blockIdx.x;
     const int lane = threadIdx.x;
+    if (tile / nb != tile % nb && SH[tile] == 0.0) {  // the zeros written by k_sp2_init_x
+        if (lane == 0) {
+            S[tile] = 0.0;
+            texp[tile] = (int8_t)-128;
+        }
+        return;
+    }
     const float* t = T + tile * (int64_t)B * B;
     double s = 0.0, mx = 0.0, dv = 0.0;
     if (B == 128) {
@@ -367,16 +386,22 @@ hipError_t launch_gershgorin(const spamm_matrix* H, double* lo, double* hi, Sp2S
 }
 
 hipError_t launch_sp2_init(const spamm_matrix* H, spamm_matrix* X, double* part, Sp2State* st, hipStream_t s) {
-    const int64_t total = H->nb * H->nb * (int64_t)H->b * H->b;
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_sp2_init_x, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)H->tiles,
-                       (float*)X->tiles, H->n, H->b, H->nb, st);
     const unsigned tiles = (unsigned)(X->nb * X->nb);
+    const float* ht = (const float*)H->tiles;
+    float* xt = (float*)X->tiles;
     switch (X->b) {
-        case 32: hipLaunchKernelGGL(k_tile_stats<32>, dim3(tiles), dim3(64), 0, s, (const float*)X->tiles, X->nb, X->norms, X->texp, part); break;
-        case 64: hipLaunchKernelGGL(k_tile_stats<64>, dim3(tiles), dim3(64), 0, s, (const float*)X->tiles, X->nb, X->norms, X->texp, part); break;
-        case 128: hipLaunchKernelGGL(k_tile_stats<128>, dim3(tiles), dim3(64), 0, s, (const float*)X->tiles, X->nb, X->norms, X->texp, part); break;
+        case 32:
+            hipLaunchKernelGGL(k_sp2_init_x<32>, dim3(tiles), dim3(256), 0, s, ht, H->norms, xt, H->n, H->nb, st);
+            hipLaunchKernelGGL(k_tile_stats<32>, dim3(tiles), dim3(64), 0, s, xt, H->norms, X->nb, X->norms, X->texp, part);
+            break;
+        case 64:
+            hipLaunchKernelGGL(k_sp2_init_x<64>, dim3(tiles), dim3(256), 0, s, ht, H->norms, xt, H->n, H->nb, st);
+            hipLaunchKernelGGL(k_tile_stats<64>, dim3(tiles), dim3(64), 0, s, xt, H->norms, X->nb, X->norms, X->texp, part);
+            break;
+        case 128:
+            hipLaunchKernelGGL(k_sp2_init_x<128>, dim3(tiles), dim3(256), 0, s, ht, H->norms, xt, H->n, H->nb, st);
+            hipLaunchKernelGGL(k_tile_stats<128>, dim3(tiles), dim3(64), 0, s, xt, H->norms, X->nb, X->norms, X->texp, part);
+            break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = launch_upper_norms(X, s, nullptr);
