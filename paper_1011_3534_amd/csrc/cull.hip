@@ -34,7 +34,8 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
 template <bool ONE_BLOCK, int NT>
 __device__ void cull_pass(const ProdDesc* __restrict__ desc, int nprod, int l, const uint64_t* __restrict__ in,
                           uint64_t* __restrict__ out, DevCounters* __restrict__ ctr, int64_t out_cap, int want_bound,
-                          unsigned* wave_tot, unsigned long long* block_base, unsigned long long* s_count) {
+                          unsigned* wave_tot, unsigned long long* block_base, unsigned long long* s_count,
+                          unsigned long long* s_surv) {
     const int64_t P = ONE_BLOCK ? (int64_t)s_count[l] : (int64_t)ctr->front_count[l];
     const int64_t items = P + nprod;
     const int lane = threadIdx.x & (kWave - 1);
@@ -112,7 +113,12 @@ __device__ void cull_pass(const ProdDesc* __restrict__ desc, int nprod, int l, c
             const bool uniform = __all(!(have) || m == m0);
             if (uniform) {
                 const unsigned long long s = wave_sum_u64(mine);
-                if (lane == 0 && s) atomicAdd(&ctr->survivors[m0][c], s);
+                // one product per launch: the block adds its waves in LDS and
+                // its caller adds the block total once
+                if (lane == 0 && s) {
+                    if (s_surv) atomicAdd(s_surv, s);
+                    else atomicAdd(&ctr->survivors[m0][c], s);
+                }
             } else if (mine) {
                 atomicAdd(&ctr->survivors[m][c], mine);
             }
@@ -164,8 +170,13 @@ __global__ void __launch_bounds__(kCullThreads)
     if (active && *active == 0) return;
     __shared__ unsigned wave_tot[kCullThreads / kWave];
     __shared__ unsigned long long block_base;
+    __shared__ unsigned long long s_surv;
+    if (threadIdx.x == 0) s_surv = 0;
+    __syncthreads();
     cull_pass<false, kCullThreads>(desc, nprod, l, in, out, ctr, out_cap, want_bound, wave_tot, &block_base,
-                                   nullptr);
+                                   nullptr, nprod == 1 ? &s_surv : nullptr);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_surv) atomicAdd(&ctr->survivors[0][l - 1], s_surv);
 }
 
 // Tiers top .. stop + 1 in one block (small frontiers): the frontier of tier l
@@ -185,7 +196,7 @@ __global__ void __launch_bounds__(kTopThreads)
         const uint64_t* in = (l & 1) ? front1 : front0;
         uint64_t* out = ((l - 1) & 1) ? front1 : front0;
         cull_pass<true, kTopThreads>(desc, nprod, l, in, out, ctr, out_cap, want_bound, wave_tot, &block_base,
-                                     s_count);
+                                     s_count, nullptr);
         __syncthreads();  // this tier's stores are read by the next pass of the same block
     }
     if (threadIdx.x < kMaxLevels) ctr->front_count[threadIdx.x] = s_count[threadIdx.x];
@@ -196,8 +207,18 @@ __global__ void __launch_bounds__(kTopThreads)
 // are FP64 sums of their children's non-negative norms (rounding is
 // monotone), so every ancestor of a passing node passes too and the descent
 // from the root keeps exactly this set; only the depth-scaled schedule, whose
-// thresholds differ per tier, needs the descent.  Kept nodes are compacted
-// per block (wave ballots, one atomic per block) into the tier-s buffer.
+// thresholds differ per tier, needs the descent.  Each block takes a
+// contiguous range of nodes in two passes (count, then store), so the
+// frontier counter sees one atomic per block.  (This path runs without
+// statistics; the survivors of tier s are not counted.)
+__device__ inline bool enum_keep(const ProdDesc& d, const double* SA, const double* SB, int ms, int64_t idx,
+                                 uint32_t& I, uint32_t& J, uint32_t& K) {
+    I = (uint32_t)(idx / ((int64_t)ms * ms));
+    J = (uint32_t)((idx / ms) % ms);
+    K = (uint32_t)(idx % ms);
+    return !(SA[(int64_t)I * ms + K] * SB[(int64_t)K * ms + J] < d.tau2) && !(d.sym_upper && I > J);
+}
+
 __global__ void __launch_bounds__(kCullThreads)
     k_cull_enum(const ProdDesc* __restrict__ desc, int s, int ms, uint64_t* __restrict__ out,
                 DevCounters* __restrict__ ctr, int64_t out_cap, const int* __restrict__ active) {
@@ -208,36 +229,42 @@ __global__ void __launch_bounds__(kCullThreads)
     const double* SA = d.SA + d.lvl_off[s];
     const double* SB = d.SB + d.lvl_off[s];
     const int64_t total = (int64_t)ms * ms * ms;
+    const int64_t per = ((total + gridDim.x - 1) / gridDim.x + kCullThreads - 1) / kCullThreads * kCullThreads;
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < total ? lo + per : total;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    for (int64_t base = (int64_t)blockIdx.x * kCullThreads; base < total; base += (int64_t)gridDim.x * kCullThreads) {
+    uint32_t I, J, K;
+    // pass 1: this block's count
+    unsigned cnt = 0;
+    for (int64_t idx = lo + threadIdx.x; idx < hi; idx += kCullThreads) cnt += enum_keep(d, SA, SB, ms, idx, I, J, K);
+    for (int dd = kWave / 2; dd >= 1; dd /= 2) cnt += __shfl_xor(cnt, dd, kWave);
+    if (lane == 0) wave_tot[wid] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned tot = 0;
+        for (int w = 0; w < kCullThreads / kWave; ++w) tot += wave_tot[w];
+        block_base = tot ? atomicAdd(&ctr->front_count[s], (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    // pass 2: stores in node order within the block
+    unsigned long long run = block_base;
+    for (int64_t base = lo; base < hi; base += kCullThreads) {
         const int64_t idx = base + threadIdx.x;
-        uint32_t I = 0, J = 0, K = 0;
-        bool keep = false;
-        if (idx < total) {
-            I = (uint32_t)(idx / ((int64_t)ms * ms));
-            J = (uint32_t)((idx / ms) % ms);
-            K = (uint32_t)(idx % ms);
-            keep = !(SA[(int64_t)I * ms + K] * SB[(int64_t)K * ms + J] < d.tau2) && !(d.sym_upper && I > J);
-        }
+        const bool keep = idx < hi && enum_keep(d, SA, SB, ms, idx, I, J, K);
         const unsigned long long bal = __ballot(keep);
+        __syncthreads();  // wave_tot of the previous chunk has been read
         if (lane == 0) wave_tot[wid] = (unsigned)__popcll(bal);
         __syncthreads();
-        unsigned wave_off = 0, block_tot = 0;
+        unsigned wave_off = 0, chunk_tot = 0;
         for (int w = 0; w < kCullThreads / kWave; ++w) {
             if (w < wid) wave_off += wave_tot[w];
-            block_tot += wave_tot[w];
+            chunk_tot += wave_tot[w];
         }
-        if (threadIdx.x == 0) {
-            block_base = block_tot ? atomicAdd(&ctr->front_count[s], (unsigned long long)block_tot) : 0ull;
-            if (block_tot) atomicAdd(&ctr->survivors[0][s], (unsigned long long)block_tot);
-        }
-        __syncthreads();
         if (keep) {
-            const int64_t pos = (int64_t)block_base + wave_off + __popcll(bal & ((1ull << lane) - 1ull));
+            const int64_t pos = (int64_t)run + wave_off + __popcll(bal & ((1ull << lane) - 1ull));
             if (pos >= out_cap) atomicOr(&ctr->status, kDevCapacity);
             else out[pos] = node_key(0, I, J, K);
         }
-        __syncthreads();
+        run += chunk_tot;
     }
 }
 
@@ -303,7 +330,7 @@ hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t
         const int fs = plan.flat_start;
         const int64_t cells = (int64_t)plan.flat_m * plan.flat_m * plan.flat_m;
         int64_t blocks = (cells + kCullThreads - 1) / kCullThreads;
-        const int64_t maxb = (int64_t)num_cus() * 8;
+        const int64_t maxb = (int64_t)num_cus();  // one block per CU: few counter atomics
         blocks = blocks < 1 ? 1 : (blocks > maxb ? maxb : blocks);
         hipLaunchKernelGGL(k_cull_enum, dim3((unsigned)blocks), dim3(kCullThreads), 0, s, d_desc, fs, plan.flat_m,
                            (fs & 1) ? front1 : front0, ctr, plan.front_cap, active);
