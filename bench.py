@@ -449,21 +449,24 @@ def run_learned_tau(args):
         out[f"floor_{p}"] = sp.rel_err(sp.multiply(A, A, 0.0, p), E)
     del E
     log(f"floors: f32 {out['floor_f32']:.2e}, f16x3 {out['floor_f16x3']:.2e}")
-    for name, mdl in (("learned", model), ("bisection", None)):
+    # learned tau with FP32 leaves, plain bisection with FP32 leaves (the method
+    # without the network), and learned tau with FP16x3 leaves (low precision)
+    for name, mdl, prec in (("learned", model, "f32"), ("bisection", None, "f32"), ("learned_f16x3", model, "f16x3")):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
-            C, info = sp.tau_select(A, A, target, mdl, "f32", 0.05)
+            C, info = sp.tau_select(A, A, target, mdl, prec, 0.05)
         except sp.SpammError as exc:
             out[name] = {"error": str(exc)}
             log(f"{name}: {exc}")
             continue
         torch.cuda.synchronize()
         info["seconds"] = time.perf_counter() - t0
-        info["step_ms"] = _time(torch, lambda: sp.multiply(A, A, info["tau"], "f32", out=C), 5, 1)
+        info["step_ms"] = _time(torch, lambda: sp.multiply(A, A, info["tau"], prec, out=C), 5, 1)
+        info["leaf_precision"] = prec
         out[name] = info
         log(f"{name}: tau={info['tau']:.3e} err={info['rel_err']:.2e} evals={info['evaluations']} "
-            f"T={info['tasks']} {info['seconds']:.1f} s")
+            f"T={info['tasks']} {info['seconds']:.1f} s, product {info['step_ms']:.1f} ms")
         del C
     best = {}
     for i, _, _, _, lt, err in meta:
