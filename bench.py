@@ -108,6 +108,9 @@ def main():
     ap.add_argument("--presplit", action="store_true",
                     help="16-bit leaves: build the operand with its split hi/lo tiles (spamm_build_ex) "
                          "instead of splitting on the fly in the leaf kernel")
+    ap.add_argument("--build", default="view", choices=["view", "packed"],
+                    help="how a step builds the operand: view (spamm_build_view: leaf norms only, the leaf "
+                         "kernels read the dense array) or packed (spamm_build: copy into tile-major storage)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 256 MiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--workload", default="algebraic8192",
@@ -189,29 +192,46 @@ def main():
             continue
         tau, err, T = d["found"]
         C = d["handle"]
-        # a step builds the operand and multiplies (with --presplit the build
-        # also writes the split hi/lo tiles the 16-bit leaves then read)
+        # a step builds the operand and multiplies: as a view (norms only) or
+        # packed (with --presplit the packed build also writes the split
+        # hi/lo tiles the 16-bit leaves then read); both give the same bits
         bp = p if args.presplit else None
-        for _ in range(args.warmup):
-            sp.build(A_d, b, out=A, prec=bp)
-            sp.multiply(A, A, tau, p, out=C)
-        torch.cuda.synchronize()
-        ev0.record()
-        for _ in range(args.steps):
-            sp.build(A_d, b, out=A, prec=bp)
-            sp.multiply(A, A, tau, p, out=C)
-        ev1.record()
-        torch.cuda.synchronize()
-        step_ms = ev0.elapsed_time(ev1) / args.steps
-        phases = [sp.multiply_timed(A, A, tau, p, out=C)[1] for _ in range(args.steps)]
+        Av = sp.build(A_d, b, view=True)
+
+        def step(mode):
+            if mode == "view":
+                sp.build(A_d, b, out=Av, view=True)
+                sp.multiply(Av, Av, tau, p, out=C)
+            else:
+                sp.build(A_d, b, out=A, prec=bp)
+                sp.multiply(A, A, tau, p, out=C)
+
+        modes = {}
+        for mode in ("packed", "view"):
+            for _ in range(args.warmup):
+                step(mode)
+            torch.cuda.synchronize()
+            ev0.record()
+            for _ in range(args.steps):
+                step(mode)
+            ev1.record()
+            torch.cuda.synchronize()
+            modes[mode] = ev0.elapsed_time(ev1) / args.steps
+        mode = "packed" if args.presplit else args.build
+        step_ms = modes[mode]
+        other = "view" if mode == "packed" else "packed"
+        Ah = Av if mode == "view" else A
+        phases = [sp.multiply_timed(Ah, Ah, tau, p, out=C)[1] for _ in range(args.steps)]
         leaf_ms = float(np.mean([ph["ms_leaf"] for ph in phases]))
         cull_ms = float(np.mean([ph["ms_cull"] for ph in phases]))
         mult_ms = float(np.mean([ph["ms_total"] for ph in phases]))
         flops = 2.0 * b ** 3 * T
-        results[p] = {"tau": tau, "rel_err": err, "tasks": T, "step_ms": step_ms, "multiply_ms": mult_ms,
+        results[p] = {"tau": tau, "rel_err": err, "tasks": T, "step_ms": step_ms, "build": mode,
+                      f"step_ms_{other}_build": modes[other], "multiply_ms": mult_ms,
                       "leaf_ms": leaf_ms, "cull_ms": cull_ms, "leaf_tflops": flops / leaf_ms / 1e9,
                       "step_tflops": flops / step_ms / 1e9, "speedup_vs_dense_fp32": dense_ms / step_ms}
-        log(f"{p}: step {step_ms:.3f} ms (multiply {mult_ms:.3f}, leaf {leaf_ms:.3f}, cull {cull_ms:.3f}) "
+        log(f"{p}: step {step_ms:.3f} ms ({mode} build; {other} build {modes[other]:.3f}) "
+            f"(multiply {mult_ms:.3f}, leaf {leaf_ms:.3f}, cull {cull_ms:.3f}) "
             f"leaf {flops / leaf_ms / 1e9:.1f} TFLOP/s")
 
     if not results:
@@ -230,7 +250,7 @@ def main():
            "data": "synthetic",
            "config": {"workload": f"algebraic decay u/(|i-j|^2+1), u~U(0.5,1.5), n={n}, leaf {b}, FP32 storage, "
                                   f"C=A*A, tau for rel. err <= {args.target:g}",
-                      "n": n, "leaf": b, "tau": r["tau"], "leaf_precision": best},
+                      "n": n, "leaf": b, "tau": r["tau"], "leaf_precision": best, "operand_build": r["build"]},
            "rel_err": r["rel_err"], "tasks": r["tasks"], "leaf_tflops": round(achieved, 3),
            "spamm_step_ms": round(r["step_ms"], 4), "dense_fp32_gemm_ms": round(dense_ms, 4),
            "dense_fp32_rel_err": dense_err, "speedup_vs_dense_fp32": round(dense_ms / r["step_ms"], 3),
@@ -352,29 +372,43 @@ def run_batched64(args):
     Cs, sts = sp.multiply_batched(hs, hs, taus, "f32", stats=True, schedule=tune["schedule"])
     T = sum(s["tasks"] for s in sts)
     flops = 2.0 * b ** 3 * T
+    # views need every n to be a multiple of the leaf size
+    view = args.build == "view" and all(d.shape[0] % b == 0 for d in dense)
+    hv = sp.build_batched(dense, b, view=True) if view else hs
 
-    def step():
+    def build(mode):
+        if mode == "view":
+            sp.build_batched(dense, b, outs=hv, view=True)
+        else:
+            sp.build_batched(dense, b, outs=hs)
+
+    def step(mode):
         # the 64 operands built in one batched pass, then one batched product
-        sp.build_batched(dense, b, outs=hs)
-        sp.multiply_batched(hs, hs, taus, "f32", outs=Cs, schedule=tune["schedule"])
+        build(mode)
+        h = hv if mode == "view" else hs
+        sp.multiply_batched(h, h, taus, "f32", outs=Cs, schedule=tune["schedule"])
 
-    step_ms = _time(torch, step, args.steps, args.warmup)
-    build_ms = _time(torch, lambda: sp.build_batched(dense, b, outs=hs), args.steps, args.warmup)
+    mode = "view" if view else "packed"
+    step_ms = _time(torch, lambda: step(mode), args.steps, args.warmup)
+    step_packed_ms = _time(torch, lambda: step("packed"), args.steps, args.warmup)
+    build_ms = _time(torch, lambda: build(mode), args.steps, args.warmup)
+    build_packed_ms = _time(torch, lambda: build("packed"), args.steps, args.warmup)
     build_single_ms = _time(torch, lambda: [sp.build(d, b, out=h) for d, h in zip(dense, hs)], args.steps,
                             args.warmup)
-    mult_ms = _time(torch, lambda: sp.multiply_batched(hs, hs, taus, "f32", outs=Cs, schedule=tune["schedule"]),
+    mult_ms = _time(torch, lambda: sp.multiply_batched(hv, hv, taus, "f32", outs=Cs, schedule=tune["schedule"]),
                     args.steps, args.warmup)
     others = {}
     for other in ("static", "lpt", "list"):
         if other != tune["schedule"]:
             others[f"multiply_ms_{other}"] = _time(
-                torch, lambda: sp.multiply_batched(hs, hs, taus, "f32", outs=Cs, schedule=other), args.steps,
+                torch, lambda: sp.multiply_batched(hv, hv, taus, "f32", outs=Cs, schedule=other), args.steps,
                 args.warmup)
     dense_ms = _time(torch, lambda: [torch.matmul(d, d) for d in dense], 3, 1)
     dense_flops = sum(2.0 * d.shape[0] ** 3 for d in dense)
     print(json.dumps({"metric": METRIC, "workload": "batched64", "tune": tune, "tune_report": rep,
                       "tune_seconds": tune_s, "tasks": T, "leaf_flops": flops, "step_ms": step_ms,
-                      "build_ms": build_ms, "build_ms_one_call_per_matrix": build_single_ms,
+                      "operand_build": mode, "step_ms_packed_build": step_packed_ms, "build_ms": build_ms,
+                      "build_ms_packed": build_packed_ms, "build_ms_packed_one_call_per_matrix": build_single_ms,
                       "multiply_ms": mult_ms, **others,
                       "step_tflops": flops / step_ms / 1e9, "dense_fp32_gemm_ms": dense_ms,
                       "dense_flops": dense_flops, "speedup_vs_dense_fp32": dense_ms / step_ms,

@@ -161,6 +161,33 @@ spamm_status spamm_build_batched(int32_t count, const void* const* dev_a, const 
 spamm_status spamm_build_ex(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf,
                             spamm_leaf_prec prec, void* stream, spamm_matrix** out);
 
+/* spamm_build without the copy (section 2, Eq. 1: the tree's leaves are the
+ * b x b blocks of the matrix, wherever they are stored).  The handle keeps
+ * dev_a itself as its tile storage (tile (I, K) is rows I*b.. and columns
+ * K*b.. of dev_a) and owns only the norm pyramid, so the build reads dev_a
+ * once and writes no tiles.  dev_a must outlive the handle and must not be
+ * written while the handle is in use (rebuild after every change).
+ * A view is an operand of spamm_multiply*, spamm_tau_*, spamm_to_dense,
+ * spamm_diff_norms and spamm_norms; it cannot receive a product (EINVAL) and
+ * is not an SP2 Hamiltonian (EUNSUPPORTED).  Norms and products of a view are
+ * the same bits as those of a spamm_build handle of the same array.
+ *   out : in/out as for spamm_build; an existing handle must be a view of
+ *         the same n, leaf and dtype, and is re-pointed at dev_a.
+ * Errors: as spamm_build; EINVAL also for n not a multiple of leaf, dev_a or
+ * lda * element size not a multiple of 16 bytes, leaf * lda * element size
+ * >= 2^31 bytes, or an existing handle that is not a view (and spamm_build
+ * on an existing view). */
+spamm_status spamm_build_view(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf,
+                              void* stream, spamm_matrix** out);
+
+/* spamm_build_view of count matrices, one launch for all leaf norms and one
+ * per upper tier, as spamm_build_batched.  Arguments, errors and the
+ * no-change-on-error rule as spamm_build_batched, with the view conditions
+ * of spamm_build_view applying to every matrix. */
+spamm_status spamm_build_view_batched(int32_t count, const void* const* dev_a, const int64_t* n,
+                                      const int64_t* lda, spamm_dtype dt, int32_t leaf, void* stream,
+                                      spamm_matrix** out);
+
 /* ------------------------------------------------------------------ multiply */
 
 /* C ~= A B by Eq. (4) with absolute threshold tau.

@@ -125,6 +125,8 @@ def lib():
         "spamm_build": ([_VP, i64, i64, i32, i32, _VP, PP], i32),
         "spamm_build_ex": ([_VP, i64, i64, i32, i32, i32, _VP, PP], i32),
         "spamm_build_batched": ([i32, _VP, _VP, _VP, i32, i32, _VP, _VP], i32),
+        "spamm_build_view": ([_VP, i64, i64, i32, i32, _VP, PP], i32),
+        "spamm_build_view_batched": ([i32, _VP, _VP, _VP, i32, i32, _VP, _VP], i32),
         "spamm_multiply": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Stats)], i32),
         "spamm_multiply_ex": ([_VP, _VP, dbl, i32, i32, _VP, PP, ctypes.POINTER(Stats)], i32),
         "spamm_multiply_timed": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Timing)], i32),
@@ -220,8 +222,9 @@ def use_torch_allocator(enable: bool = True):
 class Matrix:
     """Owning wrapper of a spamm_matrix handle."""
 
-    def __init__(self, handle: ctypes.c_void_p):
+    def __init__(self, handle: ctypes.c_void_p, source=None):
         self._h = handle
+        self.source = source  # the tensor a view reads its tiles from (kept alive)
         n, b, dt, lv = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib().spamm_info(handle, ctypes.byref(n), ctypes.byref(b), ctypes.byref(dt), ctypes.byref(lv)))
         self.n, self.leaf, self.levels = n.value, b.value, lv.value
@@ -268,12 +271,15 @@ class Matrix:
         return np.sort(keys[:cnt.value])
 
 
-def build(a, leaf: int, out: Matrix | None = None, stream=None, prec: str | None = None) -> Matrix:
+def build(a, leaf: int, out: Matrix | None = None, stream=None, prec: str | None = None,
+          view: bool = False) -> Matrix:
     """Quadtree of a dense CUDA tensor (float32 or float64, row-major).
 
     With out given (same n, leaf, dtype) the handle is rebuilt in place.  With
     prec naming a 16-bit leaf precision the same pass also writes the split
-    hi/lo tiles those products read (spamm_build_ex)."""
+    hi/lo tiles those products read (spamm_build_ex).  With view=True the
+    handle reads its tiles from `a` itself (spamm_build_view: norms only, no
+    copy); it keeps a reference to `a`, which must not change while in use."""
     import torch
     if not (a.is_cuda and a.dim() == 2 and a.shape[0] == a.shape[1]):
         raise ValueError("build expects a square CUDA tensor")
@@ -283,6 +289,15 @@ def build(a, leaf: int, out: Matrix | None = None, stream=None, prec: str | None
         raise ValueError("build expects unit column stride")
     h = ctypes.c_void_p(out.handle.value if out is not None else None)
     dt = 0 if a.dtype == torch.float64 else 1
+    if view:
+        if prec is not None:
+            raise ValueError("a view has no split tiles (prec applies to packed builds)")
+        _check(lib().spamm_build_view(ctypes.c_void_p(a.data_ptr()), a.shape[0], a.stride(0), dt, leaf,
+                                      _stream(stream), ctypes.byref(h)))
+        if out is not None:
+            out.source = a
+            return out
+        return Matrix(h, source=a)
     if prec is None:
         _check(lib().spamm_build(ctypes.c_void_p(a.data_ptr()), a.shape[0], a.stride(0), dt, leaf,
                                  _stream(stream), ctypes.byref(h)))
@@ -292,9 +307,10 @@ def build(a, leaf: int, out: Matrix | None = None, stream=None, prec: str | None
     return out if out is not None else Matrix(h)
 
 
-def build_batched(tensors, leaf: int, outs=None, stream=None) -> list:
+def build_batched(tensors, leaf: int, outs=None, stream=None, view: bool = False) -> list:
     """Quadtrees of several dense CUDA tensors of one dtype in one pass
-    (spamm_build_batched).  outs: None or a list of handles/None to rebuild."""
+    (spamm_build_batched; view=True: spamm_build_view_batched, see build).
+    outs: None or a list of handles/None to rebuild."""
     import torch
     count = len(tensors)
     dts = {a.dtype for a in tensors}
@@ -309,8 +325,13 @@ def build_batched(tensors, leaf: int, outs=None, stream=None) -> list:
     LD = (ctypes.c_int64 * count)(*[a.stride(0) for a in tensors])
     outs = outs or [None] * count
     PO = (ctypes.c_void_p * count)(*[(o.handle.value if o is not None else None) for o in outs])
-    _check(lib().spamm_build_batched(count, PA, N, LD, dt, leaf, _stream(stream), PO))
-    return [o if o is not None else Matrix(ctypes.c_void_p(PO[m])) for m, o in enumerate(outs)]
+    fn = lib().spamm_build_view_batched if view else lib().spamm_build_batched
+    _check(fn(count, PA, N, LD, dt, leaf, _stream(stream), PO))
+    res = [o if o is not None else Matrix(ctypes.c_void_p(PO[m])) for m, o in enumerate(outs)]
+    if view:
+        for m, o in enumerate(res):
+            o.source = tensors[m]
+    return res
 
 
 TAU_FLAT, TAU_DEPTH_SCALED = 0, 1

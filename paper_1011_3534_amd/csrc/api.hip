@@ -115,18 +115,18 @@ void release(spamm_matrix* M) {
     if (!M) return;
     if (M->last_stream) (void)hipStreamSynchronize(M->last_stream);
     release_scratch(M);
-    dev_free(M, M->tiles, M->last_stream);
+    if (!M->view) dev_free(M, M->tiles, M->last_stream);
     dev_free(M, M->norms, M->last_stream);
     dev_free(M, M->texp, M->last_stream);
     dev_free(M, M->split, M->last_stream);
     delete M;
 }
 
-// Device storage of a handle: tiles, norm pyramid (+ tier tables + status
-// word at its tail) and per-tile exponents.
+// Device storage of a handle: tiles (not for a view), norm pyramid (+ tier
+// tables + status word at its tail) and per-tile exponents.
 spamm_status alloc_storage(spamm_matrix* M, hipStream_t s) {
     const size_t tiles = (size_t)(M->nb * M->nb) * M->b * M->b * M->elem;
-    M->tiles = dev_alloc(M, tiles, s);
+    if (!M->view) M->tiles = dev_alloc(M, tiles, s);
     const size_t nbytes = (size_t)M->norms_total * 8 + kMaxLevels * 8 + kMaxLevels * 4 + 64;
     M->norms = (double*)dev_alloc(M, nbytes, s);
     M->texp = (int8_t*)dev_alloc(M, (size_t)(M->nb * M->nb), s);
@@ -185,6 +185,8 @@ ProdDesc make_desc(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C
     d.eA = A->texp;
     d.eB = B->texp;
     d.eC = C->texp;
+    d.ga = tile_geo(A);
+    d.gb = tile_geo(B);
     d.A16 = A->split;  // read only when current (LeafPlan::presplit)
     d.B16 = B->split;
     d.mask = C->ps->mask;
@@ -342,10 +344,22 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
 
 using namespace spamm;
 
-extern "C" {
+namespace {
 
-spamm_status spamm_build_ex(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf,
-                            spamm_leaf_prec prec, void* stream, spamm_matrix** out) {
+// A view reads its tiles from the caller's array with 32-bit buffer offsets,
+// 16-byte loads and no padding.
+spamm_status check_view(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf) {
+    const int64_t elem = dt == SPAMM_F64 ? 8 : 4;
+    if (n % leaf != 0) return set_error(SPAMM_EINVAL, "a view needs n to be a multiple of the leaf size");
+    if ((uintptr_t)dev_a % 16 != 0 || (lda * elem) % 16 != 0)
+        return set_error(SPAMM_EINVAL, "a view needs a 16-byte aligned array and row pitch");
+    if ((int64_t)leaf * lda * elem > (int64_t)INT32_MAX)
+        return set_error(SPAMM_EINVAL, "a view needs leaf * lda * element size < 2^31 bytes");
+    return SPAMM_OK;
+}
+
+spamm_status build_single(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf,
+                          spamm_leaf_prec prec, bool view, void* stream, spamm_matrix** out) {
     if (!out) return set_error(SPAMM_EINVAL, "out is null");
     if (!dev_a) return set_error(SPAMM_EINVAL, "dev_a is null");
     if (n < 1 || lda < n) return set_error(SPAMM_EINVAL, "need n >= 1 and lda >= n");
@@ -353,22 +367,39 @@ spamm_status spamm_build_ex(const void* dev_a, int64_t n, int64_t lda, spamm_dty
     if (!leaf_ok(leaf)) return set_error(SPAMM_EINVAL, "leaf must be 32, 64 or 128");
     if ((int)prec < 0 || (int)prec > 5) return set_error(SPAMM_EINVAL, "unknown leaf precision");
     if (ceil_div(n, leaf) > kMaxNb) return set_error(SPAMM_EINVAL, "n / leaf exceeds 2^19 leaves");
-    const int kind = split_kind(prec);
+    if (view) {
+        spamm_status v = check_view(dev_a, n, lda, dt, leaf);
+        if (v != SPAMM_OK) return v;
+    }
+    const int kind = view ? -1 : split_kind(prec);
     if (kind >= 0 && dt != SPAMM_F32)
         return set_error(SPAMM_EUNSUPPORTED, "16-bit leaf precisions take FP32 tiles");
     hipStream_t s = (hipStream_t)stream;
     spamm_matrix* M = *out;
     const bool fresh = M == nullptr;
     spamm_status st = SPAMM_OK;
+    if (!fresh) {
+        if (M->n != n || M->b != leaf || M->dt != dt)
+            return set_error(SPAMM_EINVAL, "existing handle differs in n, leaf or dtype");
+        if (M->view != view)
+            return set_error(SPAMM_EINVAL, view ? "existing handle owns packed tiles (not a view)"
+                                                : "existing handle is a view (spamm_build_view)");
+    }
     if (fresh) {
         M = new_handle(n, leaf, dt);
+        if (view) {
+            M->view = true;
+            M->tiles = const_cast<void*>(dev_a);
+            M->ld = lda;
+        }
         st = alloc_storage(M, s);
         if (st != SPAMM_OK) {
             release(M);
             return st;
         }
-    } else if (M->n != n || M->b != leaf || M->dt != dt) {
-        return set_error(SPAMM_EINVAL, "existing handle differs in n, leaf or dtype");
+    } else if (view) {
+        M->tiles = const_cast<void*>(dev_a);
+        M->ld = lda;
     }
     if (kind >= 0 && (st = alloc_split(M, s)) != SPAMM_OK) {
         if (fresh) release(M);
@@ -392,8 +423,8 @@ spamm_status spamm_build_ex(const void* dev_a, int64_t n, int64_t lda, spamm_dty
     return SPAMM_OK;
 }
 
-spamm_status spamm_build_batched(int32_t count, const void* const* dev_a, const int64_t* n, const int64_t* lda,
-                                 spamm_dtype dt, int32_t leaf, void* stream, spamm_matrix** out) {
+spamm_status build_batched(int32_t count, const void* const* dev_a, const int64_t* n, const int64_t* lda,
+                           spamm_dtype dt, int32_t leaf, bool view, void* stream, spamm_matrix** out) {
     if (count < 1 || count > kMaxBatch) return set_error(SPAMM_EINVAL, "count outside [1, 128]");
     if (!dev_a || !n || !lda || !out) return set_error(SPAMM_EINVAL, "null argument");
     if (dt != SPAMM_F32 && dt != SPAMM_F64) return set_error(SPAMM_EINVAL, "unknown dtype");
@@ -402,8 +433,15 @@ spamm_status spamm_build_batched(int32_t count, const void* const* dev_a, const 
         if (!dev_a[m]) return set_error(SPAMM_EINVAL, "dev_a[m] is null");
         if (n[m] < 1 || lda[m] < n[m]) return set_error(SPAMM_EINVAL, "need n >= 1 and lda >= n");
         if (ceil_div(n[m], leaf) > kMaxNb) return set_error(SPAMM_EINVAL, "n / leaf exceeds 2^19 leaves");
+        if (view) {
+            spamm_status v = check_view(dev_a[m], n[m], lda[m], dt, leaf);
+            if (v != SPAMM_OK) return v;
+        }
         if (out[m] && (out[m]->n != n[m] || out[m]->b != leaf || out[m]->dt != dt))
             return set_error(SPAMM_EINVAL, "existing handle differs in n, leaf or dtype");
+        if (out[m] && out[m]->view != view)
+            return set_error(SPAMM_EINVAL, view ? "existing handle owns packed tiles (not a view)"
+                                                : "existing handle is a view (spamm_build_view)");
         for (int q = 0; q < m; ++q)
             if (out[m] && out[m] == out[q]) return set_error(SPAMM_EINVAL, "out handles must be distinct");
     }
@@ -420,6 +458,11 @@ spamm_status spamm_build_batched(int32_t count, const void* const* dev_a, const 
         if (!M[m]) {
             M[m] = new_handle(n[m], leaf, dt);
             fresh[m] = true;
+            if (view) {
+                M[m]->view = true;
+                M[m]->tiles = const_cast<void*>(dev_a[m]);
+                M[m]->ld = lda[m];
+            }
             st = alloc_storage(M[m], s);
         }
     }
@@ -458,8 +501,41 @@ spamm_status spamm_build_batched(int32_t count, const void* const* dev_a, const 
         release_fresh();
         return st;
     }
-    for (int m = 0; m < count; ++m) out[m] = M[m];
+    // a rebuilt view reads the new array
+    for (int m = 0; m < count; ++m) {
+        if (view) {
+            M[m]->tiles = const_cast<void*>(dev_a[m]);
+            M[m]->ld = lda[m];
+        }
+        out[m] = M[m];
+    }
     return SPAMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+spamm_status spamm_build_ex(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf,
+                            spamm_leaf_prec prec, void* stream, spamm_matrix** out) {
+    return build_single(dev_a, n, lda, dt, leaf, prec, false, stream, out);
+}
+
+spamm_status spamm_build_view(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf,
+                              void* stream, spamm_matrix** out) {
+    return build_single(dev_a, n, lda, dt, leaf, dt == SPAMM_F64 ? SPAMM_LEAF_F64 : SPAMM_LEAF_F32, true, stream,
+                        out);
+}
+
+spamm_status spamm_build_batched(int32_t count, const void* const* dev_a, const int64_t* n, const int64_t* lda,
+                                 spamm_dtype dt, int32_t leaf, void* stream, spamm_matrix** out) {
+    return build_batched(count, dev_a, n, lda, dt, leaf, false, stream, out);
+}
+
+spamm_status spamm_build_view_batched(int32_t count, const void* const* dev_a, const int64_t* n,
+                                      const int64_t* lda, spamm_dtype dt, int32_t leaf, void* stream,
+                                      spamm_matrix** out) {
+    return build_batched(count, dev_a, n, lda, dt, leaf, true, stream, out);
 }
 
 spamm_status spamm_build(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf, void* stream,
@@ -481,6 +557,7 @@ spamm_status spamm_multiply_ex(const spamm_matrix* A, const spamm_matrix* B, dou
     spamm_matrix* Cm = *C;
     if (Cm) {
         if (Cm == A || Cm == B) return set_error(SPAMM_EINVAL, "C may not alias an operand");
+        if (Cm->view) return set_error(SPAMM_EINVAL, "a view cannot receive a product");
         if (Cm->n != A->n || Cm->b != A->b || Cm->dt != cdt)
             return set_error(SPAMM_EINVAL, "existing C differs in n, leaf or result type");
     }
@@ -653,6 +730,7 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
         if (A[m]->b != b) return set_error(SPAMM_EINVAL, "products of one batch share the leaf size");
         if (A[m]->dt != A[0]->dt) return set_error(SPAMM_EINVAL, "products of one batch share the operand type");
         if (C[m]) {
+            if (C[m]->view) return set_error(SPAMM_EINVAL, "a view cannot receive a product");
             if (C[m]->n != A[m]->n || C[m]->b != b || C[m]->dt != cdt)
                 return set_error(SPAMM_EINVAL, "existing C differs in n, leaf or result type");
             for (int q = 0; q < count; ++q)
@@ -813,6 +891,7 @@ spamm_status spamm_sp2_ex(const spamm_matrix* H, int64_t n_occ, double tau, int3
     if (prec == SPAMM_LEAF_F64 || H->dt != SPAMM_F32)
         return set_error(SPAMM_EUNSUPPORTED, "SP2 runs on FP32 tiles with FP32 or split 16-bit leaves");
     if (H->nb * H->nb > (int64_t)UINT32_MAX) return set_error(SPAMM_EUNSUPPORTED, "SP2 needs nb^2 < 2^32 tiles");
+    if (H->view) return set_error(SPAMM_EUNSUPPORTED, "SP2 takes a packed H (spamm_build), not a view");
     hipStream_t s = (hipStream_t)stream;
     (void)num_cus();  // device query outside the capture
     spamm_matrix* X[2] = {nullptr, nullptr};

@@ -98,11 +98,11 @@ struct Stage16 {
     uint32_t b[G::NARR][UB][8];
 };
 
-// ra: A tile from the chunk's first column (row stride B); rb: B tile from
-// the chunk's first row (row stride B).
+// ra: A tile from the chunk's first column (rows lda apart); rb: B tile
+// from the chunk's first row (rows ldb apart).
 template <int B, int P, typename TA>
 __device__ inline void stage_load(Stage<B, P, TA>& st, __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rb,
-                                  int tid) {
+                                  int tid, int lda, int ldb) {
     using S = Stage<B, P, TA>;
     constexpr int KC = S::KC, VA = S::VA;
 #pragma unroll
@@ -110,7 +110,7 @@ __device__ inline void stage_load(Stage<B, P, TA>& st, __amdgpu_buffer_rsrc_t ra
         const int unit = tid + u * 256;
         if (S::PARTIAL && unit >= S::NU) break;
         const int r = unit / (KC / VA), k = (unit % (KC / VA)) * VA;
-        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(ra, (r * B + k) * (int)sizeof(TA), 0, 0);
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(ra, (r * lda + k) * (int)sizeof(TA), 0, 0);
         const TA* e = reinterpret_cast<const TA*>(&v);
 #pragma unroll
         for (int j = 0; j < VA; ++j) st.a[u][j] = e[j];
@@ -120,7 +120,7 @@ __device__ inline void stage_load(Stage<B, P, TA>& st, __amdgpu_buffer_rsrc_t ra
         const int unit = tid + u * 256;
         if (S::PARTIAL && unit >= S::NU) break;
         const int k = unit / (B / VA), c = (unit % (B / VA)) * VA;
-        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rb, (k * B + c) * (int)sizeof(TA), 0, 0);
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rb, (k * ldb + c) * (int)sizeof(TA), 0, 0);
         const TA* e = reinterpret_cast<const TA*>(&v);
 #pragma unroll
         for (int j = 0; j < VA; ++j) st.b[u][j] = e[j];
@@ -237,7 +237,7 @@ struct Stage16c {
 
 template <int B, int P>
 __device__ inline void stage16c_load(Stage16c<B, P>& st, __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rb,
-                                     int tid) {
+                                     int tid, int lda, int ldb) {
     using S = Stage16c<B, P>;
     constexpr int KC = S::KC;
 #pragma unroll
@@ -246,7 +246,7 @@ __device__ inline void stage16c_load(Stage16c<B, P>& st, __amdgpu_buffer_rsrc_t 
         if (S::PARTIAL && unit >= S::NU) break;
         const int r = unit / (KC / 8), k = (unit % (KC / 8)) * 8;
         // one lane offset per unit; the constant parts go in the scalar offset
-        const int vo = (r * B + k) * 4;
+        const int vo = (r * lda + k) * 4;
         const f32x4 v0 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, vo, 0, 0));
         const f32x4 v1 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, vo, 16, 0));
 #pragma unroll
@@ -262,7 +262,7 @@ __device__ inline void stage16c_load(Stage16c<B, P>& st, __amdgpu_buffer_rsrc_t 
         const int c = unit % B, k = (unit / B) * 8;
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-            st.b[u][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, (k * B + c) * 4, j * B * 4, 0));
+            st.b[u][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, (k * ldb + c) * 4, j * ldb * 4, 0));
     }
 }
 
@@ -400,6 +400,10 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
     const int64_t lo16 = (int64_t)nb * nb * B * B;  // hi tiles -> lo tiles
     constexpr int64_t TS = (int64_t)B * B;
+    // operand tiles: rows lda (ldb) apart; ext_a (ext_b) elements from a
+    // tile's first element to one past its last
+    const int lda = (int)d.ga.ld, ldb = (int)d.gb.ld;
+    const int64_t ext_a = (int64_t)(B - 1) * lda + B, ext_b = (int64_t)(B - 1) * ldb + B;
 
     Acc acc[R][R], part[R][R];
 #pragma unroll
@@ -513,13 +517,15 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             const int tt = live ? t : T - 1;
             const int k = __builtin_amdgcn_readfirstlane(kl->k[tt / NCH]);
             const int ch = tt % NCH;
-            const int64_t ta = ((int64_t)I * nb + k) * TS, tb = ((int64_t)k * nb + J) * TS;
             if constexpr (is16(P) && !PRESPLIT) {
-                const uint32_t na = live ? (uint32_t)((TS - ch * KC) * 4) : 0u;
-                const uint32_t nbb = live ? (uint32_t)((TS - ch * KC * B) * 4) : 0u;
+                const int64_t ta = d.ga.tile(I, k), tb = d.gb.tile(k, J);
+                const uint32_t na = live ? (uint32_t)((ext_a - ch * KC) * 4) : 0u;
+                const uint32_t nbb = live ? (uint32_t)((ext_b - ch * KC * ldb) * 4) : 0u;
                 stage16c_load<B, P>(st, rsrc((const float*)d.A + ta + ch * KC, na),
-                                    rsrc((const float*)d.B + tb + (int64_t)ch * KC * B, nbb), tid);
+                                    rsrc((const float*)d.B + tb + (int64_t)ch * KC * ldb, nbb), tid, lda, ldb);
             } else if constexpr (is16(P)) {
+                // split tiles are always packed
+                const int64_t ta = ((int64_t)I * nb + k) * TS, tb = ((int64_t)k * nb + J) * TS;
                 const uint32_t na = live ? (uint32_t)((TS - ch * KC) * 2) : 0u;
                 const uint32_t nbb = live ? (uint32_t)((TS - ch * KC * B) * 2) : 0u;
                 __amdgpu_buffer_rsrc_t ra[2], rb[2];
@@ -530,10 +536,11 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
                 }
                 stage16_load<B, P>(st, ra, rb, tid);
             } else {
-                const uint32_t na = live ? (uint32_t)((TS - ch * KC) * sizeof(TA)) : 0u;
-                const uint32_t nbb = live ? (uint32_t)((TS - ch * KC * B) * sizeof(TA)) : 0u;
+                const int64_t ta = d.ga.tile(I, k), tb = d.gb.tile(k, J);
+                const uint32_t na = live ? (uint32_t)((ext_a - ch * KC) * sizeof(TA)) : 0u;
+                const uint32_t nbb = live ? (uint32_t)((ext_b - ch * KC * ldb) * sizeof(TA)) : 0u;
                 stage_load<B, P, TA>(st, rsrc((const TA*)d.A + ta + ch * KC, na),
-                                     rsrc((const TA*)d.B + tb + (int64_t)ch * KC * B, nbb), tid);
+                                     rsrc((const TA*)d.B + tb + (int64_t)ch * KC * ldb, nbb), tid, lda, ldb);
             }
         };
         // (step t's FP16 scales apply when splitting on the fly; a store past

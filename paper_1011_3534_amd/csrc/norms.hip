@@ -62,7 +62,8 @@ __device__ __forceinline__ void pack_wave(const T* __restrict__ a, int64_t n, in
 #pragma unroll
     for (int j = 0; j < V; ++j) acc[j] = 0.0;
 
-    T* tdst = tiles + ((I * nb + (live ? K : 0)) * B) * (int64_t)B + cin;
+    // (a view keeps the caller's array as its tiles: tiles == NULL, norms only)
+    T* tdst = tiles ? tiles + ((I * nb + (live ? K : 0)) * B) * (int64_t)B + cin : nullptr;
 #pragma unroll 8
     for (int r = 0; r < B; ++r) {
         const int64_t row = I * B + r;
@@ -87,7 +88,7 @@ __device__ __forceinline__ void pack_wave(const T* __restrict__ a, int64_t n, in
             acc[j] = __fma_rn(xd, xd, acc[j]);
             mx = fmax(mx, fabs(xd));
         }
-        if (live) {
+        if (live && tiles) {
             VT v;
             T* pv = reinterpret_cast<T*>(&v);
 #pragma unroll
@@ -233,13 +234,11 @@ __global__ void __launch_bounds__(1024) k_norm_small_tiers(double* __restrict__ 
 }
 
 template <typename T>
-__global__ void k_to_dense(const T* __restrict__ tiles, int64_t n, int b, int64_t nb, T* __restrict__ out,
-                           int64_t ldo) {
+__global__ void k_to_dense(const T* __restrict__ tiles, TileGeo g, int64_t n, T* __restrict__ out, int64_t ldo) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = t / n, col = t % n;
     if (row >= n) return;
-    const int64_t I = row / b, K = col / b;
-    out[row * ldo + col] = tiles[((I * nb + K) * b + (row % b)) * b + (col % b)];
+    out[row * ldo + col] = tiles[g.at(row, col)];
 }
 
 template <typename TX, typename TY>
@@ -275,17 +274,17 @@ __global__ void __launch_bounds__(256) k_diff_norms(const TX* __restrict__ x, co
     }
 }
 
-// ||X - Y||^2 and ||Y||^2 for handles of equal n but different leaf sizes:
-// element (row, col) is looked up in each handle's own tile layout.
+// ||X - Y||^2 and ||Y||^2 for handles of equal n but different layouts
+// (leaf sizes, views): element (row, col) is looked up in each handle's own.
 template <typename TX, typename TY>
-__global__ void __launch_bounds__(256) k_diff_norms_any(const TX* __restrict__ x, int bx, int64_t nbx,
-                                                        const TY* __restrict__ y, int by, int64_t nby, int64_t n,
+__global__ void __launch_bounds__(256) k_diff_norms_any(const TX* __restrict__ x, TileGeo gx,
+                                                        const TY* __restrict__ y, TileGeo gy, int64_t n,
                                                         double* __restrict__ out) {
     double d2 = 0.0, r2 = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n * n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t row = i / n, col = i % n;
-        const double xv = (double)x[(((row / bx) * nbx + col / bx) * bx + row % bx) * bx + col % bx];
-        const double yv = (double)y[(((row / by) * nby + col / by) * by + row % by) * by + col % by];
+        const double xv = (double)x[gx.at(row, col)];
+        const double yv = (double)y[gy.at(row, col)];
         const double dv = xv - yv;
         d2 = __fma_rn(dv, dv, d2);
         r2 = __fma_rn(yv, yv, r2);
@@ -322,7 +321,7 @@ hipError_t pack_t(const void* a, int64_t n, int64_t lda, spamm_matrix* M, unsign
     const int64_t blocks = (waves + 3) / 4;
     const int vec = ((uintptr_t)a % 16 == 0) && (lda % V == 0) && (n % V == 0);
     hipLaunchKernelGGL((k_pack_norm<T, B>), dim3((unsigned)blocks), dim3(256), 0, s, (const T*)a, n, lda, nb,
-                       nstrips, (T*)M->tiles, M->norms, M->texp, status, vec);
+                       nstrips, M->view ? nullptr : (T*)M->tiles, M->norms, M->texp, status, vec);
     return hipGetLastError();
 }
 
@@ -448,7 +447,7 @@ PackDesc pack_desc(const void* a, int64_t n, int64_t lda, spamm_matrix* M, unsig
     d.nb = M->nb;
     d.nstrips = (M->nb * M->b + kWave * V - 1) / (kWave * V);
     d.wave_base = wave_base;
-    d.tiles = M->tiles;
+    d.tiles = M->view ? nullptr : M->tiles;
     d.S0 = M->norms;
     d.texp = M->texp;
     d.status = status;
@@ -460,24 +459,24 @@ hipError_t launch_to_dense(const spamm_matrix* M, void* out, int64_t ldo, hipStr
     const int64_t cnt = M->n * M->n;
     const unsigned blocks = (unsigned)((cnt + 255) / 256);
     if (M->dt == SPAMM_F32)
-        hipLaunchKernelGGL(k_to_dense<float>, dim3(blocks), dim3(256), 0, s, (const float*)M->tiles, M->n, M->b,
-                           M->nb, (float*)out, ldo);
+        hipLaunchKernelGGL(k_to_dense<float>, dim3(blocks), dim3(256), 0, s, (const float*)M->tiles, tile_geo(M),
+                           M->n, (float*)out, ldo);
     else
-        hipLaunchKernelGGL(k_to_dense<double>, dim3(blocks), dim3(256), 0, s, (const double*)M->tiles, M->n,
-                           M->b, M->nb, (double*)out, ldo);
+        hipLaunchKernelGGL(k_to_dense<double>, dim3(blocks), dim3(256), 0, s, (const double*)M->tiles,
+                           tile_geo(M), M->n, (double*)out, ldo);
     return hipGetLastError();
 }
 
-// Padding is zero in both handles, so the padded tile storage can be
-// compared element by element.
+// Padding is zero in both packed handles, so their padded tile storage can
+// be compared element by element.
 hipError_t launch_diff_norms(const spamm_matrix* X, const spamm_matrix* Y, double* d_out, hipStream_t s) {
     const int64_t count = X->nb * X->nb * (int64_t)X->b * X->b;
     const unsigned blocks = 1024;
     const bool xf = X->dt == SPAMM_F32, yf = Y->dt == SPAMM_F32;
-    if (X->b != Y->b) {
-#define SPAMM_DIFF_ANY(TX, TY)                                                                                     \
-    hipLaunchKernelGGL((k_diff_norms_any<TX, TY>), dim3(blocks), dim3(256), 0, s, (const TX*)X->tiles, X->b, X->nb, \
-                       (const TY*)Y->tiles, Y->b, Y->nb, X->n, d_out)
+    if (X->b != Y->b || X->view || Y->view) {
+#define SPAMM_DIFF_ANY(TX, TY)                                                                                   \
+    hipLaunchKernelGGL((k_diff_norms_any<TX, TY>), dim3(blocks), dim3(256), 0, s, (const TX*)X->tiles, tile_geo(X), \
+                       (const TY*)Y->tiles, tile_geo(Y), X->n, d_out)
         if (xf && yf) SPAMM_DIFF_ANY(float, float);
         else if (xf) SPAMM_DIFF_ANY(float, double);
         else if (yf) SPAMM_DIFF_ANY(double, float);

@@ -73,6 +73,19 @@ __device__ inline void split16x2(spamm_f2 x, uint32_t& hi, uint32_t& lo) {
     }
 }
 
+// Where the elements of a handle's tiles live: element (r, c) of tile (I, K)
+// is at I*si + K*sk + r*ld + c.  Packed tiles (the library's own storage)
+// are b*b apart in (I, K) row-major order with rows b apart; a view reads
+// the caller's row-major array, whose rows are ld apart.
+struct TileGeo {
+    int64_t si, sk, ld;
+    int32_t b, pad_;
+    __host__ __device__ int64_t tile(int64_t I, int64_t K) const { return I * si + K * sk; }
+    __host__ __device__ int64_t at(int64_t row, int64_t col) const {
+        return tile(row / b, col / b) + (row % b) * ld + col % b;
+    }
+};
+
 // Per-product descriptor read by the cull and leaf kernels.  Operand and
 // result pyramids share the same tier shapes (equal n and leaf).
 struct ProdDesc {
@@ -100,6 +113,7 @@ struct ProdDesc {
     int32_t depth_tau;        // 1: a node at depth k below the root is tested against tau / 8^k
     int32_t sym_upper;        // 1: symmetric squaring: only tiles I <= J are formed, C_JI = C_IJ^T
     int32_t pad_;
+    TileGeo ga, gb;           // layouts of the A and B tiles (C tiles are packed)
 };
 
 // Device-side counters of one product launch sequence.
@@ -132,7 +146,9 @@ struct spamm_matrix {
     int32_t L = 0;
     spamm_dtype dt = SPAMM_F32;
     size_t elem = 4;
-    void* tiles = nullptr;
+    void* tiles = nullptr;       // packed tiles, or the borrowed array of a view
+    bool view = false;           // tiles borrow the caller's row-major array (not owned)
+    int64_t ld = 0;              // a view's row stride (elements)
     double* norms = nullptr;
     int8_t* texp = nullptr;
     uint16_t* split = nullptr;   // split 16-bit tiles (hi, then lo), made on demand
@@ -167,6 +183,23 @@ void* dev_alloc(spamm_matrix* owner, size_t bytes, hipStream_t s);
 void dev_free(spamm_matrix* owner, void* p, hipStream_t s);
 int num_cus();
 
+// Tile layout of a handle (see TileGeo).
+inline TileGeo tile_geo(const spamm_matrix* M) {
+    TileGeo g;
+    g.b = M->b;
+    g.pad_ = 0;
+    if (M->view) {
+        g.si = (int64_t)M->b * M->ld;
+        g.sk = M->b;
+        g.ld = M->ld;
+    } else {
+        g.si = M->nb * M->b * (int64_t)M->b;
+        g.sk = (int64_t)M->b * M->b;
+        g.ld = M->b;
+    }
+    return g;
+}
+
 // launchers (norms.hip) ---------------------------------------------------------
 // split_kind >= 0 (FP32 input, M->split allocated): the same pass also writes
 // the split 16-bit tiles of that kind.
@@ -179,7 +212,7 @@ struct PackDesc {
     const void* a;            // dense row-major input
     int64_t n, lda, nb, nstrips;
     int64_t wave_base;        // first global wave of this matrix
-    void* tiles;
+    void* tiles;              // NULL: norms only (a view)
     double* S0;               // leaf tier of the pyramid
     int8_t* texp;
     unsigned* status;

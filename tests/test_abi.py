@@ -39,6 +39,30 @@ def test_build_rejects_bad_arguments():
     assert b"leaf" in L.spamm_last_error() or b"null" in L.spamm_last_error()
 
 
+def test_view_build_rejects_bad_layouts():
+    # a view reads the caller's array in place: no padding, 16-byte rows,
+    # 32-bit buffer offsets (checked before any device work)
+    L = _lib_or_skip()
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.spamm_build_view(fake, 100, 128, 1, 64, None, ctypes.byref(h)) == 1          # n % leaf != 0
+    assert b"multiple of the leaf" in L.spamm_last_error()
+    assert L.spamm_build_view(ctypes.c_void_p(0x1004), 128, 128, 1, 64, None, ctypes.byref(h)) == 1  # base
+    assert L.spamm_build_view(fake, 128, 130, 1, 64, None, ctypes.byref(h)) == 1          # row pitch 520 B
+    assert b"16-byte" in L.spamm_last_error()
+    assert L.spamm_build_view(fake, 128, 1 << 23, 1, 64, None, ctypes.byref(h)) == 1      # 64 rows = 2 GiB
+    assert b"2^31" in L.spamm_last_error()
+    assert L.spamm_build_view(None, 128, 128, 1, 64, None, ctypes.byref(h)) == 1
+    assert L.spamm_build_view(fake, 128, 128, 1, 48, None, ctypes.byref(h)) == 1
+    assert h.value is None
+    PA = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    N = (ctypes.c_int64 * 2)(128, 96)
+    LD = (ctypes.c_int64 * 2)(128, 96)
+    PO = (ctypes.c_void_p * 2)(None, None)
+    assert L.spamm_build_view_batched(2, PA, N, LD, 1, 64, None, PO) == 1                 # 96 % 64
+    assert PO[0] is None and PO[1] is None
+
+
 def test_multiply_rejects_null_operands():
     L = _lib_or_skip()
     h = ctypes.c_void_p()
