@@ -215,6 +215,12 @@ spamm_status check_operands(const spamm_matrix* A, const spamm_matrix* B, double
         return set_error(SPAMM_EUNSUPPORTED, "leaf precisions below FP64 take FP32 operand tiles");
     if (prec == SPAMM_LEAF_F64 && A->dt != B->dt)
         return set_error(SPAMM_EUNSUPPORTED, "FP64 leaves take operands of one element type");
+    // the leaf kernels step between operand tiles with 32-bit byte strides
+    for (const spamm_matrix* M : {A, B}) {
+        const TileGeo g = tile_geo(M);
+        if (std::max(g.si, g.sk) * (int64_t)M->elem > (int64_t)UINT32_MAX)
+            return set_error(SPAMM_EUNSUPPORTED, "an operand tile row exceeds 4 GiB");
+    }
     return SPAMM_OK;
 }
 

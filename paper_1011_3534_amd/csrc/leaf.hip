@@ -400,10 +400,19 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
     const int64_t lo16 = (int64_t)nb * nb * B * B;  // hi tiles -> lo tiles
     constexpr int64_t TS = (int64_t)B * B;
-    // operand tiles: rows lda (ldb) apart; ext_a (ext_b) elements from a
-    // tile's first element to one past its last
+    // Operand tiles, in bytes: A tile (I, k) at a_row + k*a_sk and B tile
+    // (k, J) at b_col + k*b_si (both strides below 2^32, checked on the
+    // host), rows lda (ldb) elements apart, ext_a (ext_b) bytes from a tile's
+    // first element to one past its last.  Computed once here, so the loop
+    // adds one scalar product per operand and step.
+    constexpr int ESZ = is16(P) ? 4 : (int)sizeof(TA);
     const int lda = (int)d.ga.ld, ldb = (int)d.gb.ld;
-    const int64_t ext_a = (int64_t)(B - 1) * lda + B, ext_b = (int64_t)(B - 1) * ldb + B;
+    const char* const a_row = (const char*)d.A + d.ga.si * I * ESZ;
+    const char* const b_col = (const char*)d.B + d.gb.sk * J * ESZ;
+    const uint32_t a_sk = (uint32_t)(d.ga.sk * ESZ), b_si = (uint32_t)(d.gb.si * ESZ);
+    const uint32_t ext_a = (uint32_t)(((int64_t)(B - 1) * lda + B) * ESZ);
+    const uint32_t ext_b = (uint32_t)(((int64_t)(B - 1) * ldb + B) * ESZ);
+    const uint32_t kc_b = (uint32_t)(G::KC * ldb * ESZ);  // bytes between B chunks
 
     Acc acc[R][R], part[R][R];
 #pragma unroll
@@ -517,30 +526,28 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             const int tt = live ? t : T - 1;
             const int k = __builtin_amdgcn_readfirstlane(kl->k[tt / NCH]);
             const int ch = tt % NCH;
+            const char* pa = a_row + (uint64_t)(uint32_t)k * a_sk + ch * (KC * ESZ);
+            const char* pb = b_col + (uint64_t)(uint32_t)k * b_si + ch * kc_b;
+            const uint32_t na = live ? ext_a - ch * (KC * ESZ) : 0u;
+            const uint32_t nbb = live ? ext_b - ch * kc_b : 0u;
             if constexpr (is16(P) && !PRESPLIT) {
-                const int64_t ta = d.ga.tile(I, k), tb = d.gb.tile(k, J);
-                const uint32_t na = live ? (uint32_t)((ext_a - ch * KC) * 4) : 0u;
-                const uint32_t nbb = live ? (uint32_t)((ext_b - ch * KC * ldb) * 4) : 0u;
-                stage16c_load<B, P>(st, rsrc((const float*)d.A + ta + ch * KC, na),
-                                    rsrc((const float*)d.B + tb + (int64_t)ch * KC * ldb, nbb), tid, lda, ldb);
+                stage16c_load<B, P>(st, rsrc(pa, na), rsrc(pb, nbb), tid, lda, ldb);
             } else if constexpr (is16(P)) {
                 // split tiles are always packed
+                (void)pa;
+                (void)pb;
                 const int64_t ta = ((int64_t)I * nb + k) * TS, tb = ((int64_t)k * nb + J) * TS;
-                const uint32_t na = live ? (uint32_t)((TS - ch * KC) * 2) : 0u;
-                const uint32_t nbb = live ? (uint32_t)((TS - ch * KC * B) * 2) : 0u;
+                const uint32_t na16 = live ? (uint32_t)((TS - ch * KC) * 2) : 0u;
+                const uint32_t nb16 = live ? (uint32_t)((TS - ch * KC * B) * 2) : 0u;
                 __amdgpu_buffer_rsrc_t ra[2], rb[2];
 #pragma unroll
                 for (int h = 0; h < G::NARR; ++h) {
-                    ra[h] = rsrc(d.A16 + h * lo16 + ta + ch * KC, na);
-                    rb[h] = rsrc(d.B16 + h * lo16 + tb + (int64_t)ch * KC * B, nbb);
+                    ra[h] = rsrc(d.A16 + h * lo16 + ta + ch * KC, na16);
+                    rb[h] = rsrc(d.B16 + h * lo16 + tb + (int64_t)ch * KC * B, nb16);
                 }
                 stage16_load<B, P>(st, ra, rb, tid);
             } else {
-                const int64_t ta = d.ga.tile(I, k), tb = d.gb.tile(k, J);
-                const uint32_t na = live ? (uint32_t)((ext_a - ch * KC) * sizeof(TA)) : 0u;
-                const uint32_t nbb = live ? (uint32_t)((ext_b - ch * KC * ldb) * sizeof(TA)) : 0u;
-                stage_load<B, P, TA>(st, rsrc((const TA*)d.A + ta + ch * KC, na),
-                                     rsrc((const TA*)d.B + tb + (int64_t)ch * KC * ldb, nbb), tid, lda, ldb);
+                stage_load<B, P, TA>(st, rsrc(pa, na), rsrc(pb, nbb), tid, lda, ldb);
             }
         };
         // (step t's FP16 scales apply when splitting on the fly; a store past
