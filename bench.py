@@ -36,17 +36,19 @@ HW_MULT = {"f64": 1, "f32": 1, "bf16": 1, "bf16x3": 3, "f16": 1, "f16x3": 3}
 # figures belong to one version of the leaf kernel source: when the source
 # hash differs they are not reported.
 PMC_TRAFFIC = {
-    "src_sha256_16": "cb57335b93e66730",
+    "src_sha256_16": "754fcbfa1b8c269a",
     "fetch_factor": 2.0, "write_factor": 1.0,
-    "leaf": {("f16x3", 64, 8192, 1e-6): (303798.9, 262915.6), ("f32", 64, 8192, 1e-6): (283889.3, 262920.2)},
+    # (precision, leaf, n, tau, operand build) -> (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
+    "leaf": {("f16x3", 64, 8192, 1e-6, "view"): (244263.4, 262947.2),
+             ("f32", 64, 8192, 1e-6, "view"): (239988.4, 262935.5)},
 }
 
 
-def leaf_traffic(prec, leaf, n, tau):
+def leaf_traffic(prec, leaf, n, tau, build):
     import hashlib
     src = os.path.join(ROOT, "paper_1011_3534_amd", "csrc", "leaf.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    key = (prec, leaf, n, float(f"{tau:.3g}"))
+    key = (prec, leaf, n, float(f"{tau:.3g}"), build)
     if sha != PMC_TRAFFIC["src_sha256_16"] or key not in PMC_TRAFFIC["leaf"]:
         return None
     f, w = PMC_TRAFFIC["leaf"][key]
@@ -111,6 +113,8 @@ def main():
     ap.add_argument("--build", default="view", choices=["view", "packed"],
                     help="how a step builds the operand: view (spamm_build_view: leaf norms only, the leaf "
                          "kernels read the dense array) or packed (spamm_build: copy into tile-major storage)")
+    ap.add_argument("--no-build-compare", action="store_true",
+                    help="time only the --build mode (profiling runs: every leaf dispatch reads one layout)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 256 MiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--workload", default="algebraic8192",
@@ -207,19 +211,20 @@ def main():
                 sp.multiply(A, A, tau, p, out=C)
 
         modes = {}
-        for mode in ("packed", "view"):
+        mode = "packed" if args.presplit else args.build
+        other = "view" if mode == "packed" else "packed"
+        for mode_t in ((mode,) if args.no_build_compare else ("packed", "view")):
             for _ in range(args.warmup):
-                step(mode)
+                step(mode_t)
             torch.cuda.synchronize()
             ev0.record()
             for _ in range(args.steps):
-                step(mode)
+                step(mode_t)
             ev1.record()
             torch.cuda.synchronize()
-            modes[mode] = ev0.elapsed_time(ev1) / args.steps
-        mode = "packed" if args.presplit else args.build
+            modes[mode_t] = ev0.elapsed_time(ev1) / args.steps
         step_ms = modes[mode]
-        other = "view" if mode == "packed" else "packed"
+        modes.setdefault(other, None)
         Ah = Av if mode == "view" else A
         phases = [sp.multiply_timed(Ah, Ah, tau, p, out=C)[1] for _ in range(args.steps)]
         leaf_ms = float(np.mean([ph["ms_leaf"] for ph in phases]))
@@ -230,7 +235,7 @@ def main():
                       f"step_ms_{other}_build": modes[other], "multiply_ms": mult_ms,
                       "leaf_ms": leaf_ms, "cull_ms": cull_ms, "leaf_tflops": flops / leaf_ms / 1e9,
                       "step_tflops": flops / step_ms / 1e9, "speedup_vs_dense_fp32": dense_ms / step_ms}
-        log(f"{p}: step {step_ms:.3f} ms ({mode} build; {other} build {modes[other]:.3f}) "
+        log(f"{p}: step {step_ms:.3f} ms ({mode} build; {other} build {modes[other] or 0:.3f}) "
             f"(multiply {mult_ms:.3f}, leaf {leaf_ms:.3f}, cull {cull_ms:.3f}) "
             f"leaf {flops / leaf_ms / 1e9:.1f} TFLOP/s")
 
@@ -241,7 +246,7 @@ def main():
     r = results[best]
     achieved = r["leaf_tflops"]
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[best], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_TFLOPS[best], 4), "traffic": leaf_traffic(best, b, n, r["tau"]),
+            "frac": round(achieved / PEAK_TFLOPS[best], 4), "traffic": leaf_traffic(best, b, n, r["tau"], r["build"]),
             "kernel": f"k_leaf<{b},{best}>", "hw_flop_mult": HW_MULT[best],
             "hw_frac": round(achieved * HW_MULT[best] / PEAK_TFLOPS[best], 4)}
     out = {"metric": METRIC, "value": round(r["step_tflops"], 3), "unit": "TFLOP/s", "n_gpus": 1,
