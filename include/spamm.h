@@ -52,7 +52,8 @@ typedef enum {
     SPAMM_ENOMEM = 2,       /* device allocation failed                             */
     SPAMM_EHIP = 3,         /* a HIP runtime call failed (message names it)         */
     SPAMM_ECAPACITY = 4,    /* a device-side buffer would overflow                  */
-    SPAMM_ENONFINITE = 5,   /* a non-finite norm was met (inf/nan in an operand)    */
+    SPAMM_ENONFINITE = 5,   /* an operand holds an inf or NaN (its root norm is     *
+                             * not finite), reported by the syncing calls         */
     SPAMM_ENOCONV = 6,      /* SP2 did not meet its stopping rule within max_iter   */
     SPAMM_EUNSUPPORTED = 7  /* valid request this build does not implement          */
 } spamm_status;
@@ -203,7 +204,8 @@ spamm_status spamm_build_view_batched(int32_t count, const void* const* dev_a, c
  *           fills the statistics.
  * The result carries its own norm pyramid, so it can be an operand of the
  * next product.  Every C tile with no kept product is exactly zero.
- * Errors: EINVAL, ENOMEM, EHIP, ENONFINITE (reported through st). */
+ * Errors: EINVAL, ENOMEM, EHIP; with st, ENONFINITE when A or B holds an
+ * inf or NaN (the product is still written) and ECAPACITY. */
 spamm_status spamm_multiply(const spamm_matrix* A, const spamm_matrix* B, double tau,
                             spamm_leaf_prec prec, void* stream, spamm_matrix** C,
                             spamm_stats* st);
@@ -281,7 +283,7 @@ typedef struct {
  * Batch scratch (frontiers, counters, schedule) is allocated for the call and
  * released at its end.
  * Errors: EINVAL (count < 1 or > 128, mismatched pairs, mixed leaf sizes),
- * ENOMEM, EHIP. */
+ * ENOMEM, EHIP; with st, ECAPACITY and ENONFINITE as spamm_multiply. */
 spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
                                     const spamm_matrix* const* B, const double* tau,
                                     spamm_leaf_prec prec, const spamm_tune* tune, void* stream,
@@ -439,7 +441,8 @@ spamm_status spamm_info(const spamm_matrix* M, int64_t* n, int32_t* leaf, spamm_
 
 /* Squared norms of tier `level` (0 = leaves) copied to host_out
  * (m_l x m_l row-major, m_l = ceil(nb / 2^level)); cap in elements.
- * Synchronises the stream. */
+ * Synchronises the stream.  ENONFINITE (after the copy) when the matrix
+ * holds an inf or NaN. */
 spamm_status spamm_norms(const spamm_matrix* M, int32_t level, double* host_out, int64_t cap,
                          void* stream);
 

@@ -186,6 +186,16 @@ def _check(code):
         raise SpammError(code, msg.decode() if msg else "")
 
 
+def _check_result(code, h, out):
+    """_check for calls that hand back a result handle: a syncing check that
+    fails after the product was written (ECAPACITY, ENONFINITE) still returns
+    a fresh handle, which is freed before raising."""
+    if code != 0 and out is None and h.value:
+        lib().spamm_free(h)
+        h.value = None
+    _check(code)
+
+
 def _stream(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -193,29 +203,33 @@ def _stream(stream):
 
 
 def use_torch_allocator(enable: bool = True):
-    """Back the library's device allocations with torch's caching allocator."""
+    """Back the library's device allocations with torch's caching allocator.
+
+    Every handle keeps the allocator it was created with (its storage is
+    returned to it when the handle is freed), so the callbacks are made once
+    and live as long as the process: a handle made while they were installed
+    may be freed after the library's allocator was switched back or set again."""
     global _alloc_cb, _dealloc_cb
     import torch
 
     if not enable:
         _check(lib().spamm_set_allocator(_ALLOC_FN(), _DEALLOC_FN(), None))
-        _alloc_cb = _dealloc_cb = None
         return
+    if _alloc_cb is None:
+        def _alloc(nbytes, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes))
+            except Exception:          # OOM: the library reports SPAMM_ENOMEM
+                return None
 
-    def _alloc(nbytes, ctx):
-        try:
-            return torch.cuda.caching_allocator_alloc(int(nbytes))
-        except Exception:          # OOM: the library reports SPAMM_ENOMEM
-            return None
+        def _dealloc(ptr, ctx):
+            try:
+                torch.cuda.caching_allocator_delete(int(ptr))
+            except Exception:
+                pass
 
-    def _dealloc(ptr, ctx):
-        try:
-            torch.cuda.caching_allocator_delete(int(ptr))
-        except Exception:
-            pass
-
-    _alloc_cb = _ALLOC_FN(_alloc)
-    _dealloc_cb = _DEALLOC_FN(_dealloc)
+        _alloc_cb = _ALLOC_FN(_alloc)
+        _dealloc_cb = _DEALLOC_FN(_dealloc)
     _check(lib().spamm_set_allocator(_alloc_cb, _dealloc_cb, None))
 
 
@@ -345,11 +359,12 @@ def multiply(A: Matrix, B: Matrix, tau: float, prec: str = "f32", out: Matrix | 
     h = ctypes.c_void_p(out.handle.value if out is not None else None)
     st = Stats() if stats else None
     if depth_scaled:
-        _check(lib().spamm_multiply_ex(A.handle, B.handle, float(tau), LEAF[prec], TAU_DEPTH_SCALED,
-                                       _stream(stream), ctypes.byref(h), ctypes.byref(st) if st is not None else None))
+        code = lib().spamm_multiply_ex(A.handle, B.handle, float(tau), LEAF[prec], TAU_DEPTH_SCALED,
+                                       _stream(stream), ctypes.byref(h), ctypes.byref(st) if st is not None else None)
     else:
-        _check(lib().spamm_multiply(A.handle, B.handle, float(tau), LEAF[prec], _stream(stream), ctypes.byref(h),
-                                    ctypes.byref(st) if st is not None else None))
+        code = lib().spamm_multiply(A.handle, B.handle, float(tau), LEAF[prec], _stream(stream), ctypes.byref(h),
+                                    ctypes.byref(st) if st is not None else None)
+    _check_result(code, h, out)
     C = out if out is not None else Matrix(h)
     return (C, st.to_dict()) if stats else C
 
@@ -381,8 +396,13 @@ def multiply_batched(As, Bs, taus, prec: str = "f32", outs=None, stats: bool = F
     if schedule is not None:
         tune = Tune()
         tune.schedule = SCHEDULE[schedule]
-    _check(lib().spamm_multiply_batched(count, PA, PB, T, LEAF[prec], ctypes.byref(tune) if tune else None,
-                                        _stream(stream), PC, st if st is not None else None))
+    code = lib().spamm_multiply_batched(count, PA, PB, T, LEAF[prec], ctypes.byref(tune) if tune else None,
+                                        _stream(stream), PC, st if st is not None else None)
+    if code != 0:
+        for m in range(count):
+            if (outs is None or outs[m] is None) and PC[m]:
+                lib().spamm_free(ctypes.c_void_p(PC[m]))
+    _check(code)
     Cs = []
     for m in range(count):
         if outs is not None and outs[m] is not None:
@@ -508,8 +528,9 @@ def tau_select(A: Matrix, B: Matrix, target: float, model: TauModel | None = Non
     """(C at the selected tau, info dict); judged against the exact product."""
     h = ctypes.c_void_p(out.handle.value if out is not None else None)
     info = TauInfo()
-    _check(lib().spamm_tau_select(A.handle, B.handle, float(target), model.handle if model else None, LEAF[prec],
-                                  float(resolution_decades), _stream(stream), ctypes.byref(h), ctypes.byref(info)))
+    code = lib().spamm_tau_select(A.handle, B.handle, float(target), model.handle if model else None, LEAF[prec],
+                                  float(resolution_decades), _stream(stream), ctypes.byref(h), ctypes.byref(info))
+    _check_result(code, h, out)
     C = out if out is not None else Matrix(h)
     return C, info.to_dict()
 

@@ -1,7 +1,9 @@
 // extern "C" entry points of libspamm (declared in include/spamm.h).
 //
 // Host-side validation happens before anything is enqueued; device-side
-// conditions are latched in a status word and reported by syncing calls.
+// conditions are reported by syncing calls (a product's capacity flag in its
+// counters; a non-finite operand by its root norm, which an inf or NaN
+// anywhere in the matrix makes non-finite).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -138,14 +140,17 @@ spamm_status alloc_storage(spamm_matrix* M, hipStream_t s) {
     int* mm = reinterpret_cast<int*>(off + kMaxLevels);
     SPAMM_HIP(hipMemcpyAsync(off, M->lvl_off, sizeof(int64_t) * kMaxLevels, hipMemcpyHostToDevice, s));
     SPAMM_HIP(hipMemcpyAsync(mm, M->lvl_m, sizeof(int32_t) * kMaxLevels, hipMemcpyHostToDevice, s));
-    SPAMM_HIP(hipMemsetAsync(mm + kMaxLevels, 0, 64, s));  // status word
     return SPAMM_OK;
 }
 
-unsigned* status_word(const spamm_matrix* M) {
-    int64_t* off = reinterpret_cast<int64_t*>(M->norms + M->norms_total);
-    int* mm = reinterpret_cast<int*>(off + kMaxLevels);
-    return reinterpret_cast<unsigned*>(mm + kMaxLevels);
+// The squared Frobenius norm of the whole matrix (the root of its pyramid)
+// is finite iff every element is: x*x of an inf or NaN is inf or NaN, and
+// FP64 sums of FP32 squares cannot overflow.  Call after the stream syncs.
+spamm_status check_finite(const spamm_matrix* M, const char* what) {
+    double root = 0.0;
+    SPAMM_HIP(hipMemcpy(&root, M->norms + M->lvl_off[M->L], sizeof root, hipMemcpyDeviceToHost));
+    if (!std::isfinite(root)) return set_error(SPAMM_ENONFINITE, std::string("non-finite value in ") + what);
+    return SPAMM_OK;
 }
 
 // Product scratch owned by the result handle.
@@ -413,8 +418,7 @@ spamm_status build_single(const void* dev_a, int64_t n, int64_t lda, spamm_dtype
     }
     M->last_stream = s;
     M->gen++;
-    hipError_t e = hipMemsetAsync(status_word(M), 0, 4, s);
-    if (e == hipSuccess) e = launch_pack_norm(dev_a, n, lda, dt, M, status_word(M), kind, s);
+    hipError_t e = launch_pack_norm(dev_a, n, lda, dt, M, kind, s);
     if (e == hipSuccess) e = launch_upper_norms(M, s, nullptr);
     if (e != hipSuccess) {
         st = hip_error(e, "spamm_build kernels");
@@ -484,7 +488,7 @@ spamm_status build_batched(int32_t count, const void* const* dev_a, const int64_
     for (int m = 0; m < count; ++m) {
         M[m]->last_stream = s;
         M[m]->gen++;
-        hp[m] = pack_desc(dev_a[m], n[m], lda[m], M[m], status_word(M[m]), waves);
+        hp[m] = pack_desc(dev_a[m], n[m], lda[m], M[m], waves);
         waves += hp[m].nb * hp[m].nstrips;
         ht[m] = norm_table(M[m]);
     }
@@ -588,7 +592,12 @@ spamm_status spamm_multiply_ex(const spamm_matrix* A, const spamm_matrix* B, dou
         return r;
     }
     *C = Cm;
-    if (st) return read_stats(Cm, s, st, tau);
+    if (st) {
+        r = read_stats(Cm, s, st, tau);
+        if (r == SPAMM_OK) r = check_finite(A, "operand A");
+        if (r == SPAMM_OK) r = check_finite(B, "operand B");
+        return r;
+    }
     return SPAMM_OK;
 }
 
@@ -644,10 +653,7 @@ spamm_status spamm_norms(const spamm_matrix* M, int32_t level, double* host_out,
     hipStream_t s = (hipStream_t)stream;
     SPAMM_HIP(hipStreamSynchronize(s));
     SPAMM_HIP(hipMemcpy(host_out, M->norms + M->lvl_off[level], sizeof(double) * m * m, hipMemcpyDeviceToHost));
-    unsigned stw = 0;
-    SPAMM_HIP(hipMemcpy(&stw, status_word(M), 4, hipMemcpyDeviceToHost));
-    if (stw & kDevNonFinite) return set_error(SPAMM_ENONFINITE, "non-finite norm in operand");
-    return SPAMM_OK;
+    return check_finite(M, "the matrix");
 }
 
 spamm_status spamm_task_list(const spamm_matrix* C, uint64_t* host_keys, int64_t cap, int64_t* count,
@@ -867,6 +873,10 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
             o.culled_bound = h.culled_bound[m];
         }
         if (e == hipSuccess && (h.status & kDevCapacity)) r = set_error(SPAMM_ECAPACITY, "frontier capacity exceeded");
+        for (int m = 0; m < count && e == hipSuccess && r == SPAMM_OK; ++m) {
+            r = check_finite(A[m], "an operand A[m]");
+            if (r == SPAMM_OK) r = check_finite(B[m], "an operand B[m]");
+        }
     }
     dev_free(owner, ws, s);
     if (e != hipSuccess) {

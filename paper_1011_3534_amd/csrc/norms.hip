@@ -44,7 +44,7 @@ __device__ inline int8_t tile_exponent(double mx) {
 template <typename T, int B>
 __device__ __forceinline__ void pack_wave(const T* __restrict__ a, int64_t n, int64_t lda, int64_t nb,
                                           int64_t nstrips, T* __restrict__ tiles, double* __restrict__ S0,
-                                          int8_t* __restrict__ texp, unsigned* status, int vec, int64_t gw) {
+                                          int8_t* __restrict__ texp, int vec, int64_t gw) {
     constexpr int V = Vec16<T>::V;
     constexpr int LPT = B / V;  // lanes per tile
     using VT = typename Vec16<T>::type;
@@ -118,7 +118,6 @@ __device__ __forceinline__ void pack_wave(const T* __restrict__ a, int64_t n, in
     if (live && tl == 0) {
         S0[I * nb + K] = acc[0];
         texp[I * nb + K] = tile_exponent(mx);
-        if (!isfinite(acc[0])) atomicOr(status, kDevNonFinite);
     }
 }
 
@@ -126,9 +125,9 @@ template <typename T, int B>
 __global__ void __launch_bounds__(256) k_pack_norm(const T* __restrict__ a, int64_t n, int64_t lda,
                                                    int64_t nb, int64_t nstrips, T* __restrict__ tiles,
                                                    double* __restrict__ S0, int8_t* __restrict__ texp,
-                                                   unsigned* status, int vec) {
+                                                   int vec) {
     const int64_t gw = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-    pack_wave<T, B>(a, n, lda, nb, nstrips, tiles, S0, texp, status, vec, gw);
+    pack_wave<T, B>(a, n, lda, nb, nstrips, tiles, S0, texp, vec, gw);
 }
 
 // Batch: the waves of all matrices in one launch; wave_base is the first
@@ -142,13 +141,8 @@ __global__ void __launch_bounds__(256) k_pack_norm_batched(const PackDesc* __res
         if (pd[mid].wave_base <= gw) lo = mid; else hi = mid - 1;
     }
     const PackDesc& d = pd[lo];
-    pack_wave<T, B>((const T*)d.a, d.n, d.lda, d.nb, d.nstrips, (T*)d.tiles, d.S0, d.texp, d.status, d.vec,
+    pack_wave<T, B>((const T*)d.a, d.n, d.lda, d.nb, d.nstrips, (T*)d.tiles, d.S0, d.texp, d.vec,
                     gw - d.wave_base);
-}
-
-__global__ void k_zero_status_batched(const PackDesc* __restrict__ pd, int count) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m < count) *pd[m].status = 0u;
 }
 
 // One tier up: P[I,K] = (S[2I,2K] + S[2I,2K+1]) + (S[2I+1,2K] + S[2I+1,2K+1]).
@@ -313,7 +307,7 @@ __global__ void k_fill_u64(uint64_t* p, int64_t count, uint64_t v) {
 }
 
 template <typename T, int B>
-hipError_t pack_t(const void* a, int64_t n, int64_t lda, spamm_matrix* M, unsigned* status, hipStream_t s) {
+hipError_t pack_t(const void* a, int64_t n, int64_t lda, spamm_matrix* M, hipStream_t s) {
     constexpr int V = Vec16<T>::V;
     const int64_t nb = M->nb;
     const int64_t nstrips = (nb * B + kWave * V - 1) / (kWave * V);
@@ -321,37 +315,37 @@ hipError_t pack_t(const void* a, int64_t n, int64_t lda, spamm_matrix* M, unsign
     const int64_t blocks = (waves + 3) / 4;
     const int vec = ((uintptr_t)a % 16 == 0) && (lda % V == 0) && (n % V == 0);
     hipLaunchKernelGGL((k_pack_norm<T, B>), dim3((unsigned)blocks), dim3(256), 0, s, (const T*)a, n, lda, nb,
-                       nstrips, M->view ? nullptr : (T*)M->tiles, M->norms, M->texp, status, vec);
+                       nstrips, M->view ? nullptr : (T*)M->tiles, M->norms, M->texp, vec);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_pack_norm(const void* a, int64_t n, int64_t lda, spamm_dtype dt, spamm_matrix* M,
-                            unsigned* status, int split_kind, hipStream_t s) {
+                            int split_kind, hipStream_t s) {
     if (split_kind >= 0) {
         // pack, then split the tiles just written (measured faster than one
         // fused pass that keeps each column's values in registers)
         if (dt != SPAMM_F32 || !M->split) return hipErrorInvalidValue;
         hipError_t e = hipErrorInvalidValue;
         switch (M->b) {
-            case 32: e = pack_t<float, 32>(a, n, lda, M, status, s); break;
-            case 64: e = pack_t<float, 64>(a, n, lda, M, status, s); break;
-            case 128: e = pack_t<float, 128>(a, n, lda, M, status, s); break;
+            case 32: e = pack_t<float, 32>(a, n, lda, M, s); break;
+            case 64: e = pack_t<float, 64>(a, n, lda, M, s); break;
+            case 128: e = pack_t<float, 128>(a, n, lda, M, s); break;
         }
         return e == hipSuccess ? launch_split(M, split_kind, nullptr, s) : e;
     }
     if (dt == SPAMM_F32) {
         switch (M->b) {
-            case 32: return pack_t<float, 32>(a, n, lda, M, status, s);
-            case 64: return pack_t<float, 64>(a, n, lda, M, status, s);
-            case 128: return pack_t<float, 128>(a, n, lda, M, status, s);
+            case 32: return pack_t<float, 32>(a, n, lda, M, s);
+            case 64: return pack_t<float, 64>(a, n, lda, M, s);
+            case 128: return pack_t<float, 128>(a, n, lda, M, s);
         }
     } else {
         switch (M->b) {
-            case 32: return pack_t<double, 32>(a, n, lda, M, status, s);
-            case 64: return pack_t<double, 64>(a, n, lda, M, status, s);
-            case 128: return pack_t<double, 128>(a, n, lda, M, status, s);
+            case 32: return pack_t<double, 32>(a, n, lda, M, s);
+            case 64: return pack_t<double, 64>(a, n, lda, M, s);
+            case 128: return pack_t<double, 128>(a, n, lda, M, s);
         }
     }
     return hipErrorInvalidValue;
@@ -413,7 +407,6 @@ hipError_t launch_upper_norms_batched(spamm_matrix* const* M, int count, const N
 // order, so wave_base ascends).
 hipError_t launch_pack_norm_batched(const PackDesc* d_pd, int count, int64_t waves, spamm_dtype dt, int b,
                                     hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_status_batched, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, d_pd, count);
     const unsigned blocks = (unsigned)((waves + 3) / 4);
 #define SPAMM_PACK_B(T, BB) \
     hipLaunchKernelGGL((k_pack_norm_batched<T, BB>), dim3(blocks), dim3(256), 0, s, d_pd, count)
@@ -437,7 +430,7 @@ hipError_t launch_pack_norm_batched(const PackDesc* d_pd, int count, int64_t wav
 }
 
 // Descriptor of one matrix of a batched pack; wave_base as laid out by the caller.
-PackDesc pack_desc(const void* a, int64_t n, int64_t lda, spamm_matrix* M, unsigned* status, int64_t wave_base) {
+PackDesc pack_desc(const void* a, int64_t n, int64_t lda, spamm_matrix* M, int64_t wave_base) {
     PackDesc d;
     std::memset(&d, 0, sizeof d);
     const int V = M->dt == SPAMM_F32 ? 4 : 2;
@@ -450,7 +443,6 @@ PackDesc pack_desc(const void* a, int64_t n, int64_t lda, spamm_matrix* M, unsig
     d.tiles = M->view ? nullptr : M->tiles;
     d.S0 = M->norms;
     d.texp = M->texp;
-    d.status = status;
     d.vec = ((uintptr_t)a % 16 == 0) && (lda % V == 0) && (n % V == 0);
     return d;
 }

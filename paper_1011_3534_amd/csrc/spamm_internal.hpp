@@ -14,8 +14,7 @@ constexpr int kMaxLevels = SPAMM_MAX_LEVELS;
 constexpr int kMaxBatch = 128;
 constexpr int kWave = 64;
 
-// Status bits latched on the device, surfaced by the next syncing call.
-constexpr unsigned kDevNonFinite = 1u;
+// Status bit latched on the device by a product, surfaced by the next syncing call.
 constexpr unsigned kDevCapacity = 2u;
 
 // Frontier key of an octree node: product index m (7 bits) | I | J | K (19 bits each).
@@ -204,7 +203,7 @@ inline TileGeo tile_geo(const spamm_matrix* M) {
 // split_kind >= 0 (FP32 input, M->split allocated): the same pass also writes
 // the split 16-bit tiles of that kind.
 hipError_t launch_pack_norm(const void* a, int64_t n, int64_t lda, spamm_dtype dt, spamm_matrix* M,
-                            unsigned* status, int split_kind, hipStream_t s);
+                            int split_kind, hipStream_t s);
 hipError_t launch_upper_norms(spamm_matrix* M, hipStream_t s, const int* active);
 
 // Batched builds and result pyramids (norms.hip).
@@ -215,7 +214,6 @@ struct PackDesc {
     void* tiles;              // NULL: norms only (a view)
     double* S0;               // leaf tier of the pyramid
     int8_t* texp;
-    unsigned* status;
     int32_t vec, pad_;
 };
 struct NormTable {
@@ -224,7 +222,7 @@ struct NormTable {
     int32_t m[kMaxLevels];
     int32_t L, pad_;
 };
-PackDesc pack_desc(const void* a, int64_t n, int64_t lda, spamm_matrix* M, unsigned* status, int64_t wave_base);
+PackDesc pack_desc(const void* a, int64_t n, int64_t lda, spamm_matrix* M, int64_t wave_base);
 NormTable norm_table(const spamm_matrix* M);
 hipError_t launch_pack_norm_batched(const PackDesc* d_pd, int count, int64_t waves, spamm_dtype dt, int b,
                                     hipStream_t s);

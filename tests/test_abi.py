@@ -81,6 +81,18 @@ def test_helpers_reject_null():
     L.spamm_free(None)                                                           # no-op
 
 
+def test_allocator_callbacks_outlive_reinstall():
+    # handles keep the allocator they were made with: the ctypes thunks must
+    # stay alive when the allocator is installed again or switched back
+    _lib_or_skip()
+    sp.use_torch_allocator(True)
+    a, d = sp._alloc_cb, sp._dealloc_cb
+    sp.use_torch_allocator(True)
+    assert sp._alloc_cb is a and sp._dealloc_cb is d
+    sp.use_torch_allocator(False)
+    assert sp._alloc_cb is a and sp._dealloc_cb is d
+
+
 def test_set_allocator_requires_both_functions():
     L = _lib_or_skip()
     alloc = sp._ALLOC_FN(lambda n, c: None)

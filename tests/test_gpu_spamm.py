@@ -380,3 +380,30 @@ def test_flat_start_cull_matches_full_descent(n, b, tau):
     assert np.array_equal(C1.to_dense().cpu().numpy(), C2.to_dense().cpu().numpy())
     for lv in range(C1.levels + 1):
         assert np.array_equal(C1.norms(lv), C2.norms(lv))
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+@pytest.mark.parametrize("view", [False, True])
+def test_nonfinite_operand_is_reported(bad, view):
+    """An inf or NaN anywhere makes the root norm non-finite: spamm_norms and
+    products with statistics report ENONFINITE; a rebuild from finite data
+    clears it."""
+    print(f"[case] nonfinite bad={bad} view={view}", flush=True)
+    n, b = 256, 64
+    a = si.exp_decay(n, 0.9, 51, np.float32)
+    a_bad = a.copy()
+    a_bad[200, 17] = bad
+    A = sp.build(to_dev(a_bad), b, view=view)
+    with pytest.raises(sp.SpammError) as e:
+        A.norms(0)
+    assert e.value.status == "ENONFINITE"
+    F = sp.build(to_dev(a), b)
+    with pytest.raises(sp.SpammError) as e:
+        sp.multiply(F, A, 1e-6, "f32", stats=True)
+    assert e.value.status == "ENONFINITE"
+    C = sp.multiply(F, A, 1e-6, "f32")  # without statistics nothing syncs or checks
+    C2 = sp.multiply(F, F, 1e-6, "f32", out=C, stats=True)[0]
+    assert C2 is C
+    good = to_dev(a)
+    A2 = sp.build(good, b, out=A, view=view)
+    assert np.all(np.isfinite(A2.norms(0)))
