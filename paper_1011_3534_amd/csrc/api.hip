@@ -322,6 +322,12 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
         while (fs < C->L && C->lvl_m[fs] > 64) ++fs;
         cp.flat_start = fs;
         cp.flat_m = C->lvl_m[fs];
+        // up to 2^27 leaf triples, testing every one in a single pass (no
+        // frontier, no atomics per triple) beats the descent
+        if (C->nb * C->nb * C->nb <= ((int64_t)1 << 27)) {
+            cp.leaf_direct = 1;
+            cp.leaf_nb = C->nb;
+        }
     }
     int64_t items[kMaxLevels];
     tier_items(C, ps->front_cap, items);

@@ -268,6 +268,48 @@ __global__ void __launch_bounds__(kCullThreads)
     }
 }
 
+// The leaf tier of a single product straight from the flat rule, without
+// the tiers above (every ancestor of a passing triple passes, see
+// enum_keep): bit K of C tile (I, J) is set iff
+// !(S_A[I,K] * S_B[K,J] < tau^2).  Lane j of a wave owns mask word w of tile
+// (I, J0 + j) and walks its 64 K, so S_A[I,K] is one value per wave and row
+// K of S_B is read coalesced across the lanes; the word is built in a
+// register and stored once, so every mask word is written (no clearing, no
+// atomics) and the kept K of a tile stay in ascending order.  Block
+// (x, y, w): rows I = x*kLeafRows .., tiles J = 64y .., word w.
+constexpr int kLeafRows = 2;
+__global__ void __launch_bounds__(kLeafRows * kWave)
+    k_cull_leaf(const ProdDesc* __restrict__ desc, DevCounters* __restrict__ ctr, const int* __restrict__ active) {
+    if (active && *active == 0) return;
+    const ProdDesc& d = desc[0];
+    const int nb = d.nb, W = d.W;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int I = blockIdx.x * kLeafRows + wid, J = blockIdx.y * kWave + lane, w = blockIdx.z;
+    unsigned long long bits = 0;
+    if (I < nb && J < nb && !(d.sym_upper && I > J)) {
+        const double* SA = d.SA + d.lvl_off[0] + (int64_t)I * nb;
+        const double* SB = d.SB + d.lvl_off[0] + J;
+        const int k0 = w * 64, kn = min(64, nb - k0);
+        const double t2 = d.tau2;
+#pragma unroll 8
+        for (int k = 0; k < kn; ++k) {
+            const double sa = SA[k0 + k], sb = SB[(int64_t)(k0 + k) * nb];
+            bits |= (unsigned long long)!(sa * sb < t2) << k;
+        }
+    }
+    if (I < nb && J < nb) d.mask[((int64_t)I * nb + J) * W + w] = bits;
+    // kept triples (the product's task count): one atomic per block
+    __shared__ unsigned long long s_cnt[kLeafRows];
+    const unsigned long long c = wave_sum_u64((unsigned long long)__popcll(bits));
+    if (lane == 0) s_cnt[wid] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int r = 0; r < kLeafRows; ++r) t += s_cnt[r];
+        if (t) atomicAdd(&ctr->survivors[0][0], t);
+    }
+}
+
 // Counters, per-product non-empty tile counts and (single product) the leaf
 // bitmask, zeroed in one launch.
 __global__ void k_cull_prep(DevCounters* ctr, unsigned long long* nonempty, int nprod, uint64_t* mask,
@@ -317,7 +359,9 @@ hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t
                           uint64_t* front1, DevCounters* ctr, int want_bound, const int* active,
                           const int64_t* tier_items, hipStream_t s) {
     {
-        const int64_t words = mask ? plan.mask_words : 0;  // (a batch clears its masks with launch_clear_masks)
+        // (a batch clears its masks with launch_clear_masks; the direct leaf
+        // pass writes every word)
+        const int64_t words = mask && !plan.leaf_direct ? plan.mask_words : 0;
         int64_t blocks = (words + 255) / 256;
         blocks = blocks < 8 ? 8 : (blocks > 2048 ? 2048 : blocks);
         hipLaunchKernelGGL(k_cull_prep, dim3((unsigned)blocks), dim3(256), 0, s, ctr, plan.nonempty, plan.count, mask,
@@ -325,6 +369,13 @@ hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t
     }
     const int top = plan.Lmax < 1 ? 1 : plan.Lmax;
     int l = top;
+    if (plan.leaf_direct) {
+        const unsigned nb = (unsigned)plan.leaf_nb;
+        hipLaunchKernelGGL(k_cull_leaf, dim3((nb + kLeafRows - 1) / kLeafRows, (nb + kWave - 1) / kWave,
+                                             (nb + 63) / 64),
+                           dim3(kLeafRows * kWave), 0, s, d_desc, ctr, active);
+        return hipGetLastError();
+    }
     if (plan.flat_start >= 1) {
         // tier flat_start enumerated directly; its frontier lives in buffer (flat_start & 1)
         const int fs = plan.flat_start;

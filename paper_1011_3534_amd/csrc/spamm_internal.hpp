@@ -243,6 +243,8 @@ struct CullPlan {
     unsigned long long* nonempty = nullptr;  // per-product non-empty tile counters (zeroed with the rest)
     int flat_start = 0;     // single product, flat threshold: enumerate tier flat_start (>= 1) directly
     int flat_m = 0;         //   its size m; the tiers above it are not visited (nor counted)
+    int leaf_direct = 0;    // single product, flat threshold: test every leaf triple, no tiers visited
+    int64_t leaf_nb = 0;    //   (nb of the product; the leaf tier's kept count is still counted)
 };
 hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t* mask, uint64_t* front0,
                           uint64_t* front1, DevCounters* ctr, int want_bound, const int* active,

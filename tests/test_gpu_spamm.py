@@ -364,8 +364,8 @@ def test_depth_scaled_rejects_small_tau():
 @pytest.mark.parametrize("n,b,tau", [(8192, 64, 1e-6), (4000, 32, 1e-6), (900, 64, 1e-5), (130, 64, 1e-6),
                                      (100, 64, 1e-6), (700, 16 * 2, 0.0)])
 def test_flat_start_cull_matches_full_descent(n, b, tau):
-    # without statistics a single flat-threshold product enumerates the first
-    # tier of at most 64^3 nodes directly (the tiers above are implied by the
+    # without statistics a single flat-threshold product tests every leaf
+    # triple directly (up to 2^27 of them; the tiers above are implied by the
     # flat rule): the kept triples equal the oracle's, and C equals the product
     # culled by the full descent from the root (taken when statistics are on)
     _case(f"flat-start cull n={n} b={b} tau={tau}")
@@ -379,6 +379,24 @@ def test_flat_start_cull_matches_full_descent(n, b, tau):
     assert np.array_equal(C2.task_list(), keys) and st["tasks"] == len(keys)
     assert np.array_equal(C1.to_dense().cpu().numpy(), C2.to_dense().cpu().numpy())
     for lv in range(C1.levels + 1):
+        assert np.array_equal(C1.norms(lv), C2.norms(lv))
+
+
+def test_flat_start_enumeration_beyond_direct_leaf_pass():
+    # nb = 513 (> 2^27 leaf triples): without statistics the cull enumerates
+    # the first tier of at most 64^3 nodes and descends from there; kept
+    # triples, C and its pyramid equal the full descent's (statistics on)
+    _case("flat-start enumeration n=16416 b=32 tau=1e-6")
+    n, b, tau = 16416, 32, 1e-6
+    a = sp.generate_decay(si.algebraic_table(n, 2.0), 45, 0.5, 1.5, False)
+    A = sp.build(a, b)
+    assert A.nb == 513
+    C1 = sp.multiply(A, A, tau, "f32")
+    C2, st = sp.multiply(A, A, tau, "f32", stats=True)
+    k1, k2 = C1.task_list(), C2.task_list()
+    assert len(k1) == st["tasks"] > 0 and np.array_equal(k1, k2)
+    assert sp.diff_norms(C1, C2)[0] == 0.0
+    for lv in range(1, C1.levels + 1):
         assert np.array_equal(C1.norms(lv), C2.norms(lv))
 
 
