@@ -271,43 +271,41 @@ __global__ void __launch_bounds__(kCullThreads)
 // The leaf tier of a single product straight from the flat rule, without
 // the tiers above (every ancestor of a passing triple passes, see
 // enum_keep): bit K of C tile (I, J) is set iff
-// !(S_A[I,K] * S_B[K,J] < tau^2).  Lane j of a wave owns mask word w of tile
-// (I, J0 + j) and walks its 64 K, so S_A[I,K] is one value per wave and row
-// K of S_B is read coalesced across the lanes; the word is built in a
-// register and stored once, so every mask word is written (no clearing, no
-// atomics) and the kept K of a tile stay in ascending order.  Block
-// (x, y, w): rows I = x*kLeafRows .., tiles J = 64y .., word w.
-constexpr int kLeafRows = 2;
-__global__ void __launch_bounds__(kLeafRows * kWave)
+// !(S_A[I,K] * S_B[K,J] < tau^2).  Block (I, y, w) forms mask word w of the
+// tiles (I, 64y + j): lane j of wave q tests the 16 K of quarter q, reading
+// row K of S_B coalesced across the lanes (S_A[I,K] is one value per
+// wave); the quarters are OR-ed in LDS and the word is stored once, so
+// every mask word is written (no clearing, no atomics per triple) and the
+// kept K of a tile stay in ascending order.
+constexpr int kLeafQuarters = 4;
+__global__ void __launch_bounds__(kLeafQuarters * kWave)
     k_cull_leaf(const ProdDesc* __restrict__ desc, DevCounters* __restrict__ ctr, const int* __restrict__ active) {
     if (active && *active == 0) return;
     const ProdDesc& d = desc[0];
     const int nb = d.nb, W = d.W;
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    const int I = blockIdx.x * kLeafRows + wid, J = blockIdx.y * kWave + lane, w = blockIdx.z;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int I = blockIdx.x, J = blockIdx.y * kWave + lane, w = blockIdx.z;
+    constexpr int KQ = 64 / kLeafQuarters;
+    const int k0 = w * 64 + q * KQ, kn = min(KQ, nb - k0);  // kn <= 0: quarter past the last K
     unsigned long long bits = 0;
-    if (I < nb && J < nb && !(d.sym_upper && I > J)) {
-        const double* SA = d.SA + d.lvl_off[0] + (int64_t)I * nb;
-        const double* SB = d.SB + d.lvl_off[0] + J;
-        const int k0 = w * 64, kn = min(64, nb - k0);
+    if (J < nb && kn > 0 && !(d.sym_upper && I > J)) {
+        const double* SA = d.SA + d.lvl_off[0] + (int64_t)I * nb + k0;
+        const double* SB = d.SB + d.lvl_off[0] + (int64_t)k0 * nb + J;
         const double t2 = d.tau2;
 #pragma unroll 8
-        for (int k = 0; k < kn; ++k) {
-            const double sa = SA[k0 + k], sb = SB[(int64_t)(k0 + k) * nb];
-            bits |= (unsigned long long)!(sa * sb < t2) << k;
-        }
+        for (int k = 0; k < kn; ++k) bits |= (unsigned long long)!(SA[k] * SB[(int64_t)k * nb] < t2) << k;
+        bits <<= q * KQ;
     }
-    if (I < nb && J < nb) d.mask[((int64_t)I * nb + J) * W + w] = bits;
-    // kept triples (the product's task count): one atomic per block
-    __shared__ unsigned long long s_cnt[kLeafRows];
-    const unsigned long long c = wave_sum_u64((unsigned long long)__popcll(bits));
-    if (lane == 0) s_cnt[wid] = c;
+    __shared__ unsigned long long s_bits[kLeafQuarters][kWave];
+    s_bits[q][lane] = bits;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int r = 0; r < kLeafRows; ++r) t += s_cnt[r];
-        if (t) atomicAdd(&ctr->survivors[0][0], t);
-    }
+    if (q != 0) return;
+    for (int r = 1; r < kLeafQuarters; ++r) bits |= s_bits[r][lane];
+    if (J < nb) d.mask[((int64_t)I * nb + J) * W + w] = bits;
+    // kept triples (the product's task count): one atomic per block
+    const unsigned long long c = wave_sum_u64((unsigned long long)__popcll(bits));
+    if (lane == 0 && c) atomicAdd(&ctr->survivors[0][0], c);
 }
 
 // Counters, per-product non-empty tile counts and (single product) the leaf
@@ -371,9 +369,8 @@ hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t
     int l = top;
     if (plan.leaf_direct) {
         const unsigned nb = (unsigned)plan.leaf_nb;
-        hipLaunchKernelGGL(k_cull_leaf, dim3((nb + kLeafRows - 1) / kLeafRows, (nb + kWave - 1) / kWave,
-                                             (nb + 63) / 64),
-                           dim3(kLeafRows * kWave), 0, s, d_desc, ctr, active);
+        hipLaunchKernelGGL(k_cull_leaf, dim3(nb, (nb + kWave - 1) / kWave, (nb + 63) / 64), dim3(kLeafQuarters * kWave),
+                           0, s, d_desc, ctr, active);
         return hipGetLastError();
     }
     if (plan.flat_start >= 1) {

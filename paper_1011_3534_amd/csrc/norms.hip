@@ -182,35 +182,50 @@ __global__ void k_norm_parent_batched(const NormTable* __restrict__ tab, int l) 
     t.norms[t.off[l] + i] = (c[0] + c[1]) + (c[2] + c[3]);
 }
 
-// Batch, the small tiers of matrix blockIdx.x in one block, tier by tier.
-__global__ void __launch_bounds__(1024) k_norm_small_tiers_batched(const NormTable* __restrict__ tab) {
-    const NormTable& t = tab[blockIdx.x];
-    int l0 = 1;
-    while (l0 <= t.L && t.m[l0] > kSmallTier) ++l0;
-    for (int l = l0; l <= t.L; ++l) {
-        const double* S = t.norms + t.off[l - 1];
-        double* P = t.norms + t.off[l];
-        const int m = t.m[l - 1], mp = t.m[l];
-        for (int i = threadIdx.x; i < mp * mp; i += blockDim.x) {
-            const int I = i / mp, K = i % mp;
-            double c[4];
+// The small tiers l0 .. L of one pyramid in one block, tier by tier.  Only
+// the first tier reads its children from global memory; every tier is kept
+// in LDS (two buffers in turn: tier l0 has at most kSmallTier^2 nodes, the
+// next a quarter of that) for the next one, and written to global memory
+// once, so the chain of tiers waits on LDS rather than on global round trips.
+// The sum of each node is the same 2 x 2 pairwise sum as everywhere else.
+constexpr int kSmallThreads = 1024;
+
+template <typename OFF, typename MM>
+__device__ void small_tiers(double* __restrict__ norms, const OFF& off, const MM& mm, int l0, int L, double* buf0,
+                            double* buf1) {
+    // tier l0 from global memory: every load of a thread is issued before
+    // its first store (the loads and stores share the pyramid, so the
+    // compiler would otherwise wait for each node's children in turn)
+    {
+        constexpr int U = kSmallTier * kSmallTier / kSmallThreads;
+        const double* S = norms + off[l0 - 1];
+        double* P = norms + off[l0];
+        const int m = mm[l0 - 1], mp = mm[l0];
+        double c[U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = threadIdx.x + u * kSmallThreads;
+            const int I = t / mp, K = t % mp;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = 2 * I + (q >> 1), k = 2 * K + (q & 1);
-                c[q] = (r < m && k < m) ? S[(int64_t)r * m + k] : 0.0;
+                const int i = 2 * I + (q >> 1), k = 2 * K + (q & 1);
+                c[u][q] = (t < mp * mp && i < m && k < m) ? S[(int64_t)i * m + k] : 0.0;
             }
-            P[i] = (c[0] + c[1]) + (c[2] + c[3]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = threadIdx.x + u * kSmallThreads;
+            if (t < mp * mp) {
+                const double v = (c[u][0] + c[u][1]) + (c[u][2] + c[u][3]);
+                buf0[t] = v;
+                P[t] = v;
+            }
         }
         __syncthreads();
     }
-}
-
-// The small upper tiers in one block, tier by tier.
-__global__ void __launch_bounds__(1024) k_norm_small_tiers(double* __restrict__ norms, const int64_t* off,
-                                                           const int* mm, int l0, int L, const int* active) {
-    if (active && *active == 0) return;
-    for (int l = l0; l <= L; ++l) {
-        const double* S = norms + off[l - 1];
+    const double* src = buf0;
+    for (int l = l0 + 1; l <= L; ++l) {
+        double* dst = ((l - l0) & 1) ? buf1 : buf0;
         double* P = norms + off[l];
         const int m = mm[l - 1], mp = mm[l];
         for (int t = threadIdx.x; t < mp * mp; t += blockDim.x) {
@@ -219,12 +234,32 @@ __global__ void __launch_bounds__(1024) k_norm_small_tiers(double* __restrict__ 
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int i = 2 * I + (q >> 1), k = 2 * K + (q & 1);
-                c[q] = (i < m && k < m) ? S[(int64_t)i * m + k] : 0.0;
+                c[q] = (i < m && k < m) ? src[(int64_t)i * m + k] : 0.0;
             }
-            P[t] = (c[0] + c[1]) + (c[2] + c[3]);
+            const double v = (c[0] + c[1]) + (c[2] + c[3]);
+            dst[t] = v;
+            P[t] = v;
         }
         __syncthreads();
+        src = dst;
     }
+}
+
+// Batch, the small tiers of matrix blockIdx.x in one block.
+__global__ void __launch_bounds__(kSmallThreads) k_norm_small_tiers_batched(const NormTable* __restrict__ tab) {
+    __shared__ double buf0[kSmallTier * kSmallTier], buf1[kSmallTier * kSmallTier / 4];
+    const NormTable& t = tab[blockIdx.x];
+    int l0 = 1;
+    while (l0 <= t.L && t.m[l0] > kSmallTier) ++l0;
+    if (l0 <= t.L) small_tiers(t.norms, t.off, t.m, l0, t.L, buf0, buf1);
+}
+
+// The small upper tiers of one pyramid in one block.
+__global__ void __launch_bounds__(kSmallThreads) k_norm_small_tiers(double* __restrict__ norms, const int64_t* off,
+                                                           const int* mm, int l0, int L, const int* active) {
+    if (active && *active == 0) return;
+    __shared__ double buf0[kSmallTier * kSmallTier], buf1[kSmallTier * kSmallTier / 4];
+    small_tiers(norms, off, mm, l0, L, buf0, buf1);
 }
 
 template <typename T>
@@ -366,7 +401,7 @@ hipError_t launch_upper_norms(spamm_matrix* M, hipStream_t s, const int* active)
         // kept at the end of the pyramid allocation
         int64_t* off = reinterpret_cast<int64_t*>(M->norms + M->norms_total);
         int* mm = reinterpret_cast<int*>(off + kMaxLevels);
-        hipLaunchKernelGGL(k_norm_small_tiers, dim3(1), dim3(1024), 0, s, M->norms, off, mm, l, M->L, active);
+        hipLaunchKernelGGL(k_norm_small_tiers, dim3(1), dim3(kSmallThreads), 0, s, M->norms, off, mm, l, M->L, active);
     }
     return hipGetLastError();
 }
@@ -398,7 +433,7 @@ hipError_t launch_upper_norms_batched(spamm_matrix* const* M, int count, const N
         hipLaunchKernelGGL(k_norm_parent_batched, dim3((unsigned)((cells + 255) / 256), (unsigned)count), dim3(256), 0,
                            s, d_tab, l);
     }
-    hipLaunchKernelGGL(k_norm_small_tiers_batched, dim3((unsigned)count), dim3(1024), 0, s, d_tab);
+    hipLaunchKernelGGL(k_norm_small_tiers_batched, dim3((unsigned)count), dim3(kSmallThreads), 0, s, d_tab);
     return hipGetLastError();
 }
 
