@@ -143,10 +143,23 @@ spamm_status alloc_storage(spamm_matrix* M, hipStream_t s) {
     return SPAMM_OK;
 }
 
+}  // namespace
+
+spamm_status ensure_tiers(const spamm_matrix* Mc, hipStream_t s, const int* active) {
+    auto* M = const_cast<spamm_matrix*>(Mc);  // the upper tiers are a cache of the leaf norms
+    if (M->tiers_valid) return SPAMM_OK;
+    SPAMM_HIP(launch_upper_norms(M, s, active));
+    M->tiers_valid = true;
+    return SPAMM_OK;
+}
+
+namespace {
+
 // The squared Frobenius norm of the whole matrix (the root of its pyramid)
 // is finite iff every element is: x*x of an inf or NaN is inf or NaN, and
 // FP64 sums of FP32 squares cannot overflow.  Call after the stream syncs.
-spamm_status check_finite(const spamm_matrix* M, const char* what) {
+spamm_status check_finite(const spamm_matrix* M, hipStream_t s, const char* what) {
+    SPAMM_HIP(hipStreamSynchronize(s));
     double root = 0.0;
     SPAMM_HIP(hipMemcpy(&root, M->norms + M->lvl_off[M->L], sizeof root, hipMemcpyDeviceToHost));
     if (!std::isfinite(root)) return set_error(SPAMM_ENONFINITE, std::string("non-finite value in ") + what);
@@ -329,6 +342,12 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
             cp.leaf_nb = C->nb;
         }
     }
+    if (!cp.leaf_direct) {
+        // the descent reads the operands' upper tiers
+        spamm_status r = ensure_tiers(A, s, d_active);
+        if (r == SPAMM_OK && B != A) r = ensure_tiers(B, s, d_active);
+        if (r != SPAMM_OK) return r;
+    }
     int64_t items[kMaxLevels];
     tier_items(C, ps->front_cap, items);
     if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[0], s));
@@ -352,7 +371,8 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
     if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[1], s));
     SPAMM_HIP(launch_leaf_typed(d_desc, lp, A->dt == SPAMM_F64, s));
     if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[2], s));
-    SPAMM_HIP(launch_upper_norms(C, s, d_active));
+    // the leaf epilogue wrote C's leaf norms; its upper tiers follow on demand
+    C->tiers_valid = false;
     if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[3], s));
     return SPAMM_OK;
 }
@@ -425,7 +445,7 @@ spamm_status build_single(const void* dev_a, int64_t n, int64_t lda, spamm_dtype
     M->last_stream = s;
     M->gen++;
     hipError_t e = launch_pack_norm(dev_a, n, lda, dt, M, kind, s);
-    if (e == hipSuccess) e = launch_upper_norms(M, s, nullptr);
+    M->tiers_valid = false;  // formed when read
     if (e != hipSuccess) {
         st = hip_error(e, "spamm_build kernels");
         if (fresh) release(M);
@@ -511,6 +531,7 @@ spamm_status build_batched(int32_t count, const void* const* dev_a, const int64_
     if (e == hipSuccess) e = hipMemcpyAsync(ws + o_tab, ht.data(), sizeof(NormTable) * count, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_pack_norm_batched(d_pd, count, waves, dt, leaf, s);
     if (e == hipSuccess) e = launch_upper_norms_batched(M.data(), count, d_tab, s);
+    for (int m = 0; m < count; ++m) M[m]->tiers_valid = e == hipSuccess;
     dev_free(M[0], ws, s);
     if (e != hipSuccess) {
         st = hip_error(e, "spamm_build_batched kernels");
@@ -600,8 +621,10 @@ spamm_status spamm_multiply_ex(const spamm_matrix* A, const spamm_matrix* B, dou
     *C = Cm;
     if (st) {
         r = read_stats(Cm, s, st, tau);
-        if (r == SPAMM_OK) r = check_finite(A, "operand A");
-        if (r == SPAMM_OK) r = check_finite(B, "operand B");
+        if (r == SPAMM_OK) r = ensure_tiers(A, s);
+        if (r == SPAMM_OK) r = ensure_tiers(B, s);
+        if (r == SPAMM_OK) r = check_finite(A, s, "operand A");
+        if (r == SPAMM_OK) r = check_finite(B, s, "operand B");
         return r;
     }
     return SPAMM_OK;
@@ -657,9 +680,11 @@ spamm_status spamm_norms(const spamm_matrix* M, int32_t level, double* host_out,
     const int64_t m = M->lvl_m[level];
     if (cap < m * m) return set_error(SPAMM_EINVAL, "host buffer too small");
     hipStream_t s = (hipStream_t)stream;
+    spamm_status r = ensure_tiers(M, s);
+    if (r != SPAMM_OK) return r;
     SPAMM_HIP(hipStreamSynchronize(s));
     SPAMM_HIP(hipMemcpy(host_out, M->norms + M->lvl_off[level], sizeof(double) * m * m, hipMemcpyDeviceToHost));
-    return check_finite(M, "the matrix");
+    return check_finite(M, s, "the matrix");
 }
 
 spamm_status spamm_task_list(const spamm_matrix* C, uint64_t* host_keys, int64_t cap, int64_t* count,
@@ -841,6 +866,16 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
         lp.list = (uint32_t*)(ws + o_ord);  // the order array holds the list
         lp.list_count = (unsigned*)(ws + o_q);
     }
+    // the descent reads the operands' upper tiers
+    for (int m = 0; m < count && r == SPAMM_OK; ++m) {
+        r = ensure_tiers(A[m], s);
+        if (r == SPAMM_OK) r = ensure_tiers(B[m], s);
+    }
+    if (r != SPAMM_OK) {
+        dev_free(owner, ws, s);
+        release_fresh();
+        return r;
+    }
     static thread_local std::vector<NormTable> htab;
     htab.resize(count);
     for (int m = 0; m < count; ++m) htab[m] = norm_table(out[m]);
@@ -858,6 +893,7 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
         e = launch_tile_list(d_desc, count, total, (uint32_t*)(ws + o_ord), (unsigned*)(ws + o_q), s);
     if (e == hipSuccess) e = launch_leaf_typed(d_desc, lp, A[0]->dt == SPAMM_F64, s);
     if (e == hipSuccess) e = launch_upper_norms_batched(out.data(), count, d_tab, s);
+    for (int m = 0; m < count; ++m) out[m]->tiers_valid = e == hipSuccess;
     if (e == hipSuccess && st) {
         static thread_local DevCounters h;
         unsigned long long ne[kMaxBatch];
@@ -880,8 +916,8 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
         }
         if (e == hipSuccess && (h.status & kDevCapacity)) r = set_error(SPAMM_ECAPACITY, "frontier capacity exceeded");
         for (int m = 0; m < count && e == hipSuccess && r == SPAMM_OK; ++m) {
-            r = check_finite(A[m], "an operand A[m]");
-            if (r == SPAMM_OK) r = check_finite(B[m], "an operand B[m]");
+            r = check_finite(A[m], s, "an operand A[m]");
+            if (r == SPAMM_OK) r = check_finite(B[m], s, "an operand B[m]");
         }
     }
     dev_free(owner, ws, s);
@@ -1062,6 +1098,9 @@ spamm_status spamm_sp2_ex(const spamm_matrix* H, int64_t n_occ, double tau, int3
     cs = nullptr;
     dev_free(owner, scratch, s);
     scratch = nullptr;
+    // the steps after convergence were skipped on the device, so the tier
+    // state recorded while capturing may not hold: form P's tiers afresh
+    X[res]->tiers_valid = false;
     *P = X[res];
     X[res] = nullptr;
     cleanup();

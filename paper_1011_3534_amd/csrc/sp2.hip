@@ -404,8 +404,7 @@ hipError_t launch_sp2_init(const spamm_matrix* H, spamm_matrix* X, double* part,
             break;
         default: return hipErrorInvalidValue;
     }
-    hipError_t e = launch_upper_norms(X, s, nullptr);
-    if (e != hipSuccess) return e;
+    X->tiers_valid = false;  // X_0's upper tiers are formed if a product reads them
     hipLaunchKernelGGL(k_sp2_start, dim3(1), dim3(1024), 0, s, part, X->nb, st);
     return hipGetLastError();
 }

@@ -149,6 +149,7 @@ struct spamm_matrix {
     bool view = false;           // tiles borrow the caller's row-major array (not owned)
     int64_t ld = 0;              // a view's row stride (elements)
     double* norms = nullptr;
+    bool tiers_valid = false;    // tiers above the leaves match the leaf norms (formed on demand)
     int8_t* texp = nullptr;
     uint16_t* split = nullptr;   // split 16-bit tiles (hi, then lo), made on demand
     int split_kind = -1;         // kSplitF16 / kSplitBF16 of the current split
@@ -205,6 +206,10 @@ inline TileGeo tile_geo(const spamm_matrix* M) {
 hipError_t launch_pack_norm(const void* a, int64_t n, int64_t lda, spamm_dtype dt, spamm_matrix* M,
                             int split_kind, hipStream_t s);
 hipError_t launch_upper_norms(spamm_matrix* M, hipStream_t s, const int* active);
+// The tiers above the leaves are formed when something reads them: builds
+// and single products write the leaf norms only, and ensure_tiers enqueues
+// the upper tiers of M on s (a no-op when they are current).
+spamm_status ensure_tiers(const spamm_matrix* M, hipStream_t s, const int* active = nullptr);
 
 // Batched builds and result pyramids (norms.hip).
 struct PackDesc {

@@ -286,6 +286,9 @@ spamm_status spamm_tau_features(const spamm_matrix* A, const spamm_matrix* B, do
     if (A->n != B->n || A->b != B->b) return set_error(SPAMM_EINVAL, "operands differ in n or leaf size");
     if (!(target > 0.0) || !std::isfinite(target)) return set_error(SPAMM_EINVAL, "target must be > 0");
     hipStream_t s = (hipStream_t)stream;
+    spamm_status r = ensure_tiers(A, s);
+    if (r == SPAMM_OK && B != A) r = ensure_tiers(B, s);
+    if (r != SPAMM_OK) return r;
     const int64_t* off = reinterpret_cast<const int64_t*>(A->norms + A->norms_total);
     const int* mm = reinterpret_cast<const int*>(off + kMaxLevels);
     hipLaunchKernelGGL(k_tau_hist, dim3(2 * kTiers), dim3(256), 0, s, A->norms, B->norms, off, mm, A->L, dev_out);
@@ -416,6 +419,8 @@ spamm_status spamm_tau_select(const spamm_matrix* A, const spamm_matrix* B, doub
     } else {
         // no model: start one decade above target * ||A||_F ||B||_F
         double ra = 0.0, rb = 0.0;
+        if ((r = ensure_tiers(A, (hipStream_t)stream)) != SPAMM_OK) return r;
+        if ((r = ensure_tiers(B, (hipStream_t)stream)) != SPAMM_OK) return r;
         SPAMM_HIP(hipStreamSynchronize((hipStream_t)stream));
         SPAMM_HIP(hipMemcpy(&ra, A->norms + A->lvl_off[A->L], 8, hipMemcpyDeviceToHost));
         SPAMM_HIP(hipMemcpy(&rb, B->norms + B->lvl_off[B->L], 8, hipMemcpyDeviceToHost));
