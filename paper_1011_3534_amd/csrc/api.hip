@@ -340,6 +340,13 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
         if (C->nb * C->nb * C->nb <= ((int64_t)1 << 27)) {
             cp.leaf_direct = 1;
             cp.leaf_nb = C->nb;
+            if (sp2_list) {
+                // an SP2 step: the pass also lists the tiles to write, and
+                // the step's finalize leaves the counters at zero
+                cp.sp2_list = sp2_list;
+                cp.sp2_state = sp2_state;
+                cp.skip_prep = true;
+            }
         }
     }
     if (!cp.leaf_direct) {
@@ -364,7 +371,7 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
     lp.presplit = presplit;
     if (sp2_list) {
         // SP2: the leaf launch visits only the C tiles that need a write
-        SPAMM_HIP(launch_sp2_tiles(d_desc, C->nb, sp2_list, sp2_state, d_active, s));
+        if (!cp.sp2_list) SPAMM_HIP(launch_sp2_tiles(d_desc, C->nb, sp2_list, sp2_state, d_active, s));
         lp.list = sp2_list;
         lp.list_count = &sp2_state->list_count;
     }
@@ -1036,6 +1043,8 @@ spamm_status spamm_sp2_ex(const spamm_matrix* H, int64_t n_occ, double tau, int3
         dst->ps->desc_valid = false;  // differs from any plain product's descriptor
         e = hipMemcpyAsync(dst->ps->desc, &dst->ps->host_desc, sizeof d, hipMemcpyHostToDevice, s);
     }
+    // product counters start at zero; each step's finalize leaves them so
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMemsetAsync(X[i]->ps->ctr, 0, sizeof(DevCounters), s);
     if (e != hipSuccess) return fail(e, "spamm_sp2 setup");
     if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return fail(e, "hipStreamCreate");
     if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)

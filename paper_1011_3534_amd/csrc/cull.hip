@@ -271,41 +271,75 @@ __global__ void __launch_bounds__(kCullThreads)
 // The leaf tier of a single product straight from the flat rule, without
 // the tiers above (every ancestor of a passing triple passes, see
 // enum_keep): bit K of C tile (I, J) is set iff
-// !(S_A[I,K] * S_B[K,J] < tau^2).  Block (I, y, w) forms mask word w of the
-// tiles (I, 64y + j): lane j of wave q tests the 16 K of quarter q, reading
-// row K of S_B coalesced across the lanes (S_A[I,K] is one value per
-// wave); the quarters are OR-ed in LDS and the word is stored once, so
-// every mask word is written (no clearing, no atomics per triple) and the
-// kept K of a tile stay in ascending order.
+// !(S_A[I,K] * S_B[K,J] < tau^2).  Block (I, y) forms every mask word of
+// the tiles (I, 64y + j): for word w, lane j of wave q tests the 16 K of
+// quarter q, reading row K of S_B coalesced across the lanes (S_A[I,K] is
+// one value per wave); the quarters are OR-ed in LDS and the word is stored
+// once, so every mask word is written (no clearing, no atomics per triple)
+// and the kept K of a tile stay in ascending order.
+//
+// SP2 (list != NULL): with all of a tile's words at hand the block also
+// decides whether the step writes the tile (kept products, or X_m or the
+// previous result nonzero there; for symmetric squarings tiles below the
+// diagonal are written by their mirrors), gives the others zero SP2
+// partials and appends the rest to the step's tile list.
 constexpr int kLeafQuarters = 4;
 __global__ void __launch_bounds__(kLeafQuarters * kWave)
-    k_cull_leaf(const ProdDesc* __restrict__ desc, DevCounters* __restrict__ ctr, const int* __restrict__ active) {
+    k_cull_leaf(const ProdDesc* __restrict__ desc, DevCounters* __restrict__ ctr, uint32_t* __restrict__ list,
+                Sp2State* __restrict__ st, const int* __restrict__ active) {
     if (active && *active == 0) return;
     const ProdDesc& d = desc[0];
     const int nb = d.nb, W = d.W;
     const int lane = threadIdx.x & (kWave - 1);
     const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int I = blockIdx.x, J = blockIdx.y * kWave + lane, w = blockIdx.z;
+    const int I = blockIdx.x, J = blockIdx.y * kWave + lane;
     constexpr int KQ = 64 / kLeafQuarters;
-    const int k0 = w * 64 + q * KQ, kn = min(KQ, nb - k0);  // kn <= 0: quarter past the last K
-    unsigned long long bits = 0;
-    if (J < nb && kn > 0 && !(d.sym_upper && I > J)) {
-        const double* SA = d.SA + d.lvl_off[0] + (int64_t)I * nb + k0;
-        const double* SB = d.SB + d.lvl_off[0] + (int64_t)k0 * nb + J;
-        const double t2 = d.tau2;
-#pragma unroll 8
-        for (int k = 0; k < kn; ++k) bits |= (unsigned long long)!(SA[k] * SB[(int64_t)k * nb] < t2) << k;
-        bits <<= q * KQ;
-    }
+    const bool live = J < nb && !(d.sym_upper && I > J);
+    const double t2 = d.tau2;
     __shared__ unsigned long long s_bits[kLeafQuarters][kWave];
-    s_bits[q][lane] = bits;
-    __syncthreads();
+    unsigned long long kept = 0, any = 0;
+    for (int w = 0; w < W; ++w) {
+        const int k0 = w * 64 + q * KQ, kn = min(KQ, nb - k0);  // kn <= 0: quarter past the last K
+        unsigned long long bits = 0;
+        if (live && kn > 0) {
+            const double* SA = d.SA + d.lvl_off[0] + (int64_t)I * nb + k0;
+            const double* SB = d.SB + d.lvl_off[0] + (int64_t)k0 * nb + J;
+#pragma unroll 8
+            for (int k = 0; k < kn; ++k) bits |= (unsigned long long)!(SA[k] * SB[(int64_t)k * nb] < t2) << k;
+            bits <<= q * KQ;
+        }
+        s_bits[q][lane] = bits;
+        __syncthreads();
+        if (q == 0) {
+            for (int r = 1; r < kLeafQuarters; ++r) bits |= s_bits[r][lane];
+            if (J < nb) d.mask[((int64_t)I * nb + J) * W + w] = bits;
+            kept += (unsigned long long)__popcll(bits);
+            any |= bits;
+        }
+        __syncthreads();
+    }
     if (q != 0) return;
-    for (int r = 1; r < kLeafQuarters; ++r) bits |= s_bits[r][lane];
-    if (J < nb) d.mask[((int64_t)I * nb + J) * W + w] = bits;
     // kept triples (the product's task count): one atomic per block
-    const unsigned long long c = wave_sum_u64((unsigned long long)__popcll(bits));
+    const unsigned long long c = wave_sum_u64(kept);
     if (lane == 0 && c) atomicAdd(&ctr->survivors[0][0], c);
+    if (!list) return;
+    const int64_t tiles = (int64_t)nb * nb, t = (int64_t)I * nb + J;
+    bool need = false;
+    if (live) {
+        const int64_t mirror = (int64_t)J * nb + I;
+        need = any != 0 || d.SA[t] != 0.0 || d.eC[t] != -128 || (d.sym_upper && I < J && d.eC[mirror] != -128);
+        if (!need) {
+            d.sp2_part[t] = 0.0;
+            if (I == J) d.sp2_part[tiles + I] = 0.0;
+            if (d.sym_upper && I < J) d.sp2_part[mirror] = 0.0;
+        }
+    }
+    const unsigned long long m = __ballot(need);
+    if (m == 0) return;
+    unsigned base = 0;
+    if (lane == 0) base = atomicAdd(&st->list_count, (unsigned)__popcll(m));
+    base = (unsigned)__shfl((int)base, 0, kWave);
+    if (need) list[base + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)t;
 }
 
 // Counters, per-product non-empty tile counts and (single product) the leaf
@@ -356,7 +390,7 @@ __global__ void k_task_keys(const ProdDesc* __restrict__ desc, int64_t nb, int W
 hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t* mask, uint64_t* front0,
                           uint64_t* front1, DevCounters* ctr, int want_bound, const int* active,
                           const int64_t* tier_items, hipStream_t s) {
-    {
+    if (!plan.skip_prep) {
         // (a batch clears its masks with launch_clear_masks; the direct leaf
         // pass writes every word)
         const int64_t words = mask && !plan.leaf_direct ? plan.mask_words : 0;
@@ -369,8 +403,8 @@ hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t
     int l = top;
     if (plan.leaf_direct) {
         const unsigned nb = (unsigned)plan.leaf_nb;
-        hipLaunchKernelGGL(k_cull_leaf, dim3(nb, (nb + kWave - 1) / kWave, (nb + 63) / 64), dim3(kLeafQuarters * kWave),
-                           0, s, d_desc, ctr, active);
+        hipLaunchKernelGGL(k_cull_leaf, dim3(nb, (nb + kWave - 1) / kWave), dim3(kLeafQuarters * kWave), 0, s, d_desc,
+                           ctr, plan.sp2_list, plan.sp2_state, active);
         return hipGetLastError();
     }
     if (plan.flat_start >= 1) {

@@ -211,7 +211,7 @@ __device__ double block_tree_sum(double v, double* red) {
 }
 
 __global__ void __launch_bounds__(kFinThreads) k_sp2_finalize(const double* part, int64_t nb,
-                                                              const unsigned long long* survivors0, Sp2State* st,
+                                                              unsigned long long* survivors0, Sp2State* st,
                                                               int m, double* bsum, unsigned* ticket) {
     if (st->active == 0) return;  // read by every block before the last one writes it
     __shared__ double red[kFinThreads];
@@ -242,6 +242,7 @@ __global__ void __launch_bounds__(kFinThreads) k_sp2_finalize(const double* part
     st->idem[m] = e;
     st->br[m] = st->branch;
     st->tasks[m] = *survivors0;
+    *survivors0 = 0;  // the next step's cull counts afresh (it may run without a zeroing launch)
     st->iter = m + 1;
     st->list_count = 0;  // the next step lists its tiles afresh
     if (e <= st->tol) {
@@ -409,7 +410,7 @@ hipError_t launch_sp2_init(const spamm_matrix* H, spamm_matrix* X, double* part,
     return hipGetLastError();
 }
 
-hipError_t launch_sp2_finalize(const double* part, int64_t nb, const unsigned long long* survivors0, Sp2State* st,
+hipError_t launch_sp2_finalize(const double* part, int64_t nb, unsigned long long* survivors0, Sp2State* st,
                                int m, hipStream_t s) {
     hipLaunchKernelGGL(k_sp2_finalize, dim3(kFinBlocks), dim3(kFinThreads), 0, s, part, nb, survivors0, st, m,
                        st->fin_bsum, &st->fin_ticket);

@@ -240,6 +240,7 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s
 hipError_t launch_split(const spamm_matrix* M, int kind, const int* active, hipStream_t s);
 
 // launchers (cull.hip) ----------------------------------------------------------
+struct Sp2State;
 struct CullPlan {
     int count;              // products in the batch
     int Lmax;               // highest tier among the products
@@ -250,6 +251,9 @@ struct CullPlan {
     int flat_m = 0;         //   its size m; the tiers above it are not visited (nor counted)
     int leaf_direct = 0;    // single product, flat threshold: test every leaf triple, no tiers visited
     int64_t leaf_nb = 0;    //   (nb of the product; the leaf tier's kept count is still counted)
+    uint32_t* sp2_list = nullptr;   // direct leaf pass of an SP2 step: also list the C tiles to write
+    Sp2State* sp2_state = nullptr;  //   (and their count); the counters are kept at zero by the step
+    bool skip_prep = false;         //   finalize, so no zeroing launch precedes the pass
 };
 hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t* mask, uint64_t* front0,
                           uint64_t* front1, DevCounters* ctr, int want_bound, const int* active,
@@ -302,7 +306,7 @@ struct Sp2State {
 };
 hipError_t launch_gershgorin(const spamm_matrix* H, double* lo, double* hi, Sp2State* st, hipStream_t s);
 hipError_t launch_sp2_init(const spamm_matrix* H, spamm_matrix* X, double* part, Sp2State* st, hipStream_t s);
-hipError_t launch_sp2_finalize(const double* part, int64_t nb, const unsigned long long* survivors0, Sp2State* st,
+hipError_t launch_sp2_finalize(const double* part, int64_t nb, unsigned long long* survivors0, Sp2State* st,
                                int m, hipStream_t s);
 hipError_t launch_energy(const spamm_matrix* P, const spamm_matrix* H, double* tile_part, double* out,
                          hipStream_t s);
