@@ -272,11 +272,12 @@ __global__ void __launch_bounds__(kCullThreads)
 // the tiers above (every ancestor of a passing triple passes, see
 // enum_keep): bit K of C tile (I, J) is set iff
 // !(S_A[I,K] * S_B[K,J] < tau^2).  Block (I, y) forms every mask word of
-// the tiles (I, 64y + j): for word w, lane j of wave q tests the 16 K of
-// quarter q, reading row K of S_B coalesced across the lanes (S_A[I,K] is
-// one value per wave); the quarters are OR-ed in LDS and the word is stored
-// once, so every mask word is written (no clearing, no atomics per triple)
-// and the kept K of a tile stay in ascending order.
+// the tiles (I, 64y + j) with up to four words at a time: wave (v, q) of
+// the block takes quarter q (16 K) of word v of the group, lane j testing
+// tile (I, 64y + j) and reading row K of S_B coalesced across the lanes
+// (S_A[I,K] is one value per wave).  The quarters are OR-ed in LDS and each
+// word is stored once, so every mask word is written (no clearing, no
+// atomics per triple) and the kept K of a tile stay in ascending order.
 //
 // SP2 (list != NULL): with all of a tile's words at hand the block also
 // decides whether the step writes the tile (kept products, or X_m or the
@@ -284,41 +285,55 @@ __global__ void __launch_bounds__(kCullThreads)
 // diagonal are written by their mirrors), gives the others zero SP2
 // partials and appends the rest to the step's tile list.
 constexpr int kLeafQuarters = 4;
-__global__ void __launch_bounds__(kLeafQuarters * kWave)
+constexpr int kLeafWords = 4;  // words per group (block of kLeafWords x kLeafQuarters waves)
+__global__ void __launch_bounds__(kLeafWords * kLeafQuarters * kWave)
     k_cull_leaf(const ProdDesc* __restrict__ desc, DevCounters* __restrict__ ctr, uint32_t* __restrict__ list,
                 Sp2State* __restrict__ st, const int* __restrict__ active) {
     if (active && *active == 0) return;
     const ProdDesc& d = desc[0];
     const int nb = d.nb, W = d.W;
     const int lane = threadIdx.x & (kWave - 1);
-    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int q = wid % kLeafQuarters, v = wid / kLeafQuarters;
+    const int group = (int)(blockDim.x / (kLeafQuarters * kWave));  // words per group: min(W, kLeafWords)
     const int I = blockIdx.x, J = blockIdx.y * kWave + lane;
     constexpr int KQ = 64 / kLeafQuarters;
     const bool live = J < nb && !(d.sym_upper && I > J);
     const double t2 = d.tau2;
-    __shared__ unsigned long long s_bits[kLeafQuarters][kWave];
-    unsigned long long kept = 0, any = 0;
-    for (int w = 0; w < W; ++w) {
+    __shared__ unsigned long long s_bits[kLeafWords * kLeafQuarters][kWave];
+    __shared__ unsigned long long s_any[kLeafWords][kWave], s_kept[kLeafWords][kWave];
+    unsigned long long kept = 0, any = 0;  // (waves q == 0: over their words)
+    for (int w0 = 0; w0 < W; w0 += group) {
+        const int w = w0 + v;
         const int k0 = w * 64 + q * KQ, kn = min(KQ, nb - k0);  // kn <= 0: quarter past the last K
         unsigned long long bits = 0;
-        if (live && kn > 0) {
+        if (live && w < W && kn > 0) {
             const double* SA = d.SA + d.lvl_off[0] + (int64_t)I * nb + k0;
             const double* SB = d.SB + d.lvl_off[0] + (int64_t)k0 * nb + J;
 #pragma unroll 8
             for (int k = 0; k < kn; ++k) bits |= (unsigned long long)!(SA[k] * SB[(int64_t)k * nb] < t2) << k;
             bits <<= q * KQ;
         }
-        s_bits[q][lane] = bits;
+        s_bits[wid][lane] = bits;
         __syncthreads();
-        if (q == 0) {
-            for (int r = 1; r < kLeafQuarters; ++r) bits |= s_bits[r][lane];
+        if (q == 0 && w < W) {
+            for (int r = 1; r < kLeafQuarters; ++r) bits |= s_bits[wid + r][lane];
             if (J < nb) d.mask[((int64_t)I * nb + J) * W + w] = bits;
             kept += (unsigned long long)__popcll(bits);
             any |= bits;
         }
         __syncthreads();
     }
-    if (q != 0) return;
+    if (q == 0) {
+        s_any[v][lane] = any;
+        s_kept[v][lane] = kept;
+    }
+    __syncthreads();
+    if (wid != 0) return;
+    for (int r = 1; r < group; ++r) {
+        any |= s_any[r][lane];
+        kept += s_kept[r][lane];
+    }
     // kept triples (the product's task count): one atomic per block
     const unsigned long long c = wave_sum_u64(kept);
     if (lane == 0 && c) atomicAdd(&ctr->survivors[0][0], c);
@@ -403,8 +418,9 @@ hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t
     int l = top;
     if (plan.leaf_direct) {
         const unsigned nb = (unsigned)plan.leaf_nb;
-        hipLaunchKernelGGL(k_cull_leaf, dim3(nb, (nb + kWave - 1) / kWave), dim3(kLeafQuarters * kWave), 0, s, d_desc,
-                           ctr, plan.sp2_list, plan.sp2_state, active);
+        const unsigned W = (nb + 63) / 64, group = W < (unsigned)kLeafWords ? W : (unsigned)kLeafWords;
+        hipLaunchKernelGGL(k_cull_leaf, dim3(nb, (nb + kWave - 1) / kWave), dim3(group * kLeafQuarters * kWave), 0, s,
+                           d_desc, ctr, plan.sp2_list, plan.sp2_state, active);
         return hipGetLastError();
     }
     if (plan.flat_start >= 1) {
