@@ -346,6 +346,11 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
                 cp.sp2_list = sp2_list;
                 cp.sp2_state = sp2_state;
                 cp.skip_prep = true;
+            } else if (!sp2) {
+                // a product without statistics: its counters are read by
+                // nothing (statistics take the full descent, which zeroes them)
+                cp.skip_prep = true;
+                cp.uncounted = true;
             }
         }
     }

@@ -334,9 +334,12 @@ __global__ void __launch_bounds__(kLeafWords * kLeafQuarters * kWave)
         any |= s_any[r][lane];
         kept += s_kept[r][lane];
     }
-    // kept triples (the product's task count): one atomic per block
-    const unsigned long long c = wave_sum_u64(kept);
-    if (lane == 0 && c) atomicAdd(&ctr->survivors[0][0], c);
+    // kept triples (the product's task count, when someone reads it): one
+    // atomic per block
+    if (ctr) {
+        const unsigned long long c = wave_sum_u64(kept);
+        if (lane == 0 && c) atomicAdd(&ctr->survivors[0][0], c);
+    }
     if (!list) return;
     const int64_t tiles = (int64_t)nb * nb, t = (int64_t)I * nb + J;
     bool need = false;
@@ -420,7 +423,7 @@ hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t
         const unsigned nb = (unsigned)plan.leaf_nb;
         const unsigned W = (nb + 63) / 64, group = W < (unsigned)kLeafWords ? W : (unsigned)kLeafWords;
         hipLaunchKernelGGL(k_cull_leaf, dim3(nb, (nb + kWave - 1) / kWave), dim3(group * kLeafQuarters * kWave), 0, s,
-                           d_desc, ctr, plan.sp2_list, plan.sp2_state, active);
+                           d_desc, plan.uncounted ? nullptr : ctr, plan.sp2_list, plan.sp2_state, active);
         return hipGetLastError();
     }
     if (plan.flat_start >= 1) {

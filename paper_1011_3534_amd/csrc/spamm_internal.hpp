@@ -254,6 +254,7 @@ struct CullPlan {
     uint32_t* sp2_list = nullptr;   // direct leaf pass of an SP2 step: also list the C tiles to write
     Sp2State* sp2_state = nullptr;  //   (and their count); the counters are kept at zero by the step
     bool skip_prep = false;         //   finalize, so no zeroing launch precedes the pass
+    bool uncounted = false;         // direct leaf pass whose counters nobody reads (no zeroing, no counts)
 };
 hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t* mask, uint64_t* front0,
                           uint64_t* front1, DevCounters* ctr, int want_bound, const int* active,
