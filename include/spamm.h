@@ -124,9 +124,12 @@ typedef struct {
  *           (I, K) row-major order) and the FP64 squared-norm pyramid of all
  *           tiers.  If *out is a handle of the same n, leaf and dtype it is
  *           rebuilt in place (no allocation).
- * One pass over dev_a computes the packed tiles and the leaf norms; the
- * upper tiers follow.  Errors: EINVAL (n < 1, lda < n, bad leaf/dtype, null
- * pointers), ENOMEM, EHIP. */
+ * One pass over dev_a computes the packed tiles and the leaf norms.  The
+ * tiers above the leaves are formed when a call first reads them (a product
+ * that descends the tiers, spamm_norms, the tau calls), on that call's
+ * stream; calls on one handle must be ordered (one stream, or events), as
+ * for every other use of it.  Errors: EINVAL (n < 1, lda < n, bad
+ * leaf/dtype, null pointers), ENOMEM, EHIP. */
 spamm_status spamm_build(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf,
                          void* stream, spamm_matrix** out);
 
@@ -202,7 +205,8 @@ spamm_status spamm_build_view_batched(int32_t count, const void* const* dev_a, c
  *           alias A or B.
  *   st    : optional; when non-NULL the call synchronises the stream and
  *           fills the statistics.
- * The result carries its own norm pyramid, so it can be an operand of the
+ * The result carries its own norm pyramid (leaf norms from the product,
+ * the tiers above formed when first read), so it can be an operand of the
  * next product.  Every C tile with no kept product is exactly zero.
  * Errors: EINVAL, ENOMEM, EHIP; with st, ENONFINITE when A or B holds an
  * inf or NaN (the product is still written) and ECAPACITY. */

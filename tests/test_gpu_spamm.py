@@ -425,3 +425,33 @@ def test_nonfinite_operand_is_reported(bad, view):
     good = to_dev(a)
     A2 = sp.build(good, b, out=A, view=view)
     assert np.all(np.isfinite(A2.norms(0)))
+
+
+@pytest.mark.parametrize("view", [False, True])
+def test_upper_tiers_formed_when_read(view):
+    """Builds and products without statistics write leaf norms only; the
+    tiers above are formed when something reads them.  A result of a
+    direct-leaf product (tiers not formed) feeds a product with statistics
+    (full descent, which reads every tier) and a depth-scaled product: both
+    equal the oracle run on the stored FP32 values, and every tier of each
+    handle equals the oracle's pyramid of its stored values."""
+    _case(f"lazy tiers view={view}")
+    n, b, tau = 1000, 32, 1e-5
+    a = si.algebraic_decay(n, 2.0, 47, np.float32) if not view else si.algebraic_decay(1024, 2.0, 47, np.float32)
+    n = a.shape[0]
+    A = sp.build(to_dev(a), b, view=view)
+    C = sp.multiply(A, A, tau, "f32")                      # direct leaf pass: no tier read or formed
+    c = C.to_dense().cpu().numpy().astype(np.float64)
+    D, st = sp.multiply(C, C, tau, "f32", stats=True)      # the descent forms C's tiers
+    ref, t_ref = oracle.spamm_flat(c, c, b, tau)
+    assert st["tasks"] == t_ref
+    assert np.all(np.abs(D.to_dense().cpu().numpy().astype(np.float64) - ref)
+                  <= elementwise_bound(c, c, b, tau, "f32"))
+    E = sp.multiply(C, C, 1e-3, "f32", depth_scaled=True)
+    refd, _, _, _ = oracle.spamm_recursive(c, c, b, 1e-3, depth_scaled=True)
+    assert np.all(np.abs(E.to_dense().cpu().numpy().astype(np.float64) - refd)
+                  <= elementwise_bound(c, c, b, 1e-3, "f32", depth_scaled=True))
+    for M, x in ((A, a.astype(np.float64)), (C, c), (D, D.to_dense().cpu().numpy().astype(np.float64))):
+        pyr = oracle.norm_pyramid(x, b)
+        for lv, S in enumerate(pyr):
+            assert np.array_equal(M.norms(lv), S), lv
