@@ -91,25 +91,46 @@ __global__ void k_scatter_order(const uint32_t* __restrict__ counts, int64_t tot
 // stored values not known to be zero (exponent -128 marks an all-zero tile,
 // whose norm is zero too).  The list order depends on the atomics; each
 // tile's result does not.
-__global__ void k_tile_list(const ProdDesc* __restrict__ desc, int nprod, int64_t total, uint32_t* __restrict__ list,
-                            unsigned* __restrict__ count) {
-    const int lane = threadIdx.x & 63;
+// The C tiles of a batch that need a write (a kept product, or stored
+// values not known to be zero), listed for the persistent leaf launch.  The
+// products' first global tiles sit in LDS for the per-lane search, and each
+// block reserves its part of the list with one atomic; the list order
+// depends on the atomics, each tile's result does not.
+__global__ void __launch_bounds__(256) k_tile_list(const ProdDesc* __restrict__ desc, int nprod, int64_t total,
+                                                   uint32_t* __restrict__ list, unsigned* __restrict__ count) {
+    __shared__ int64_t s_base[kMaxBatch];
+    __shared__ unsigned s_wave[4];
+    __shared__ unsigned s_block;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < nprod; i += blockDim.x) s_base[i] = desc[i].tile_base;
+    __syncthreads();
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t t = base + threadIdx.x;
         bool need = false;
         if (t < total) {
-            const ProdDesc& d = desc[product_of(desc, nprod, t)];
-            const int64_t local = t - d.tile_base;
+            int lo = 0, hi = nprod - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_base[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            const ProdDesc& d = desc[lo];
+            const int64_t local = t - s_base[lo];
             uint64_t any = 0;
             for (int i = 0; i < d.W; ++i) any |= d.mask[local * d.W + i];
             need = any != 0 || d.eC[local] != -128;
         }
         const unsigned long long m = __ballot(need);
-        if (m == 0) continue;
-        unsigned lbase = 0;
-        if (lane == 0) lbase = atomicAdd(count, (unsigned)__popcll(m));
-        lbase = (unsigned)__shfl((int)lbase, 0, 64);
-        if (need) list[lbase + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)t;
+        if (lane == 0) s_wave[wid] = (unsigned)__popcll(m);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned tot = (s_wave[0] + s_wave[1]) + (s_wave[2] + s_wave[3]);
+            s_block = tot ? atomicAdd(count, tot) : 0u;
+        }
+        __syncthreads();
+        unsigned off = s_block;
+        for (int w = 0; w < wid; ++w) off += s_wave[w];
+        if (need) list[off + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)t;
+        __syncthreads();  // s_wave and s_block are rewritten by the next chunk
     }
 }
 
