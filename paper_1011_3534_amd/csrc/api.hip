@@ -837,12 +837,24 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
         for (int l = 1; l < Cm->L; ++l) items[l] += (int64_t)Cm->lvl_m[l] * Cm->lvl_m[l] * Cm->lvl_m[l];
     }
     for (int l = 0; l < kMaxLevels; ++l) items[l] = std::min(items[l], cap);
+    // without statistics the flat rule needs no tier above the leaves: up to
+    // 2^27 leaf triples in all, every triple is tested in one pass
+    static thread_local std::vector<int64_t> hblk;
+    hblk.assign(count + 1, 0);
+    int64_t triples = 0;
+    for (int m = 0; m < count; ++m) {
+        const int64_t nbm = out[m]->nb;
+        triples += nbm * nbm * nbm;
+        hblk[m + 1] = hblk[m] + nbm * ceil_div(nbm, 64);
+    }
+    const bool direct = st == nullptr && triples <= ((int64_t)1 << 27);
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t o_desc = 0, o_f0 = al(sizeof(ProdDesc) * count), o_f1 = o_f0 + al((size_t)cap * 8),
                  o_ctr = o_f1 + al((size_t)cap * 8), o_cnt = o_ctr + al(sizeof(DevCounters) + 16 * kMaxBatch),
                  o_ord = o_cnt + al((size_t)total * 4), o_hist = o_ord + al((size_t)total * 4),
                  o_offs = o_hist + al((size_t)(maxc + 1) * 4), o_q = o_offs + al((size_t)(maxc + 1) * 4),
-                 o_tab = o_q + 256, bytes = o_tab + al(sizeof(NormTable) * count);
+                 o_tab = o_q + 256, o_blk = o_tab + al(sizeof(NormTable) * count),
+                 bytes = o_blk + al(sizeof(int64_t) * (count + 1));
     spamm_matrix* owner = out[0];
     char* ws = (char*)dev_alloc(owner, bytes, s);
     if (!ws) {
@@ -894,10 +906,17 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
     NormTable* d_tab = (NormTable*)(ws + o_tab);
     hipError_t e = hipMemcpyAsync(d_desc, hd.data(), sizeof(ProdDesc) * count, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_tab, htab.data(), sizeof(NormTable) * count, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_clear_masks(d_desc, count, s);
-    if (e == hipSuccess)
-        e = launch_cull_ex(d_desc, cp, nullptr, (uint64_t*)(ws + o_f0), (uint64_t*)(ws + o_f1), ctr, st != nullptr,
-                           nullptr, items, s);
+    if (direct) {
+        const int64_t* d_blk = (const int64_t*)(ws + o_blk);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ws + o_blk, hblk.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = launch_cull_leaf_batched(d_desc, count, d_blk, hblk[count], s);
+    } else {
+        if (e == hipSuccess) e = launch_clear_masks(d_desc, count, s);
+        if (e == hipSuccess)
+            e = launch_cull_ex(d_desc, cp, nullptr, (uint64_t*)(ws + o_f0), (uint64_t*)(ws + o_f1), ctr,
+                               st != nullptr, nullptr, items, s);
+    }
     if (e == hipSuccess && sched == SPAMM_SCHED_LPT)
         e = launch_lpt_order(d_desc, count, total, maxc, (uint32_t*)(ws + o_cnt), (uint32_t*)(ws + o_hist),
                              (uint32_t*)(ws + o_offs), (uint32_t*)(ws + o_ord), lp.queue, s);

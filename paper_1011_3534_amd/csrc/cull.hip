@@ -360,6 +360,50 @@ __global__ void __launch_bounds__(kLeafWords * kLeafQuarters * kWave)
     if (need) list[base + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)t;
 }
 
+// The direct leaf pass for a batch of flat-threshold products without
+// statistics: as k_cull_leaf, one block per (product, tile row I, 64 tiles
+// J), the four waves taking the quarters of each mask word in turn.
+// blk_off[m] is the first block of product m (ascending); the kept counts
+// are not formed (nothing reads them without statistics).
+__global__ void __launch_bounds__(kLeafQuarters * kWave)
+    k_cull_leaf_batched(const ProdDesc* __restrict__ desc, int nprod, const int64_t* __restrict__ blk_off) {
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = nprod - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (blk_off[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    const ProdDesc& d = desc[lo];
+    const int nb = d.nb, W = d.W, ny = (nb + kWave - 1) / kWave;
+    const int64_t local = b - blk_off[lo];
+    const int I = (int)(local / ny);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int J = (int)(local % ny) * kWave + lane;
+    constexpr int KQ = 64 / kLeafQuarters;
+    const bool live = J < nb;
+    const double t2 = d.tau2;
+    __shared__ unsigned long long s_bits[kLeafQuarters][kWave];
+    for (int w = 0; w < W; ++w) {
+        const int k0 = w * 64 + q * KQ, kn = min(KQ, nb - k0);
+        unsigned long long bits = 0;
+        if (live && kn > 0) {
+            const double* SA = d.SA + d.lvl_off[0] + (int64_t)I * nb + k0;
+            const double* SB = d.SB + d.lvl_off[0] + (int64_t)k0 * nb + J;
+#pragma unroll 8
+            for (int k = 0; k < kn; ++k) bits |= (unsigned long long)!(SA[k] * SB[(int64_t)k * nb] < t2) << k;
+            bits <<= q * KQ;
+        }
+        s_bits[q][lane] = bits;
+        __syncthreads();
+        if (q == 0 && live) {
+            for (int r = 1; r < kLeafQuarters; ++r) bits |= s_bits[r][lane];
+            d.mask[((int64_t)I * nb + J) * W + w] = bits;
+        }
+        __syncthreads();
+    }
+}
+
 // Counters, per-product non-empty tile counts and (single product) the leaf
 // bitmask, zeroed in one launch.
 __global__ void k_cull_prep(DevCounters* ctr, unsigned long long* nonempty, int nprod, uint64_t* mask,
@@ -458,6 +502,14 @@ hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t
         hipLaunchKernelGGL(k_cull_tier, dim3((unsigned)blocks), dim3(kCullThreads), 0, s, d_desc, plan.count, l,
                            in, out, ctr, plan.front_cap, want_bound, active);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_cull_leaf_batched(const ProdDesc* d_desc, int nprod, const int64_t* d_blk_off, int64_t blocks,
+                                   hipStream_t s) {
+    if (blocks > 0)
+        hipLaunchKernelGGL(k_cull_leaf_batched, dim3((unsigned)blocks), dim3(kLeafQuarters * kWave), 0, s, d_desc, nprod,
+                           d_blk_off);
     return hipGetLastError();
 }
 

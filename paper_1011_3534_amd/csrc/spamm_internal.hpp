@@ -259,6 +259,11 @@ struct CullPlan {
 hipError_t launch_cull_ex(const ProdDesc* d_desc, const CullPlan& plan, uint64_t* mask, uint64_t* front0,
                           uint64_t* front1, DevCounters* ctr, int want_bound, const int* active,
                           const int64_t* tier_items, hipStream_t s);
+// Batch of flat-threshold products without statistics: every leaf triple
+// tested, one block per (product, tile row, 64 tiles); d_blk_off[m] is the
+// first block of product m, blocks the total.  Writes every mask word.
+hipError_t launch_cull_leaf_batched(const ProdDesc* d_desc, int nprod, const int64_t* d_blk_off, int64_t blocks,
+                                   hipStream_t s);
 hipError_t launch_task_keys(const ProdDesc* d_desc, int64_t nb, int W, const uint64_t* mask,
                             uint64_t* keys_out, unsigned long long* count, int64_t cap, hipStream_t s);
 

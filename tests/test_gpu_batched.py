@@ -53,6 +53,28 @@ def test_batched_matches_oracle(leaf, prec, schedule):
             assert np.array_equal(C.norms(lv), r)
 
 
+@pytest.mark.parametrize("leaf,prec,schedule", [(64, "f32", "list"), (32, "f16x3", "static"), (128, "f32", "lpt")])
+def test_batched_direct_leaf_pass_matches_oracle(leaf, prec, schedule):
+    # without statistics the batch tests every leaf triple in one pass (no
+    # tier above the leaves is read or formed): kept triples equal the
+    # oracle's, values stay within the bound, and the results equal the
+    # batch with statistics (full descent) bit for bit
+    print(f"[case] batched direct leaf={leaf} prec={prec} schedule={schedule}", flush=True)
+    mats, taus = _batch(leaf, seed=2)
+    hs = [sp.build(to_dev(a), leaf) for a in mats]
+    Cs = sp.multiply_batched(hs, hs, taus, prec, schedule=schedule)
+    Ds, _ = sp.multiply_batched(hs, hs, taus, prec, stats=True, schedule=schedule)
+    for a, C, D, tau in zip(mats, Cs, Ds, taus):
+        a64 = a.astype(np.float64)
+        S = oracle.tile_sqnorms(a64, leaf)
+        keys, _ = oracle.tasks_flat(S, S, tau)
+        assert np.array_equal(C.task_list(), keys)
+        ref, _ = oracle.spamm_flat(a64, a64, leaf, tau)
+        out = C.to_dense().cpu().numpy()
+        assert np.all(np.abs(out.astype(np.float64) - ref) <= elementwise_bound(a64, a64, leaf, tau, prec))
+        assert np.array_equal(out.view(np.uint32), D.to_dense().cpu().numpy().view(np.uint32))
+
+
 def test_batched_equals_single_products_bitwise():
     print("[case] batched == single", flush=True)
     mats, taus = _batch(64, seed=1)
