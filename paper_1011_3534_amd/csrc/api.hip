@@ -519,31 +519,26 @@ spamm_status build_batched(int32_t count, const void* const* dev_a, const int64_
         return st;
     }
     static thread_local std::vector<PackDesc> hp;
-    static thread_local std::vector<NormTable> ht;
     hp.resize(count);
-    ht.resize(count);
     int64_t waves = 0;
     for (int m = 0; m < count; ++m) {
         M[m]->last_stream = s;
         M[m]->gen++;
         hp[m] = pack_desc(dev_a[m], n[m], lda[m], M[m], waves);
         waves += hp[m].nb * hp[m].nstrips;
-        ht[m] = norm_table(M[m]);
     }
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t o_tab = al(sizeof(PackDesc) * count), bytes = o_tab + al(sizeof(NormTable) * count);
+    const size_t bytes = sizeof(PackDesc) * count;
     char* ws = (char*)dev_alloc(M[0], bytes, s);
     if (!ws) {
         release_fresh();
         return set_error(SPAMM_ENOMEM, "batch scratch allocation failed");
     }
     const PackDesc* d_pd = (const PackDesc*)ws;
-    const NormTable* d_tab = (const NormTable*)(ws + o_tab);
     hipError_t e = hipMemcpyAsync(ws, hp.data(), sizeof(PackDesc) * count, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(ws + o_tab, ht.data(), sizeof(NormTable) * count, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_pack_norm_batched(d_pd, count, waves, dt, leaf, s);
-    if (e == hipSuccess) e = launch_upper_norms_batched(M.data(), count, d_tab, s);
-    for (int m = 0; m < count; ++m) M[m]->tiers_valid = e == hipSuccess;
+    // upper tiers when first read (a batch that descends forms the missing
+    // ones of all its operands in one launch per tier)
+    for (int m = 0; m < count; ++m) M[m]->tiers_valid = false;
     dev_free(M[0], ws, s);
     if (e != hipSuccess) {
         st = hip_error(e, "spamm_build_batched kernels");
@@ -853,7 +848,7 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
                  o_ctr = o_f1 + al((size_t)cap * 8), o_cnt = o_ctr + al(sizeof(DevCounters) + 16 * kMaxBatch),
                  o_ord = o_cnt + al((size_t)total * 4), o_hist = o_ord + al((size_t)total * 4),
                  o_offs = o_hist + al((size_t)(maxc + 1) * 4), o_q = o_offs + al((size_t)(maxc + 1) * 4),
-                 o_tab = o_q + 256, o_blk = o_tab + al(sizeof(NormTable) * count),
+                 o_tab = o_q + 256, o_blk = o_tab + al(sizeof(NormTable) * 2 * count),
                  bytes = o_blk + al(sizeof(int64_t) * (count + 1));
     spamm_matrix* owner = out[0];
     char* ws = (char*)dev_alloc(owner, bytes, s);
@@ -890,22 +885,29 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
         lp.list = (uint32_t*)(ws + o_ord);  // the order array holds the list
         lp.list_count = (unsigned*)(ws + o_q);
     }
-    // the descent reads the operands' upper tiers
-    for (int m = 0; m < count && r == SPAMM_OK; ++m) {
-        r = ensure_tiers(A[m], s);
-        if (r == SPAMM_OK) r = ensure_tiers(B[m], s);
-    }
-    if (r != SPAMM_OK) {
-        dev_free(owner, ws, s);
-        release_fresh();
-        return r;
-    }
-    static thread_local std::vector<NormTable> htab;
-    htab.resize(count);
-    for (int m = 0; m < count; ++m) htab[m] = norm_table(out[m]);
-    NormTable* d_tab = (NormTable*)(ws + o_tab);
     hipError_t e = hipMemcpyAsync(d_desc, hd.data(), sizeof(ProdDesc) * count, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_tab, htab.data(), sizeof(NormTable) * count, hipMemcpyHostToDevice, s);
+    if (!direct) {
+        // the descent reads the operands' upper tiers: the missing ones of
+        // all operands in one launch per tier
+        static thread_local std::vector<spamm_matrix*> need;
+        static thread_local std::vector<NormTable> htab;
+        need.clear();
+        htab.clear();
+        for (int m = 0; m < count; ++m)
+            for (const spamm_matrix* X : {A[m], B[m]}) {
+                auto* Xm = const_cast<spamm_matrix*>(X);  // the upper tiers are a cache of the leaf norms
+                if (Xm->tiers_valid || std::find(need.begin(), need.end(), Xm) != need.end()) continue;
+                need.push_back(Xm);
+                htab.push_back(norm_table(Xm));
+            }
+        if (!need.empty()) {
+            NormTable* d_tab = (NormTable*)(ws + o_tab);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(d_tab, htab.data(), sizeof(NormTable) * need.size(), hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = launch_upper_norms_batched(need.data(), (int)need.size(), d_tab, s);
+            for (auto* Xm : need) Xm->tiers_valid = e == hipSuccess;
+        }
+    }
     if (direct) {
         const int64_t* d_blk = (const int64_t*)(ws + o_blk);
         if (e == hipSuccess)
@@ -923,8 +925,9 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
     if (e == hipSuccess && sched == SPAMM_SCHED_LIST)
         e = launch_tile_list(d_desc, count, total, (uint32_t*)(ws + o_ord), (unsigned*)(ws + o_q), s);
     if (e == hipSuccess) e = launch_leaf_typed(d_desc, lp, A[0]->dt == SPAMM_F64, s);
-    if (e == hipSuccess) e = launch_upper_norms_batched(out.data(), count, d_tab, s);
-    for (int m = 0; m < count; ++m) out[m]->tiers_valid = e == hipSuccess;
+    // the results' leaf norms come from the epilogue; their upper tiers
+    // follow when first read
+    for (int m = 0; m < count; ++m) out[m]->tiers_valid = false;
     if (e == hipSuccess && st) {
         static thread_local DevCounters h;
         unsigned long long ne[kMaxBatch];
