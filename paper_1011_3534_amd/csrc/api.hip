@@ -379,6 +379,8 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
         if (!cp.sp2_list) SPAMM_HIP(launch_sp2_tiles(d_desc, C->nb, sp2_list, sp2_state, d_active, s));
         lp.list = sp2_list;
         lp.list_count = &sp2_state->list_count;
+        // (static stride: a step lists a few tiles per block, too few for a
+        // queue's grabs to pay for themselves)
     }
     if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[1], s));
     SPAMM_HIP(launch_leaf_typed(d_desc, lp, A->dt == SPAMM_F64, s));
@@ -884,6 +886,7 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
     } else if (sched == SPAMM_SCHED_LIST) {
         lp.list = (uint32_t*)(ws + o_ord);  // the order array holds the list
         lp.list_count = (unsigned*)(ws + o_q);
+        lp.list_queue = (unsigned*)(ws + o_q + 64);
     }
     hipError_t e = hipMemcpyAsync(d_desc, hd.data(), sizeof(ProdDesc) * count, hipMemcpyHostToDevice, s);
     if (!direct) {
@@ -923,7 +926,7 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
         e = launch_lpt_order(d_desc, count, total, maxc, (uint32_t*)(ws + o_cnt), (uint32_t*)(ws + o_hist),
                              (uint32_t*)(ws + o_offs), (uint32_t*)(ws + o_ord), lp.queue, s);
     if (e == hipSuccess && sched == SPAMM_SCHED_LIST)
-        e = launch_tile_list(d_desc, count, total, (uint32_t*)(ws + o_ord), (unsigned*)(ws + o_q), s);
+        e = launch_tile_list(d_desc, count, total, (uint32_t*)(ws + o_ord), (unsigned*)(ws + o_q), lp.list_queue, s);
     if (e == hipSuccess) e = launch_leaf_typed(d_desc, lp, A[0]->dt == SPAMM_F64, s);
     // the results' leaf norms come from the epilogue; their upper tiers
     // follow when first read

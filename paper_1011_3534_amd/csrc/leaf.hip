@@ -850,14 +850,34 @@ constexpr int list_blocks_per_cu() { return B == 32 ? 4 : (B == 64 ? 3 : 1); }
 template <int B, int P, typename TA, typename TC, bool SP2, bool PS>
 __global__ void __launch_bounds__(256, (B == 64 ? list_blocks_per_cu<B>() : 1))
     k_leaf_list(const ProdDesc* __restrict__ desc, int nprod, const uint32_t* __restrict__ list,
-                const unsigned* __restrict__ count, const int* __restrict__ branch, const int* __restrict__ active) {
+                const unsigned* __restrict__ count, unsigned* __restrict__ queue, const int* __restrict__ branch,
+                const int* __restrict__ active) {
     __shared__ __attribute__((aligned(16))) char smem[Geo<B, P>::SMEM];
     __shared__ KList kl;
     __shared__ double red[2][4];
+    __shared__ unsigned s_next;
     if (active && *active == 0) return;
     const int64_t n = (int64_t)*count;
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x)
+    if (!queue) {
+        for (int64_t i = blockIdx.x; i < n; i += gridDim.x)
+            leaf_tile<B, P, TA, TC, SP2, PS>(desc, nprod, (int64_t)list[i], smem, &kl, red, branch, false);
+        return;
+    }
+    // dynamic: each block pulls its next list position from the queue while
+    // it works on the current one (the grab's latency hides behind the
+    // tile), so blocks with cheap tiles take more of them; every block
+    // leaves once the queue passes the count
+    if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
+    __syncthreads();
+    int64_t i = s_next;
+    __syncthreads();
+    while (i < n) {
+        if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
         leaf_tile<B, P, TA, TC, SP2, PS>(desc, nprod, (int64_t)list[i], smem, &kl, red, branch, false);
+        __syncthreads();
+        i = s_next;
+        __syncthreads();
+    }
 }
 
 template <int B, int P, typename TA, typename TC, bool SP2, bool PS = false>
@@ -867,7 +887,7 @@ hipError_t go(const ProdDesc* d_desc, const LeafPlan& p, hipStream_t s) {
         int64_t grid = (int64_t)num_cus() * list_blocks_per_cu<B>();
         if (grid > p.total_tiles) grid = p.total_tiles < 1 ? 1 : p.total_tiles;
         hipLaunchKernelGGL((k_leaf_list<B, P, TA, TC, SP2, PS>), dim3((unsigned)grid), dim3(256), 0, s, d_desc,
-                           p.count, p.list, p.list_count, p.d_branch, p.d_active);
+                           p.count, p.list, p.list_count, p.list_queue, p.d_branch, p.d_active);
         return hipGetLastError();
     }
     if (p.queue) {

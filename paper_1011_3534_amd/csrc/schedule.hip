@@ -140,15 +140,18 @@ __global__ void k_zero_u32(uint32_t* p, int64_t count, unsigned long long* queue
     if (blockIdx.x == 0 && threadIdx.x == 0 && queue) *queue = 0ull;
 }
 
-__global__ void k_zero_one(unsigned* p) { *p = 0u; }
+__global__ void k_zero_one(unsigned* p, unsigned* q) {
+    *p = 0u;
+    if (q) *q = 0u;
+}
 
 }  // namespace
 
-// list: total entries; count is zeroed first (a kernel, so the sequence can
-// be captured in a graph).
+// list: total entries; count (and the leaf launch's queue, if any) is zeroed
+// first (a kernel, so the sequence can be captured in a graph).
 hipError_t launch_tile_list(const ProdDesc* d_desc, int nprod, int64_t total, uint32_t* list, unsigned* count,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_one, dim3(1), dim3(1), 0, s, count);
+                            unsigned* queue, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_one, dim3(1), dim3(1), 0, s, count, queue);
     int64_t blocks = (total + 255) / 256;
     blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
     hipLaunchKernelGGL(k_tile_list, dim3((unsigned)blocks), dim3(256), 0, s, d_desc, nprod, total, list, count);

@@ -282,13 +282,14 @@ struct LeafPlan {
     bool presplit = false;                 // 16-bit leaves: every operand has current split tiles
     const uint32_t* list = nullptr;        // C tiles to visit (persistent launch over the list)
     const unsigned* list_count = nullptr;  //   and their device-side count
+    unsigned* list_queue = nullptr;        //   zeroed queue counter: blocks pull list positions (NULL: static stride)
 };
 hipError_t launch_lpt_order(const ProdDesc* d_desc, int nprod, int64_t total, int maxc, uint32_t* counts,
                             uint32_t* hist, uint32_t* offs, uint32_t* order, unsigned long long* queue,
                             hipStream_t s);
 hipError_t launch_clear_masks(const ProdDesc* d_desc, int nprod, hipStream_t s);
 hipError_t launch_tile_list(const ProdDesc* d_desc, int nprod, int64_t total, uint32_t* list, unsigned* count,
-                            hipStream_t s);
+                            unsigned* queue, hipStream_t s);
 hipError_t launch_leaf_typed(const ProdDesc* d_desc, const LeafPlan& plan, bool a_f64, hipStream_t s);
 
 // SP2 device state (sp2.hip): the branch/active flags read by the product
