@@ -301,7 +301,7 @@ static bool split_current(const spamm_matrix* M, int kind) {
 spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C, double tau,
                              spamm_leaf_prec prec, hipStream_t s, int want_bound, int sp2, const int* d_branch,
                              const int* d_active, ProdDesc* d_desc_override, uint32_t* sp2_list,
-                             Sp2State* sp2_state, int depth_tau) {
+                             Sp2State* sp2_state, int depth_tau, bool count_tasks) {
     ProductScratch* ps = C->ps;
     ProdDesc* d_desc = d_desc_override;
     // 16-bit leaves read the operands' split tiles when both are current
@@ -346,7 +346,7 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
                 cp.sp2_list = sp2_list;
                 cp.sp2_state = sp2_state;
                 cp.skip_prep = true;
-            } else if (!sp2) {
+            } else if (!sp2 && !count_tasks) {
                 // a product without statistics: its counters are read by
                 // nothing (statistics take the full descent, which zeroes them)
                 cp.skip_prep = true;
@@ -1149,3 +1149,41 @@ spamm_status spamm_sp2_ex(const spamm_matrix* H, int64_t n_occ, double tau, int3
 }
 
 }  // extern "C"
+
+namespace spamm {
+
+spamm_status multiply_count(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,
+                            hipStream_t s, spamm_matrix** C, int64_t* tasks) {
+    if (!C || !tasks) return set_error(SPAMM_EINVAL, "null argument");
+    spamm_status v = check_operands(A, B, tau, prec);
+    if (v != SPAMM_OK) return v;
+    const spamm_dtype cdt = prec == SPAMM_LEAF_F64 ? SPAMM_F64 : SPAMM_F32;
+    spamm_matrix* Cm = *C;
+    if (Cm && (Cm == A || Cm == B || Cm->view || Cm->n != A->n || Cm->b != A->b || Cm->dt != cdt))
+        return set_error(SPAMM_EINVAL, "C does not fit the product");
+    bool fresh = false;
+    if (!Cm) {
+        Cm = new_handle(A->n, A->b, cdt);
+        fresh = true;
+        spamm_status r = alloc_storage(Cm, s);
+        if (r != SPAMM_OK) {
+            release(Cm);
+            return r;
+        }
+    }
+    Cm->last_stream = s;
+    spamm_status r = ensure_scratch(Cm, s);
+    if (r == SPAMM_OK)
+        r = enqueue_product(A, B, Cm, tau, prec, s, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, 0, true);
+    if (r != SPAMM_OK) {
+        if (fresh) release(Cm);
+        return r;
+    }
+    *C = Cm;
+    spamm_stats st;
+    r = read_stats(Cm, s, &st, tau);
+    *tasks = st.tasks;
+    return r;
+}
+
+}  // namespace spamm

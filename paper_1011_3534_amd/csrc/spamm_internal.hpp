@@ -325,6 +325,11 @@ hipError_t launch_check_symmetric(const spamm_matrix* H, unsigned* flag, hipStre
 spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C, double tau,
                              spamm_leaf_prec prec, hipStream_t s, int want_bound, int sp2, const int* d_branch,
                              const int* d_active, ProdDesc* d_desc_override, uint32_t* sp2_list = nullptr,
-                             Sp2State* sp2_state = nullptr, int depth_tau = 0);
+                             Sp2State* sp2_state = nullptr, int depth_tau = 0, bool count_tasks = false);
+// C ~= A B (flat tau) with only the kept-product count as a statistic: no
+// per-tier survivors or culled bound, so the direct leaf pass serves it.
+// Synchronises the stream.  *C as for spamm_multiply.
+spamm_status multiply_count(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,
+                            hipStream_t s, spamm_matrix** C, int64_t* tasks);
 
 }  // namespace spamm

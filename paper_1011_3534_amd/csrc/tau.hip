@@ -431,13 +431,13 @@ spamm_status spamm_tau_select(const spamm_matrix* A, const spamm_matrix* B, doub
     spamm_matrix* E = nullptr;
     if ((r = spamm_multiply(A, B, 0.0, SPAMM_LEAF_F64, stream, &E, nullptr)) != SPAMM_OK) return r;
     auto err_at = [&](double tau, double* err, int64_t* tasks) -> spamm_status {
-        spamm_stats st;
-        spamm_status q = spamm_multiply(A, B, tau, prec, stream, C, &st);
+        int64_t t = 0;
+        spamm_status q = multiply_count(A, B, tau, prec, (hipStream_t)stream, C, &t);
         if (q != SPAMM_OK) return q;
         double d2 = 0.0, r2 = 0.0;
         if ((q = spamm_diff_norms(*C, E, &d2, &r2, stream)) != SPAMM_OK) return q;
         *err = r2 > 0.0 ? std::sqrt(d2 / r2) : std::sqrt(d2);
-        *tasks = st.tasks;
+        *tasks = t;
         info->evaluations += 1;
         return SPAMM_OK;
     };
