@@ -1075,6 +1075,16 @@ spamm_status spamm_sp2_ex(const spamm_matrix* H, int64_t n_occ, double tau, int3
     }
     // product counters start at zero; each step's finalize leaves them so
     for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMemsetAsync(X[i]->ps->ctr, 0, sizeof(DevCounters), s);
+    // the second X buffer starts as an all-zero matrix that is known to be
+    // zero (exponents -128, norms 0): a listing step writes only the tiles it
+    // lists (as every later step does) instead of every tile of the fresh
+    // buffer, and the tiles no step writes hold their zeros
+    if (tau > 0.0 || symmetric) {
+        const size_t tb = (size_t)(nb * nb) * X[1]->b * X[1]->b * X[1]->elem;
+        if (e == hipSuccess) e = hipMemsetAsync(X[1]->tiles, 0, tb, s);
+        if (e == hipSuccess) e = hipMemsetAsync(X[1]->norms, 0, (size_t)(nb * nb) * sizeof(double), s);
+        if (e == hipSuccess) e = hipMemsetAsync(X[1]->texp, 0x80, (size_t)(nb * nb), s);
+    }
     if (e != hipSuccess) return fail(e, "spamm_sp2 setup");
     if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return fail(e, "hipStreamCreate");
     if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
