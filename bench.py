@@ -126,7 +126,7 @@ def main():
     ap.add_argument("--train-matrices", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library has no "
               f"multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     if args.workload != "algebraic8192":

@@ -55,7 +55,7 @@ typedef enum {
     SPAMM_ENONFINITE = 5,   /* an operand holds an inf or NaN (its root norm is     *
                              * not finite), reported by the syncing calls         */
     SPAMM_ENOCONV = 6,      /* SP2 did not meet its stopping rule within max_iter   */
-    SPAMM_EUNSUPPORTED = 7  /* valid request this build does not implement          */
+    SPAMM_EUNSUPPORTED = 7  /* valid request the library does not implement         */
 } spamm_status;
 
 /* Element type of the caller's dense matrix and of the stored tiles. */
@@ -63,7 +63,7 @@ typedef enum { SPAMM_F64 = 0, SPAMM_F32 = 1 } spamm_dtype;
 
 /* Arithmetic of the dense leaf products (section 3 uses single precision
  * 4x4 products; the MFMA variants here accumulate in FP32, FP64 in FP64).
- *   F64    : FP64 inputs, FP64 MFMA, FP64 result (also the exact judge)
+ *   F64    : FP64 inputs, FP64 MFMA, FP64 result (also the exact reference)
  *   F32    : FP32 MFMA, FP32 result
  *   BF16   : operands rounded to bfloat16 (RNE), FP32 accumulation
  *   BF16X3 : x = hi + lo with hi = bf16(x), lo = bf16(x - hi); the product
@@ -420,7 +420,7 @@ spamm_status spamm_tau_train(spamm_tau_model* m, const float* dev_x, const float
 /* tau = 10^y ||A||_F ||B||_F for the target relative error; syncs. */
 spamm_status spamm_tau_predict(const spamm_matrix* A, const spamm_matrix* B, double target,
                                const spamm_tau_model* m, void* stream, double* tau_out);
-/* Threshold that meets the target, judged against the exact product (FP64
+/* Threshold that meets the target, checked against the exact product (FP64
  * leaves at tau = 0): the starting tau -- the network's prediction for half
  * the target (m non-NULL), else 10 target ||A||_F ||B||_F -- is checked; if
  * its error exceeds the target, tau steps down (a quarter decade at a time

@@ -1,4 +1,4 @@
-"""Learned tau selector: features, MLP, Adam and the bisection judge in FP64.
+"""Learned tau selector: features, MLP, Adam and the bisection check in FP64.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 

@@ -525,7 +525,7 @@ def tau_predict(A: Matrix, B: Matrix, target: float, model: TauModel, stream=Non
 
 def tau_select(A: Matrix, B: Matrix, target: float, model: TauModel | None = None, prec: str = "f32",
                resolution_decades: float = 0.05, out: Matrix | None = None, stream=None):
-    """(C at the selected tau, info dict); judged against the exact product."""
+    """(C at the selected tau, info dict); checked against the exact product."""
     h = ctypes.c_void_p(out.handle.value if out is not None else None)
     info = TauInfo()
     code = lib().spamm_tau_select(A.handle, B.handle, float(target), model.handle if model else None, LEAF[prec],

@@ -234,7 +234,7 @@ def test_huge_tau_and_zero_matrix():
 
 def test_tau0_f64_is_dense_product():
     # tau = 0 with FP64 leaves on FP32 tiles: the exact product of the stored values
-    _case("tau=0 f64 judge")
+    _case("tau=0 f64 exact product")
     n = 777
     a = si.algebraic_decay(n, 2.0, 9, np.float32)
     bm = si.algebraic_decay(n, 1.5, 10, np.float32)
