@@ -474,11 +474,30 @@ spamm_status spamm_generate_decay(int64_t n, int64_t ld, spamm_dtype dt, const d
                                   uint64_t seed, double lo, double hi, int32_t symmetric,
                                   const double* host_diag, void* dev_out, void* stream);
 
-/* Device allocation hook.  alloc(bytes, ctx) returns device memory or NULL;
- * dealloc(ptr, ctx) releases it.  NULL functions restore hipMalloc/hipFree.
- * Handles keep the pair they were allocated with. */
-typedef void* (*spamm_alloc_fn)(size_t bytes, void* ctx);
-typedef void (*spamm_dealloc_fn)(void* ptr, void* ctx);
+/* Device allocation hook, stream-ordered.
+ *   alloc(bytes, stream, ctx)  : device memory for work enqueued on `stream`
+ *                                (a hipStream_t as void*, NULL = null stream),
+ *                                or NULL on failure (the call then returns
+ *                                SPAMM_ENOMEM)
+ *   dealloc(ptr, stream, ctx)  : release ptr once the work enqueued on
+ *                                `stream` before this call is done with it: the
+ *                                block may go to later work on that stream at
+ *                                once (stream order), to other streams only
+ *                                after this stream passes the call
+ * Every device allocation of the library goes through the hook: handle
+ * storage and product scratch (allocated on the stream of the call that
+ * creates them, released by spamm_free after it synchronises the handle's
+ * last stream), per-call workspaces of the batched, SP2, autotune, tau,
+ * diff-norm and generator calls (allocated and released on the stream of the
+ * call, the release enqueued right after the kernels that read them), and
+ * tau models (allocated on the null stream, released by
+ * spamm_tau_model_free after a device synchronisation).
+ * NULL functions restore hipMalloc / hipFree (hipFree waits for the device).
+ * Handles and models keep the pair they were allocated with, so the
+ * functions must stay callable until every such object is freed; ctx is
+ * passed through unchanged.  Errors: EINVAL if exactly one function is NULL. */
+typedef void* (*spamm_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*spamm_dealloc_fn)(void* ptr, void* stream, void* ctx);
 spamm_status spamm_set_allocator(spamm_alloc_fn alloc, spamm_dealloc_fn dealloc, void* ctx);
 
 /* Release a handle (NULL is a no-op).  Synchronises the handle's last stream. */

@@ -58,10 +58,8 @@ def _load():
     lib.orc_spamm_flat.restype = i64
     lib.orc_tasks_flat.argtypes = [_DP, _DP, i64, dbl, _U64P, i64, _DP]
     lib.orc_tasks_flat.restype = i64
-    lib.orc_tasks_hierarchical.argtypes = [_DP, _DP, i64, dbl, i32, _U64P, i64, _I64P]
+    lib.orc_tasks_hierarchical.argtypes = [_DP, _DP, i64, dbl, i32, _U64P, i64, _I64P, _DP]
     lib.orc_tasks_hierarchical.restype = i64
-    lib.orc_dense_matmul.argtypes = [_DP, _DP, i64, _DP]
-    lib.orc_dense_matmul.restype = None
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = i32
     _lib = lib
@@ -163,14 +161,18 @@ def tasks_flat(SA, SB, tau: float, want_keys: bool = True):
     return (keys[:t].copy() if want_keys else int(t)), float(bound.value)
 
 
-def count_hierarchical(SA, SB, tau: float, depth_scaled: bool = False):
-    """Kept octree nodes per tier (tier 0 = leaf triples) from leaf norms."""
+def count_hierarchical(SA, SB, tau: float, depth_scaled: bool = False, want_bound: bool = False):
+    """Kept octree nodes per tier (tier 0 = leaf triples) from leaf norms.
+
+    want_bound: also return the culled-node bound (sum over the octree nodes
+    the recursion culls, at any tier, of ||A^k||_F ||B^k||_F; Eq. 3)."""
     SA, SB = _f64(SA), _f64(SB)
     nb = SA.shape[0]
     kept = np.zeros(num_levels(nb) + 1, dtype=np.int64)
+    bound = ctypes.c_double(0.0)
     t = _load().orc_tasks_hierarchical(_p(SA), _p(SB), nb, float(tau), int(bool(depth_scaled)), None, 0,
-                                       _p(kept, _I64P))
-    return int(t), kept
+                                       _p(kept, _I64P), ctypes.byref(bound))
+    return (int(t), kept, float(bound.value)) if want_bound else (int(t), kept)
 
 
 def tasks_hierarchical(SA, SB, tau: float, depth_scaled: bool = False):
@@ -181,20 +183,12 @@ def tasks_hierarchical(SA, SB, tau: float, depth_scaled: bool = False):
     kept = np.zeros(num_levels(nb) + 1, dtype=np.int64)
     lib = _load()
     t = lib.orc_tasks_hierarchical(_p(SA), _p(SB), nb, float(tau), int(bool(depth_scaled)), None, 0,
-                                   _p(kept, _I64P))
+                                   _p(kept, _I64P), None)
     keys = np.empty(max(t, 1), dtype=np.uint64)
     t2 = lib.orc_tasks_hierarchical(_p(SA), _p(SB), nb, float(tau), int(bool(depth_scaled)), _p(keys, _U64P), t,
-                                    _p(kept, _I64P))
+                                    _p(kept, _I64P), None)
     assert t2 == t
     return np.sort(keys[:t]), kept
-
-
-def dense_matmul(a, bm) -> np.ndarray:
-    a, bm = _f64(a), _f64(bm)
-    n = a.shape[0]
-    c = np.empty((n, n), dtype=np.float64)
-    _load().orc_dense_matmul(_p(a), _p(bm), n, _p(c))
-    return c
 
 
 def unpack_keys(keys):

@@ -15,7 +15,9 @@
  *     ||A^k|| ||B^k|| < tau, computed densely at the finest tier, and
  *     otherwise assembled from the 8 sub-products;
  *   - the same result by flat enumeration of leaf triples (I,J,K);
- *   - the plain dense product (the tau = 0 limit, section 3).
+ *   - the culled-norm sums that bound the omitted part of the product
+ *     (section 2, Eq. 3: an omitted block product has norm at most
+ *     ||A^k|| ||B^k||), over culled leaf triples or over culled octree nodes.
  *
  * Readings fixed here where the paper is silent:
  *   - norms are carried as FP64 *squared* Frobenius norms S and the cull test
@@ -300,12 +302,18 @@ typedef struct {
     int64_t* level_kept;
     uint64_t* keys;
     int64_t cap, count;
+    double bound;  /* sum over culled nodes of sqrt(S_A) sqrt(S_B) */
 } count_ctx;
 
 static void count_rec(count_ctx* x, int32_t l, int64_t I, int64_t J, int64_t K, double tau) {
     double sa = x->pa->S[l][I * x->pa->m[l] + K];
     double sb = x->pb->S[l][K * x->pb->m[l] + J];
-    if (sa * sb < tau * tau) return;
+    if (sa * sb < tau * tau) {
+        /* Eq. (3): the whole block product under a culled node has norm at
+         * most ||A^k||_F ||B^k||_F */
+        x->bound += sqrt(sa) * sqrt(sb);
+        return;
+    }
     x->level_kept[l] += 1;
     if (l == 0) {
         if (x->keys && x->count < x->cap) x->keys[x->count] = pack_key(I, J, K);
@@ -324,9 +332,13 @@ static void count_rec(count_ctx* x, int32_t l, int64_t I, int64_t J, int64_t K, 
 
 /* Hierarchical kept leaf triples from leaf norms only (the recursion of
  * Eq. 4 with the products left out).  level_kept: L+1 entries, tier 0 =
- * leaves; keys optional (up to cap). */
+ * leaves; keys optional (up to cap); culled_bound (optional) receives the
+ * sum over the culled octree nodes -- the nodes the recursion tests and
+ * drops, at whatever tier -- of sqrt(S_A) sqrt(S_B), which bounds the
+ * Frobenius norm of the omitted part of the product (Eq. 3). */
 int64_t orc_tasks_hierarchical(const double* SA, const double* SB, int64_t nb, double tau,
-                               int32_t depth_scaled, uint64_t* keys, int64_t cap, int64_t* level_kept) {
+                               int32_t depth_scaled, uint64_t* keys, int64_t cap, int64_t* level_kept,
+                               double* culled_bound) {
     pyramid pa, pb;
     memset(&pa, 0, sizeof pa);
     memset(&pb, 0, sizeof pb);
@@ -346,20 +358,10 @@ int64_t orc_tasks_hierarchical(const double* SA, const double* SB, int64_t nb, d
         m = ceil_div(m, 2);
     }
     memset(level_kept, 0, sizeof(int64_t) * (size_t)(pa.L + 1));
-    count_ctx x = {&pa, &pb, depth_scaled, level_kept, keys, cap, 0};
+    count_ctx x = {&pa, &pb, depth_scaled, level_kept, keys, cap, 0, 0.0};
     count_rec(&x, pa.L, 0, 0, 0, tau);
+    if (culled_bound) *culled_bound = x.bound;
     free_pyramid(&pa);
     free_pyramid(&pb);
     return x.count;
-}
-
-/* Plain dense product C = A B (i, k, j loop order), the tau = 0 limit. */
-void orc_dense_matmul(const double* a, const double* bm, int64_t n, double* c) {
-    memset(c, 0, sizeof(double) * (size_t)(n * n));
-#pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i)
-        for (int64_t k = 0; k < n; ++k) {
-            double aik = a[i * n + k];
-            for (int64_t j = 0; j < n; ++j) c[i * n + j] = c[i * n + j] + aik * bm[k * n + j];
-        }
 }

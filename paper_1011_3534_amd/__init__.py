@@ -107,8 +107,8 @@ _lib = None
 _alloc_cb = None
 _dealloc_cb = None
 _VP = ctypes.c_void_p
-_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
-_DEALLOC_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_DEALLOC_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
 
 def lib():
@@ -205,10 +205,14 @@ def _stream(stream):
 def use_torch_allocator(enable: bool = True):
     """Back the library's device allocations with torch's caching allocator.
 
-    Every handle keeps the allocator it was created with (its storage is
-    returned to it when the handle is freed), so the callbacks are made once
-    and live as long as the process: a handle made while they were installed
-    may be freed after the library's allocator was switched back or set again."""
+    The library passes the stream each block is used on: the block is taken
+    from (and returned to) that stream's pool, so a block released right
+    after the kernels that read it is reused only by later work on the same
+    stream.  Every handle keeps the allocator it was created with (its
+    storage is returned to it when the handle is freed), so the callbacks are
+    made once and live as long as the process: a handle made while they were
+    installed may be freed after the library's allocator was switched back or
+    set again."""
     global _alloc_cb, _dealloc_cb
     import torch
 
@@ -216,13 +220,13 @@ def use_torch_allocator(enable: bool = True):
         _check(lib().spamm_set_allocator(_ALLOC_FN(), _DEALLOC_FN(), None))
         return
     if _alloc_cb is None:
-        def _alloc(nbytes, ctx):
+        def _alloc(nbytes, stream, ctx):
             try:
-                return torch.cuda.caching_allocator_alloc(int(nbytes))
+                return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
             except Exception:          # OOM: the library reports SPAMM_ENOMEM
                 return None
 
-        def _dealloc(ptr, ctx):
+        def _dealloc(ptr, stream, ctx):
             try:
                 torch.cuda.caching_allocator_delete(int(ptr))
             except Exception:

@@ -36,19 +36,44 @@ spamm_status hip_error(hipError_t e, const char* what) {
     return e == hipErrorOutOfMemory ? SPAMM_ENOMEM : SPAMM_EHIP;
 }
 
-void* dev_alloc(spamm_matrix* owner, size_t bytes, hipStream_t) {
+Allocator current_allocator() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Allocator a;
+    a.alloc = g_alloc;
+    a.dealloc = g_dealloc;
+    a.ctx = g_actx;
+    return a;
+}
+
+void* raw_alloc(const Allocator& a, size_t bytes, hipStream_t s) {
     if (bytes == 0) bytes = 256;
     bytes = (bytes + 255) & ~(size_t)255;
-    if (owner->alloc) return owner->alloc(bytes, owner->actx);
+    if (a.alloc) return a.alloc(bytes, (void*)s, a.ctx);
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
     return p;
 }
 
-void dev_free(spamm_matrix* owner, void* p, hipStream_t) {
+void raw_free(const Allocator& a, void* p, hipStream_t s) {
     if (!p) return;
-    if (owner->dealloc) owner->dealloc(p, owner->actx);
+    if (a.dealloc) a.dealloc(p, (void*)s, a.ctx);
     else (void)hipFree(p);
+}
+
+void* dev_alloc(spamm_matrix* owner, size_t bytes, hipStream_t s) {
+    Allocator a;
+    a.alloc = owner->alloc;
+    a.dealloc = owner->dealloc;
+    a.ctx = owner->actx;
+    return raw_alloc(a, bytes, s);
+}
+
+void dev_free(spamm_matrix* owner, void* p, hipStream_t s) {
+    Allocator a;
+    a.alloc = owner->alloc;
+    a.dealloc = owner->dealloc;
+    a.ctx = owner->actx;
+    raw_free(a, p, s);
 }
 
 int num_cus() {
@@ -93,9 +118,10 @@ spamm_matrix* new_handle(int64_t n, int32_t b, spamm_dtype dt) {
     M->dt = dt;
     M->elem = dt == SPAMM_F64 ? 8 : 4;
     tier_shapes(M->nb, M->L, M->lvl_m, M->lvl_off, M->norms_total);
-    M->alloc = g_alloc;
-    M->dealloc = g_dealloc;
-    M->actx = g_actx;
+    const Allocator a = current_allocator();
+    M->alloc = a.alloc;
+    M->dealloc = a.dealloc;
+    M->actx = a.ctx;
     (void)hipGetDevice(&M->device);
     return M;
 }
@@ -727,13 +753,14 @@ spamm_status spamm_diff_norms(const spamm_matrix* X, const spamm_matrix* Y, doub
     if (!X || !Y || !diff2 || !ref2) return set_error(SPAMM_EINVAL, "null argument");
     if (X->n != Y->n) return set_error(SPAMM_EINVAL, "handles differ in n");
     hipStream_t s = (hipStream_t)stream;
-    double* d = nullptr;
-    SPAMM_HIP(hipMalloc(&d, 2 * 1024 * sizeof(double)));
-    hipError_t e = launch_diff_norms(X, Y, d, s);
+    const Allocator al = current_allocator();
+    double* d = (double*)raw_alloc(al, 2 * 1024 * sizeof(double), s);
+    if (!d) return set_error(SPAMM_ENOMEM, "spamm_diff_norms workspace allocation failed");
     std::vector<double> h(2048);
+    hipError_t e = launch_diff_norms(X, Y, d, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, h.size() * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e == hipSuccess) e = hipMemcpy(h.data(), d, h.size() * 8, hipMemcpyDeviceToHost);
-    (void)hipFree(d);
+    raw_free(al, d, s);
     if (e != hipSuccess) return hip_error(e, "spamm_diff_norms");
     double a = 0.0, b = 0.0;
     for (int i = 0; i < 1024; ++i) {

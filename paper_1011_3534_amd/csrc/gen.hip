@@ -57,9 +57,10 @@ extern "C" spamm_status spamm_generate_decay(int64_t n, int64_t ld, spamm_dtype 
     if (!host_table || !dev_out) return set_error(SPAMM_EINVAL, "null argument");
     if (dt != SPAMM_F32 && dt != SPAMM_F64) return set_error(SPAMM_EINVAL, "unknown dtype");
     hipStream_t s = (hipStream_t)stream;
-    double* d = nullptr;
     const size_t nt = (size_t)n * (host_diag ? 2 : 1);
-    SPAMM_HIP(hipMalloc(&d, nt * sizeof(double)));
+    const Allocator al = current_allocator();
+    double* d = (double*)raw_alloc(al, nt * sizeof(double), s);
+    if (!d) return set_error(SPAMM_ENOMEM, "spamm_generate_decay table allocation failed");
     hipError_t e = hipMemcpyAsync(d, host_table, (size_t)n * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && host_diag) e = hipMemcpyAsync(d + n, host_diag, (size_t)n * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
@@ -76,7 +77,7 @@ extern "C" spamm_status spamm_generate_decay(int64_t n, int64_t ld, spamm_dtype 
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(d);
+    raw_free(al, d, s);
     if (e != hipSuccess) return hip_error(e, "spamm_generate_decay");
     return SPAMM_OK;
 }

@@ -703,6 +703,7 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         red[1][w] = idem;
     }
     // canonical squared norm of the stored tile: wave 0, one (or two) columns per lane
+    double s_tile = 0.0;  // (tid 0: the tile's norm, which a NaN anywhere in it makes NaN)
     if (w == 0) {
         double s = 0.0;
         if (lane < B) {
@@ -743,6 +744,7 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         }
         if (lane == 0) {
             d.SC[local] = s;
+            s_tile = s;
             if constexpr (SP2) {
                 if (I == J) d.sp2_part[(int64_t)nb * nb + I] = tr;
             }
@@ -783,6 +785,9 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             e = ilogb(m2);
             e = e < -127 ? -127 : (e > 127 ? 127 : e);
         }
+        // fmax passes over NaN: a tile holding NaN is marked "not known zero"
+        // through its norm, so a later product rewrites it
+        if (s_tile != s_tile) e = 127;
         d.eC[local] = (int8_t)e;
         if constexpr (SP2) d.sp2_part[local] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
         if (mirror) {

@@ -32,8 +32,12 @@ struct Vec16<double> {
 __device__ inline double shfl_down_d(double v, int d) { return __shfl_down(v, d, kWave); }
 __device__ inline float shfl_xor_f(float v, int d) { return __shfl_xor(v, d, kWave); }
 
-// Exponent e with max|x| in [2^e, 2^(e+1)); -128 for an all-zero tile.
-__device__ inline int8_t tile_exponent(double mx) {
+// Exponent e with max|x| in [2^e, 2^(e+1)); -128 for an all-zero tile.  The
+// maximum (fmax) passes over NaN, but the tile's squared norm S does not: a
+// NaN anywhere makes S NaN, and the tile then gets 127 ("not known zero",
+// as for inf), never the all-zero mark.
+__device__ inline int8_t tile_exponent(double mx, double S) {
+    if (S != S) return (int8_t)127;
     if (!(mx > 0.0)) return (int8_t)-128;
     int e = ilogb(mx);
     e = e < -127 ? -127 : (e > 127 ? 127 : e);
@@ -119,7 +123,7 @@ __device__ __forceinline__ void pack_wave(const T* __restrict__ a, int64_t n, in
     for (int d = 1; d < LPT; d *= 2) mx = fmax(mx, (double)__shfl_xor(mx, d, kWave));
     if (live && tl == 0) {
         S0[I * nb + K] = acc[0];
-        texp[I * nb + K] = tile_exponent(mx);
+        texp[I * nb + K] = tile_exponent(mx, acc[0]);
     }
 }
 

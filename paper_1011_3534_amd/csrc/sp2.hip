@@ -167,6 +167,7 @@ __global__ void __launch_bounds__(64) k_tile_stats(const float* __restrict__ T, 
             e = ilogb(mx);
             e = e < -127 ? -127 : (e > 127 ? 127 : e);
         }
+        if (s != s) e = 127;  // fmax passed over a NaN, the norm did not: not known zero
         texp[tile] = (int8_t)e;
         const int64_t I = tile / nb, K = tile % nb;
         if (I == K) diag[nb * nb + I] = dv;

@@ -179,6 +179,17 @@ spamm_status hip_error(hipError_t e, const char* what);
     } while (0)
 
 // allocation ------------------------------------------------------------------
+// The allocator pair an object was created with (the hook of
+// spamm_set_allocator at that time; null functions: hipMalloc / hipFree).
+struct Allocator {
+    spamm_alloc_fn alloc = nullptr;
+    spamm_dealloc_fn dealloc = nullptr;
+    void* ctx = nullptr;
+};
+Allocator current_allocator();
+// Stream-ordered allocation and release through an allocator pair.
+void* raw_alloc(const Allocator& a, size_t bytes, hipStream_t s);
+void raw_free(const Allocator& a, void* p, hipStream_t s);
 void* dev_alloc(spamm_matrix* owner, size_t bytes, hipStream_t s);
 void dev_free(spamm_matrix* owner, void* p, hipStream_t s);
 int num_cus();

@@ -20,6 +20,8 @@ struct spamm_tau_model {
     float* m = nullptr;       // Adam moments
     float* v = nullptr;
     int64_t t = 0;            // Adam step count
+    spamm::Allocator al;      // the allocator pair the weights came from
+    hipStream_t last_stream = nullptr;  // stream of the last call that used the weights
 };
 
 namespace spamm {
@@ -248,15 +250,20 @@ extern "C" {
 spamm_status spamm_tau_model_create(const float* host_params, spamm_tau_model** out) {
     if (!host_params || !out) return set_error(SPAMM_EINVAL, "null argument");
     auto* m = new spamm_tau_model();
+    m->al = current_allocator();
     const size_t bytes = (size_t)kNParam * sizeof(float);
-    if (hipMalloc(&m->params, bytes) != hipSuccess || hipMalloc(&m->m, bytes) != hipSuccess ||
-        hipMalloc(&m->v, bytes) != hipSuccess) {
+    m->params = (float*)raw_alloc(m->al, bytes, nullptr);
+    m->m = (float*)raw_alloc(m->al, bytes, nullptr);
+    m->v = (float*)raw_alloc(m->al, bytes, nullptr);
+    if (!m->params || !m->m || !m->v) {
         spamm_tau_model_free(m);
         return set_error(SPAMM_ENOMEM, "tau model allocation failed");
     }
-    hipError_t e = hipMemcpy(m->params, host_params, bytes, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(m->m, 0, bytes);
-    if (e == hipSuccess) e = hipMemset(m->v, 0, bytes);
+    // set up on the null stream, where the weights were allocated
+    hipError_t e = hipMemcpyAsync(m->params, host_params, bytes, hipMemcpyHostToDevice, nullptr);
+    if (e == hipSuccess) e = hipMemsetAsync(m->m, 0, bytes, nullptr);
+    if (e == hipSuccess) e = hipMemsetAsync(m->v, 0, bytes, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
         spamm_tau_model_free(m);
         return hip_error(e, "spamm_tau_model_create");
@@ -267,16 +274,19 @@ spamm_status spamm_tau_model_create(const float* host_params, spamm_tau_model** 
 
 spamm_status spamm_tau_model_params(const spamm_tau_model* m, float* host_params) {
     if (!m || !host_params) return set_error(SPAMM_EINVAL, "null argument");
-    SPAMM_HIP(hipDeviceSynchronize());
-    SPAMM_HIP(hipMemcpy(host_params, m->params, (size_t)kNParam * sizeof(float), hipMemcpyDeviceToHost));
+    // the weights were last written on last_stream: copy in that stream's order
+    SPAMM_HIP(hipMemcpyAsync(host_params, m->params, (size_t)kNParam * sizeof(float), hipMemcpyDeviceToHost,
+                             m->last_stream));
+    SPAMM_HIP(hipStreamSynchronize(m->last_stream));
     return SPAMM_OK;
 }
 
 void spamm_tau_model_free(spamm_tau_model* m) {
     if (!m) return;
-    (void)hipFree(m->params);
-    (void)hipFree(m->m);
-    (void)hipFree(m->v);
+    if (m->last_stream) (void)hipStreamSynchronize(m->last_stream);
+    raw_free(m->al, m->params, m->last_stream);
+    raw_free(m->al, m->m, m->last_stream);
+    raw_free(m->al, m->v, m->last_stream);
     delete m;
 }
 
@@ -302,13 +312,15 @@ spamm_status spamm_tau_forward(const spamm_tau_model* m, const float* dev_x, int
                                void* stream) {
     if (!m || !dev_x || !dev_y || count < 1) return set_error(SPAMM_EINVAL, "bad argument");
     hipStream_t s = (hipStream_t)stream;
-    void* ws = nullptr;
-    SPAMM_HIP(hipMalloc(&ws, work_bytes(count)));
+    const Allocator al = current_allocator();
+    void* ws = raw_alloc(al, work_bytes(count), s);
+    if (!ws) return set_error(SPAMM_ENOMEM, "tau workspace allocation failed");
+    const_cast<spamm_tau_model*>(m)->last_stream = s;
     Work w = carve(ws, count);
     w.yhat = dev_y;
     hipError_t e = forward(m->params, dev_x, count, w, s);
+    raw_free(al, ws, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(ws);
     if (e != hipSuccess) return hip_error(e, "spamm_tau_forward");
     return SPAMM_OK;
 }
@@ -317,8 +329,10 @@ spamm_status spamm_tau_grad(const spamm_tau_model* m, const float* dev_x, const 
                             float* host_grad, float* host_loss, void* stream) {
     if (!m || !dev_x || !dev_y || count < 1 || !host_grad) return set_error(SPAMM_EINVAL, "bad argument");
     hipStream_t s = (hipStream_t)stream;
-    void* ws = nullptr;
-    SPAMM_HIP(hipMalloc(&ws, work_bytes(count)));
+    const Allocator al = current_allocator();
+    void* ws = raw_alloc(al, work_bytes(count), s);
+    if (!ws) return set_error(SPAMM_ENOMEM, "tau workspace allocation failed");
+    const_cast<spamm_tau_model*>(m)->last_stream = s;
     Work w = carve(ws, count);
     unsigned nb = 0;
     hipError_t e = forward(m->params, dev_x, count, w, s);
@@ -326,8 +340,8 @@ spamm_status spamm_tau_grad(const spamm_tau_model* m, const float* dev_x, const 
     std::vector<float> part(8192);
     if (e == hipSuccess) e = hipMemcpyAsync(host_grad, w.grad, (size_t)kNParam * 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(part.data(), w.part, (size_t)nb * 4, hipMemcpyDeviceToHost, s);
+    raw_free(al, ws, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(ws);
     if (e != hipSuccess) return hip_error(e, "spamm_tau_grad");
     if (host_loss) {
         double l = 0.0;
@@ -343,8 +357,10 @@ spamm_status spamm_tau_train(spamm_tau_model* m, const float* dev_x, const float
         return set_error(SPAMM_EINVAL, "bad argument");
     hipStream_t s = (hipStream_t)stream;
     const int64_t B = batch < count ? batch : count;
-    void* ws = nullptr;
-    SPAMM_HIP(hipMalloc(&ws, work_bytes(B)));
+    const Allocator al = current_allocator();
+    void* ws = raw_alloc(al, work_bytes(B), s);
+    if (!ws) return set_error(SPAMM_ENOMEM, "tau workspace allocation failed");
+    m->last_stream = s;
     Work w = carve(ws, B);
     std::vector<float> part(8192);
     hipError_t e = hipSuccess;
@@ -372,8 +388,8 @@ spamm_status spamm_tau_train(spamm_tau_model* m, const float* dev_x, const float
         }
         if (host_loss) host_loss[ep] = (float)(loss / (double)count);
     }
+    raw_free(al, ws, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(ws);
     if (e != hipSuccess) return hip_error(e, "spamm_tau_train");
     return SPAMM_OK;
 }
@@ -382,8 +398,9 @@ spamm_status spamm_tau_predict(const spamm_matrix* A, const spamm_matrix* B, dou
                                const spamm_tau_model* m, void* stream, double* tau_out) {
     if (!A || !B || !m || !tau_out) return set_error(SPAMM_EINVAL, "null argument");
     hipStream_t s = (hipStream_t)stream;
-    float* buf = nullptr;
-    SPAMM_HIP(hipMalloc(&buf, (kIn + 16) * sizeof(float)));
+    const Allocator al = current_allocator();
+    float* buf = (float*)raw_alloc(al, (kIn + 16) * sizeof(float), s);
+    if (!buf) return set_error(SPAMM_ENOMEM, "tau workspace allocation failed");
     spamm_status r = spamm_tau_features(A, B, target, buf, stream);
     float yh = 0.0f;
     if (r == SPAMM_OK) r = spamm_tau_forward(m, buf, 1, buf + kIn, stream);
@@ -392,8 +409,8 @@ spamm_status spamm_tau_predict(const spamm_matrix* A, const spamm_matrix* B, dou
     if (r == SPAMM_OK) e = hipMemcpyAsync(&yh, buf + kIn, 4, hipMemcpyDeviceToHost, s);
     if (r == SPAMM_OK && e == hipSuccess) e = hipMemcpyAsync(&ra, A->norms + A->lvl_off[A->L], 8, hipMemcpyDeviceToHost, s);
     if (r == SPAMM_OK && e == hipSuccess) e = hipMemcpyAsync(&rb, B->norms + B->lvl_off[B->L], 8, hipMemcpyDeviceToHost, s);
+    raw_free(al, buf, s);
     if (r == SPAMM_OK && e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(buf);
     if (r != SPAMM_OK) return r;
     if (e != hipSuccess) return hip_error(e, "spamm_tau_predict");
     // tau = 10^y ||A||_F ||B||_F

@@ -95,7 +95,7 @@ def test_allocator_callbacks_outlive_reinstall():
 
 def test_set_allocator_requires_both_functions():
     L = _lib_or_skip()
-    alloc = sp._ALLOC_FN(lambda n, c: None)
+    alloc = sp._ALLOC_FN(lambda n, s, c: None)
     assert L.spamm_set_allocator(alloc, sp._DEALLOC_FN(), None) == 1
     assert L.spamm_set_allocator(sp._ALLOC_FN(), sp._DEALLOC_FN(), None) == 0
 

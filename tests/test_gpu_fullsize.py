@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 import spamm_inputs as si
+from gpu_util import check_row_many
 from oracle import sp2 as osp2
 
 pytestmark = pytest.mark.gpu
@@ -56,6 +57,34 @@ def test_workload_32768_task_list():
     print(f"  T={len(keys)}", flush=True)
 
 
+def test_workload_32768_sampled_rows():
+    # the same operand at tau = 1e-8: C tile row 300 (kept K of its tiles
+    # spread over both 256-K segments of the 512-K mask) with FP32 and FP16x3
+    # leaves against one oracle evaluation of that row
+    n, b, tau, I = 32768, 64, 1e-8, 300
+    print(f"[case] n={n} b={b} tau={tau} tile row {I}", flush=True)
+    Ad = sp.generate_decay(si.algebraic_table(n, 1.5), 5, 0.5, 1.5, False)
+    A = sp.build(Ad, b)
+    rs = slice(I * b, (I + 1) * b)
+    outs = {}
+    for prec in ("f32", "f16x3"):
+        C = sp.multiply(A, A, tau, prec)
+        outs[prec] = C.to_dense()[rs].cpu().numpy().copy()
+        if prec == "f32":
+            keys = C.task_list()
+        del C
+    Ii, Jj, Kk = oracle.unpack_keys(keys)
+    row = Ii == I
+    assert any(np.any(Kk[row & (Jj == j)] < 256) and np.any(Kk[row & (Jj == j)] >= 256) for j in range(512))
+    a64 = Ad.cpu().numpy().astype(np.float64)
+    del Ad, A
+    full = {p: np.zeros((n, n), np.float32) for p in outs}   # lazily touched: only row I is written
+    for p, o in outs.items():
+        full[p][rs] = o
+    worst = check_row_many(full, a64, b, tau, I)
+    print(f"  worst/bound {worst}", flush=True)
+
+
 def test_sp2_full_size_first_step():
     # SP2 at n = 16384, leaf 64, tau = 1e-6: step 0 from X_0 = (eps_max I - H) /
     # (eps_max - eps_min) built by the oracle (FP64, rounded to FP32): same task
@@ -98,8 +127,18 @@ def test_batched_full_64_task_lists():
     print(f"[case] batched 64 full, sum n^2 = {sum(n * n for n, _, _ in params):.3e}", flush=True)
     dense = [sp.generate_decay(si.exp_table(n, lam), useed, -1.0, 1.0, True) for n, lam, useed in params]
     hs = sp.build_batched(dense, 64)
+    # values: one C tile row of the largest, the smallest and two middle products
+    order = np.argsort([n for n, _, _ in params])
+    sample = [int(order[-1]), int(order[0]), int(order[20]), int(order[40])]
+    kept_dense = {m: dense[m].cpu().numpy().astype(np.float64) for m in sample}
     del dense
     Cs, sts = sp.multiply_batched(hs, hs, [1e-6] * len(hs), "f32", stats=True, schedule="list")
+    for m in sample:
+        a64 = kept_dense[m]
+        I = (a64.shape[0] // 64) // 2
+        w = check_row_many({"f32": Cs[m].to_dense().cpu().numpy()}, a64, 64, 1e-6, I)
+        print(f"  product {m} n={a64.shape[0]} row {I} worst/bound {w['f32']:.2e}", flush=True)
+    del kept_dense
     total = 0
     for (n, lam, useed), h, C, st in zip(params, hs, Cs, sts):
         S = h.norms(0)

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import spamm_inputs as si
-from gpu_util import elementwise_bound, to_dev
+from gpu_util import check_rows, elementwise_bound, to_dev
 
 pytestmark = pytest.mark.gpu
 sp = pytest.importorskip("paper_1011_3534_amd")
@@ -182,26 +182,105 @@ def test_precision_ladder_error_order():
 
 
 def test_workload_8192_task_list_and_sampled_rows():
-    # algebraic decay 1/(|i-j|^2+1), n = 8192, leaf 64, tau = 1e-6, FP32 leaves:
-    # full kept-triple list bit-exact, three C tile rows against the oracle
-    _case("n=8192 b=64 tau=1e-6 f32 full task list")
+    # algebraic decay 1/(|i-j|^2+1), n = 8192, leaf 64, tau = 1e-6: full
+    # kept-triple list bit-exact; C tile rows against the oracle with FP32 and
+    # FP16x3 leaves, the latter on the timed path (a view of the dense array,
+    # no statistics: the direct leaf pass) as well as on a packed operand
+    _case("n=8192 b=64 tau=1e-6 full task list, f32 and f16x3 rows")
     n, b, tau = 8192, 64, 1e-6
     a = si.algebraic_workload(n)
-    A = sp.build(to_dev(a), b)
+    ad = to_dev(a)
+    A = sp.build(ad, b)
     C, st = sp.multiply(A, A, tau, "f32", stats=True)
     a64 = a.astype(np.float64)
     S = oracle.tile_sqnorms(a64, b)
     assert np.array_equal(A.norms(0), S)
     keys, _ = oracle.tasks_flat(S, S, tau)
     assert np.array_equal(C.task_list(), keys)
+    rows = (0, 63, 127)
+    w32 = check_rows(C.to_dense().cpu().numpy(), a64, a64, b, tau, "f32", rows)
+    V = sp.build(ad, b, view=True)
+    CV = sp.multiply(V, V, tau, "f16x3")
+    assert np.array_equal(CV.task_list(), keys)
+    w16 = check_rows(CV.to_dense().cpu().numpy(), a64, a64, b, tau, "f16x3", rows)
+    CP = sp.multiply(A, A, tau, "f16x3")
+    assert sp.diff_norms(CP, CV)[0] == 0.0           # packed and view operands: the same bits
+    print(f"  T={st['tasks']} nonempty={st['nonempty_tiles']} worst/bound f32 {w32:.2e} f16x3 {w16:.2e}",
+          flush=True)
+
+
+@pytest.mark.parametrize("n,b,tau,p", [(8224, 32, 0.0, 2.0), (16448, 64, 1e-7, 1.5)])
+@pytest.mark.parametrize("prec", ["f32", "f16x3"])
+def test_multi_segment_tiles_match_oracle(n, b, tau, p, prec):
+    # nb = 257: a tile's kept K are listed 256 at a time (segments of four
+    # 64-bit mask words), and tiles whose kept K straddle K = 256 run two
+    # segments with the accumulator carried across.  At tau = 0 every tile
+    # keeps all 257 K; in the banded case the tiles near the middle of the
+    # matrix straddle the boundary.  Sampled C tile rows against the oracle.
+    _case(f"multi-segment n={n} b={b} tau={tau} p={p} {prec}")
+    a = sp.generate_decay(si.algebraic_table(n, p), 61, 0.5, 1.5, False)
+    A = sp.build(a, b)
+    assert A.nb == 257
+    C = sp.multiply(A, A, tau, prec)
+    a64 = a.cpu().numpy().astype(np.float64)
+    S = oracle.tile_sqnorms(a64, b)
+    keys, _ = oracle.tasks_flat(S, S, tau)
+    got = C.task_list()
+    assert np.array_equal(got, keys)
+    I, J, K = oracle.unpack_keys(keys)
+    rows = (0, 128, 255, 256) if tau == 0.0 else (250, 255, 256)
+    for r in rows:
+        sel = I == r
+        # each sampled row has a tile whose kept K lie on both sides of 256
+        assert any(np.any(K[sel & (J == j)] < 256) and np.any(K[sel & (J == j)] >= 256) for j in range(257))
     out = C.to_dense().cpu().numpy()
-    for I in (0, 63, 127):
-        ref, _ = oracle.spamm_flat(a64, a64, b, tau, rows=(I, I + 1))
-        absref, _ = oracle.spamm_flat(np.abs(a64), np.abs(a64), b, tau, rows=(I, I + 1))
-        rows = slice(I * b, (I + 1) * b)
-        err = np.abs(out[rows].astype(np.float64) - ref[rows])
-        assert np.all(err <= (n + 3) * 2.0 ** -24 * absref[rows] * 1.01)
-    print(f"  T={st['tasks']} nonempty={st['nonempty_tiles']}", flush=True)
+    worst = check_rows(out, a64, a64, b, tau, prec, rows)
+    print(f"  T={len(keys)} worst/bound {worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("n,b,tau,prec,fam,depth", [
+    (1024, 32, 1e-6, "f64", "exp", False), (1000, 64, 1e-6, "f32", "alg", False),
+    (900, 64, 1e-4, "f16x3", "alg", False), (2048, 64, 1e-7, "f32", "alg", False),
+    (450, 32, 1e-3, "f32", "alg", True), (1024, 32, 1e-4, "f64", "exp", True)])
+def test_culled_bound_matches_oracle(n, b, tau, prec, fam, depth):
+    # the statistic culled_bound: the sum over the octree nodes the descent
+    # culls (any tier, root included) of ||A^k||_F ||B^k||_F (Eq. 3), against
+    # the oracle recursion's own sum; FP64 atomics add in any order
+    _case(f"culled bound n={n} b={b} tau={tau} depth={depth}")
+    a, bm = _operands(n, fam, prec == "f64" and fam == "exp")
+    A, B = sp.build(to_dev(a), b), sp.build(to_dev(bm), b)
+    _, st = sp.multiply(A, B, tau, prec, stats=True, depth_scaled=depth)
+    SA = oracle.tile_sqnorms(a.astype(np.float64), b)
+    SB = oracle.tile_sqnorms(bm.astype(np.float64), b)
+    T, kept, bound = oracle.count_hierarchical(SA, SB, tau, depth_scaled=depth, want_bound=True)
+    assert st["tasks"] == T and st["survivors"] == kept.tolist()
+    assert abs(st["culled_bound"] - bound) <= 1e-12 * bound
+    if not depth:
+        # Eq. (3): the omitted part of the product lies below the bound
+        E = sp.multiply(A, B, 0.0, "f64")
+        C = sp.multiply(A, B, tau, "f64")
+        d2, _ = sp.diff_norms(C, E)
+        assert np.sqrt(d2) <= bound * (1 + 1e-12)
+    print(f"  T={T} bound={bound:.6e}", flush=True)
+
+
+def test_reused_output_after_nan_tile():
+    # a result tile that held only NaN must not pass for a known-zero tile:
+    # a later product with no kept product there rewrites it with zeros
+    _case("reused C after an all-NaN tile")
+    n, b = 256, 64
+    a = np.zeros((n, n), np.float32)
+    a[:b, :b] = np.nan
+    A = sp.build(to_dev(a), b)
+    E = sp.build(to_dev(np.eye(n, dtype=np.float32)), b)
+    for prec in ("f32", "f16x3"):
+        C = sp.multiply(A, E, 0.0, prec)                 # C tile row 0: NaN * 0 = NaN everywhere
+        first = C.to_dense().cpu().numpy()
+        assert np.all(np.isnan(first[:b])) and not np.any(first[b:])
+        Z = sp.build(to_dev(np.zeros((n, n), np.float32)), b)
+        sp.multiply(Z, Z, 1e-6, prec, out=C)             # no kept product anywhere
+        assert not np.any(C.to_dense().cpu().numpy())
+        assert not np.any(C.norms(0))
 
 
 # ------------------------------------------------------------------ edge cases

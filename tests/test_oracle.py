@@ -249,6 +249,91 @@ def test_error_below_culled_norm_bound(tau):
     assert err > 0
 
 
+def _block_constant(alpha, b):
+    """Matrix whose b x b tile (I, K) is alpha[I, K] * ones: its squared tile
+    norm is alpha^2 b^2, exact for powers of two."""
+    return np.kron(alpha, np.ones((b, b)))
+
+
+def test_flat_culled_bound_exact_on_block_constant_operands():
+    # Eq. (3) summed over culled leaf triples: sum |alpha_IK| |beta_KJ| b^2 over
+    # the triples with alpha^2 beta^2 b^4 < tau^2.  Powers of two make every norm,
+    # square root and sum exact.  Catches: the bound summing S_A S_B (squared)
+    # or sqrt(S_A + S_B), an (I,K)/(K,J) index mix-up, kept triples counted in.
+    rng = np.random.default_rng(21)
+    nb, b = 9, 16
+    alpha = 2.0 ** rng.integers(-10, 1, (nb, nb)) * rng.choice([-1.0, 1.0], (nb, nb))
+    beta = 2.0 ** rng.integers(-10, 1, (nb, nb)) * rng.choice([-1.0, 1.0], (nb, nb))
+    alpha[rng.random((nb, nb)) < 0.2] = 0.0
+    a, bm = _block_constant(alpha, b), _block_constant(beta, b)
+    for tau in (2.0 ** -3, 2.0 ** -7, 2.0 ** -12):
+        prod = (alpha[:, :, None] ** 2) * (beta[None, :, :] ** 2) * b ** 4      # [I, K, J]
+        culled = prod < tau * tau
+        ref = float(np.sum((np.abs(alpha)[:, :, None] * np.abs(beta)[None, :, :] * b * b)[culled]))
+        keys, bound = oracle.tasks_flat(oracle.tile_sqnorms(a, b), oracle.tile_sqnorms(bm, b), tau)
+        assert bound == ref
+        assert len(keys) == int(np.sum(~culled))
+
+
+def test_culled_bounds_hand_computed_block_case():
+    # nb = 4 tiles of 16: a big 2x2-tile block of ones and a small one of
+    # 2^-6 on the diagonal, zeros elsewhere (A = B).  At tau = 1 the recursion
+    # culls the tier-1 node of the small block whole (its norm product is
+    # 0.25 * 0.25 < 1) while every leaf triple of the big block passes
+    # (2^8 * 2^8 >= 1).  Omitted product: (2^-6 J_32)^2 = 2^-7 J_32, Frobenius
+    # norm 2^-7 * 32 = 0.25.  Culled-node bound = sqrt(0.25) sqrt(0.25) = 0.25
+    # (tight); culled-triple bound = 8 triples * 2^-4 = 0.5.
+    b = 16
+    alpha = np.zeros((4, 4))
+    alpha[:2, :2] = 1.0
+    alpha[2:, 2:] = 2.0 ** -6
+    a = _block_constant(alpha, b)
+    S = oracle.tile_sqnorms(a, b)
+    T, kept, hbound = oracle.count_hierarchical(S, S, 1.0, want_bound=True)
+    assert hbound == 0.25
+    assert T == 8 and kept.tolist() == [8, 1, 1]
+    _, fbound = oracle.tasks_flat(S, S, 1.0)
+    assert fbound == 0.5
+    c, _, _, _ = oracle.spamm_recursive(a, a, b, 1.0)
+    assert np.linalg.norm(c - a @ a) == 0.25
+
+
+def test_culled_node_bound_limits():
+    # root culled: the bound is ||A||_F ||B||_F; no node above the leaves
+    # culled: the node bound is the triple bound (the same culled triples).
+    # Catches: the root test skipped, culled upper nodes not added, a leaf
+    # triple under a culled node counted again.
+    n, b = 256, 16
+    a = si.algebraic_decay(n, 2.0, 5, np.float64)
+    bm = si.algebraic_decay(n, 1.5, 6, np.float64)
+    SA, SB = oracle.tile_sqnorms(a, b), oracle.tile_sqnorms(bm, b)
+    T, kept, hb = oracle.count_hierarchical(SA, SB, 1e6, want_bound=True)
+    assert T == 0 and kept.sum() == 0
+    ref = np.linalg.norm(a) * np.linalg.norm(bm)
+    assert abs(hb - ref) <= 1e-13 * ref
+    # the smallest norm product of any node above the leaves (from numpy block sums)
+    upper = []
+    m = SA
+    mb = SB
+    while m.shape[0] > 1:
+        k = m.shape[0]
+        pad = -(-k // 2) * 2
+        ma, mbb = np.zeros((pad, pad)), np.zeros((pad, pad))
+        ma[:k, :k], mbb[:k, :k] = m, mb
+        m = ma.reshape(pad // 2, 2, pad // 2, 2).sum(axis=(1, 3))
+        mb = mbb.reshape(pad // 2, 2, pad // 2, 2).sum(axis=(1, 3))
+        upper.append(np.min(m[:, :, None] * mb[None, :, :]))
+    leaf_min = np.min(SA[:, :, None] * SB[None, :, :])
+    tau2 = 0.5 * (min(upper) + leaf_min) if min(upper) > leaf_min else None
+    assert tau2 is not None
+    tau = float(np.sqrt(tau2))
+    T, kept, hb = oracle.count_hierarchical(SA, SB, tau, want_bound=True)
+    assert all(kept[l] == (-(-SA.shape[0] // 2 ** l)) ** 3 for l in range(1, len(kept)))
+    keys, fb = oracle.tasks_flat(SA, SB, tau)
+    assert T == len(keys) < SA.shape[0] ** 3
+    assert abs(hb - fb) <= 1e-13 * fb
+
+
 def test_nested_in_tau_and_monotone_error():
     n, b = 256, 16
     a = si.algebraic_decay(n, 2.0, 6, np.float64)
