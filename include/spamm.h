@@ -293,6 +293,31 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
                                     spamm_leaf_prec prec, const spamm_tune* tune, void* stream,
                                     spamm_matrix** C, spamm_stats* st);
 
+/* spamm_multiply_batched for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same cull, schedule and leaf kernels, with the batch
+ * scratch (descriptors, counters, schedule arrays) in a static 16 MiB
+ * device array of the library -- one per device, kept until the process
+ * ends.  It calls no allocator: no hipMalloc, hipFree or allocator hook.
+ *   C[m]   : existing result handles (same n, leaf and result type as for
+ *            spamm_multiply_batched), each of which has already received a
+ *            product, so that its own product scratch is in place; the
+ *            handles are overwritten, the array itself is not written
+ *   other arguments as spamm_multiply_batched; no statistics.
+ * Limits: at most 2^27 leaf triples over the batch (sum of nb^3: the direct
+ * leaf pass, no frontier) and a batch plan within 16 MiB.
+ * Every call on a device shares that device's array and leaves its contents
+ * behind; calls that overlap on one device (different streams or host
+ * threads with no ordering between them) race.  Calls on one stream are
+ * ordered and safe.
+ * Errors: EINVAL as spamm_multiply_batched, also for a NULL C[m], a handle
+ * with no product scratch or on another device than the current one;
+ * ECAPACITY beyond the limits (nothing enqueued); EHIP. */
+spamm_status spamm_multiply_batched_noalloc(int32_t count, const spamm_matrix* const* A,
+                                            const spamm_matrix* const* B, const double* tau,
+                                            spamm_leaf_prec prec, const spamm_tune* tune, void* stream,
+                                            spamm_matrix* const* C);
+
 /* ------------------------------------------------------------------ autotuner */
 
 #define SPAMM_TUNE_MAX_LEAVES 3

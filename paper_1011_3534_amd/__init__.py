@@ -132,6 +132,8 @@ def lib():
         "spamm_multiply_timed": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Timing)], i32),
         "spamm_multiply_batched": ([i32, PP, PP, ctypes.POINTER(dbl), i32, ctypes.POINTER(Tune), _VP, PP,
                                     ctypes.POINTER(Stats)], i32),
+        "spamm_multiply_batched_noalloc": ([i32, PP, PP, ctypes.POINTER(dbl), i32, ctypes.POINTER(Tune), _VP,
+                                            PP], i32),
         "spamm_sp2_ex": ([_VP, i64, dbl, i32, dbl, i32, i32, _VP, PP, ctypes.POINTER(Sp2Log)], i32),
         "spamm_sp2": ([_VP, i64, dbl, i32, dbl, i32, _VP, PP, ctypes.POINTER(Sp2Log)], i32),
         "spamm_autotune_batched": ([i32, PP, ctypes.POINTER(i64), i32, ctypes.POINTER(dbl), i32,
@@ -414,6 +416,25 @@ def multiply_batched(As, Bs, taus, prec: str = "f32", outs=None, stats: bool = F
         else:
             Cs.append(Matrix(ctypes.c_void_p(PC[m])))
     return (Cs, [s.to_dict() for s in st]) if stats else Cs
+
+
+def multiply_batched_noalloc(As, Bs, taus, outs, prec: str = "f32", schedule: str | None = None, stream=None):
+    """multiply_batched into existing results, with no device allocation: the
+    batch scratch is the library's static per-device array, so calls that
+    overlap on one device race.  Every outs[m] must be a result handle that
+    has already received a product; returns outs."""
+    count = len(As)
+    PA = (ctypes.c_void_p * count)(*[a.handle.value for a in As])
+    PB = (ctypes.c_void_p * count)(*[b.handle.value for b in Bs])
+    PC = (ctypes.c_void_p * count)(*[o.handle.value for o in outs])
+    T = (ctypes.c_double * count)(*[float(t) for t in taus])
+    tune = None
+    if schedule is not None:
+        tune = Tune()
+        tune.schedule = SCHEDULE[schedule]
+    _check(lib().spamm_multiply_batched_noalloc(count, PA, PB, T, LEAF[prec], ctypes.byref(tune) if tune else None,
+                                                _stream(stream), PC))
+    return list(outs)
 
 
 def autotune_batched(dense, taus, prec: str = "f32", leaves=(32, 64, 128), max_rel_err: float = 1e-5,

@@ -788,12 +788,40 @@ const char* spamm_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
 
-extern "C" {
+namespace spamm {
+namespace {
 
-spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A, const spamm_matrix* const* B,
-                                    const double* tau, spamm_leaf_prec prec, const spamm_tune* tune, void* stream,
-                                    spamm_matrix** C, spamm_stats* st) {
-    using namespace spamm;
+// Batch scratch of spamm_multiply_batched_noalloc: one copy per device, held
+// until the process ends.  In host code `scratch` is only a stand-in for the
+// symbol; the device address comes from hipGetSymbolAddress, once per device,
+// and is what kernels and copies receive.
+constexpr size_t kStaticScratchBytes = (size_t)16 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+spamm_status static_scratch_ptr(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return set_error(SPAMM_EUNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return set_error(SPAMM_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SPAMM_OK;
+}
+
+// count products in one cull and one leaf launch.  fixed: the batch scratch
+// is the device's static array (no allocation; every C[m] must already hold
+// its product scratch, no statistics, the direct leaf pass only); otherwise
+// it comes from the allocator and is released, stream-ordered, at the end.
+spamm_status multiply_batched_impl(int32_t count, const spamm_matrix* const* A, const spamm_matrix* const* B,
+                                   const double* tau, spamm_leaf_prec prec, const spamm_tune* tune, void* stream,
+                                   spamm_matrix** C, spamm_stats* st, bool fixed) {
     if (count < 1 || count > kMaxBatch) return set_error(SPAMM_EINVAL, "count outside [1, 128]");
     if (!A || !B || !tau || !C) return set_error(SPAMM_EINVAL, "null argument");
     if (!A[0]) return set_error(SPAMM_EINVAL, "null operand");
@@ -803,7 +831,19 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
         return set_error(SPAMM_EINVAL, "unknown schedule");
     if (tune && tune->leaf && tune->leaf != b) return set_error(SPAMM_EINVAL, "tune->leaf differs from the operands");
     const spamm_dtype cdt = prec == SPAMM_LEAF_F64 ? SPAMM_F64 : SPAMM_F32;
+    int dev = 0;
+    if (fixed) {
+        if (st) return set_error(SPAMM_EINVAL, "the allocation-free product fills no statistics");
+        hipError_t ge = hipGetDevice(&dev);
+        if (ge != hipSuccess) return hip_error(ge, "hipGetDevice");
+    }
     for (int m = 0; m < count; ++m) {
+        if (fixed) {
+            if (!C[m] || !C[m]->ps)
+                return set_error(SPAMM_EINVAL, "the allocation-free product needs every C[m] to be a result handle "
+                                               "that has received a product (its product scratch in place)");
+            if (C[m]->device != dev) return set_error(SPAMM_EINVAL, "C[m] lives on another device than the current one");
+        }
         spamm_status v = check_operands(A[m], B[m], tau[m], prec);
         if (v != SPAMM_OK) return v;
         if (A[m]->b != b) return set_error(SPAMM_EINVAL, "products of one batch share the leaf size");
@@ -818,8 +858,8 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
         }
     }
     hipStream_t s = (hipStream_t)stream;
-    std::vector<spamm_matrix*> out(count, nullptr);
-    std::vector<bool> fresh(count, false);
+    spamm_matrix* out[kMaxBatch] = {};
+    bool fresh[kMaxBatch] = {};
     spamm_status r = SPAMM_OK;
     auto release_fresh = [&]() {
         for (int m = 0; m < count; ++m)
@@ -847,11 +887,9 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
     const int kind = split_kind(prec);
     bool presplit = kind >= 0;
     for (int m = 0; m < count; ++m) presplit = presplit && split_current(A[m], kind) && split_current(B[m], kind);
-    static thread_local std::vector<ProdDesc> hd;
-    hd.assign(count, ProdDesc{});
+    static thread_local ProdDesc hd[kMaxBatch];
     for (int m = 0; m < count; ++m) {
         spamm_matrix* Cm = out[m];
-        Cm->gen++;
         hd[m] = make_desc(A[m], B[m], Cm, tau[m]);
         hd[m].tile_base = total;
         total += Cm->nb * Cm->nb;
@@ -863,8 +901,8 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
     for (int l = 0; l < kMaxLevels; ++l) items[l] = std::min(items[l], cap);
     // without statistics the flat rule needs no tier above the leaves: up to
     // 2^27 leaf triples in all, every triple is tested in one pass
-    static thread_local std::vector<int64_t> hblk;
-    hblk.assign(count + 1, 0);
+    static thread_local int64_t hblk[kMaxBatch + 1];
+    hblk[0] = 0;
     int64_t triples = 0;
     for (int m = 0; m < count; ++m) {
         const int64_t nbm = out[m]->nb;
@@ -872,24 +910,38 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
         hblk[m + 1] = hblk[m] + nbm * ceil_div(nbm, 64);
     }
     const bool direct = st == nullptr && triples <= ((int64_t)1 << 27);
+    if (fixed && !direct)
+        return set_error(SPAMM_ECAPACITY, "the allocation-free product takes at most 2^27 leaf triples in all "
+                                          "(sum of nb^3 over the batch)");
+    // the frontiers are read only by the descent
+    const int64_t fcap = direct ? 0 : cap;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t o_desc = 0, o_f0 = al(sizeof(ProdDesc) * count), o_f1 = o_f0 + al((size_t)cap * 8),
-                 o_ctr = o_f1 + al((size_t)cap * 8), o_cnt = o_ctr + al(sizeof(DevCounters) + 16 * kMaxBatch),
+    const size_t o_desc = 0, o_f0 = al(sizeof(ProdDesc) * count), o_f1 = o_f0 + al((size_t)fcap * 8),
+                 o_ctr = o_f1 + al((size_t)fcap * 8), o_cnt = o_ctr + al(sizeof(DevCounters) + 16 * kMaxBatch),
                  o_ord = o_cnt + al((size_t)total * 4), o_hist = o_ord + al((size_t)total * 4),
                  o_offs = o_hist + al((size_t)(maxc + 1) * 4), o_q = o_offs + al((size_t)(maxc + 1) * 4),
                  o_tab = o_q + 256, o_blk = o_tab + al(sizeof(NormTable) * 2 * count),
                  bytes = o_blk + al(sizeof(int64_t) * (count + 1));
     spamm_matrix* owner = out[0];
-    char* ws = (char*)dev_alloc(owner, bytes, s);
-    if (!ws) {
-        release_fresh();
-        return set_error(SPAMM_ENOMEM, "batch scratch allocation failed");
+    char* ws = nullptr;
+    if (fixed) {
+        if (bytes > kStaticScratchBytes)
+            return set_error(SPAMM_ECAPACITY, "batch plan exceeds the static scratch (16 MiB)");
+        spamm_status r2 = static_scratch_ptr(dev, (void**)&ws);
+        if (r2 != SPAMM_OK) return r2;
+    } else {
+        ws = (char*)dev_alloc(owner, bytes, s);
+        if (!ws) {
+            release_fresh();
+            return set_error(SPAMM_ENOMEM, "batch scratch allocation failed");
+        }
     }
     ProdDesc* d_desc = (ProdDesc*)(ws + o_desc);
     DevCounters* ctr = (DevCounters*)(ws + o_ctr);
     for (int m = 0; m < count; ++m) {
         hd[m].nonempty = nonempty_ctr(ctr) + m;
         out[m]->ps->desc_valid = false;
+        out[m]->gen++;
     }
     CullPlan cp;
     cp.count = count;
@@ -915,7 +967,7 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
         lp.list_count = (unsigned*)(ws + o_q);
         lp.list_queue = (unsigned*)(ws + o_q + 64);
     }
-    hipError_t e = hipMemcpyAsync(d_desc, hd.data(), sizeof(ProdDesc) * count, hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(d_desc, hd, sizeof(ProdDesc) * count, hipMemcpyHostToDevice, s);
     if (!direct) {
         // the descent reads the operands' upper tiers: the missing ones of
         // all operands in one launch per tier
@@ -941,7 +993,7 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
     if (direct) {
         const int64_t* d_blk = (const int64_t*)(ws + o_blk);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(ws + o_blk, hblk.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s);
+            e = hipMemcpyAsync(ws + o_blk, hblk, sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = launch_cull_leaf_batched(d_desc, count, d_blk, hblk[count], s);
     } else {
         if (e == hipSuccess) e = launch_clear_masks(d_desc, count, s);
@@ -984,13 +1036,33 @@ spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A,
             if (r == SPAMM_OK) r = check_finite(B[m], s, "an operand B[m]");
         }
     }
-    dev_free(owner, ws, s);
+    if (!fixed) dev_free(owner, ws, s);
     if (e != hipSuccess) {
         release_fresh();
-        return hip_error(e, "spamm_multiply_batched");
+        return hip_error(e, fixed ? "spamm_multiply_batched_noalloc" : "spamm_multiply_batched");
     }
-    for (int m = 0; m < count; ++m) C[m] = out[m];
+    if (!fixed)
+        for (int m = 0; m < count; ++m) C[m] = out[m];
     return r;
+}
+
+}  // namespace
+}  // namespace spamm
+
+extern "C" {
+
+spamm_status spamm_multiply_batched(int32_t count, const spamm_matrix* const* A, const spamm_matrix* const* B,
+                                    const double* tau, spamm_leaf_prec prec, const spamm_tune* tune, void* stream,
+                                    spamm_matrix** C, spamm_stats* st) {
+    return spamm::multiply_batched_impl(count, A, B, tau, prec, tune, stream, C, st, false);
+}
+
+spamm_status spamm_multiply_batched_noalloc(int32_t count, const spamm_matrix* const* A,
+                                            const spamm_matrix* const* B, const double* tau, spamm_leaf_prec prec,
+                                            const spamm_tune* tune, void* stream, spamm_matrix* const* C) {
+    if (!C) return spamm::set_error(SPAMM_EINVAL, "null argument");
+    return spamm::multiply_batched_impl(count, A, B, tau, prec, tune, stream, const_cast<spamm_matrix**>(C),
+                                        nullptr, true);
 }
 
 spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t max_iter, double idem_tol,
