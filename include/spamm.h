@@ -184,6 +184,20 @@ spamm_status spamm_build_ex(const void* dev_a, int64_t n, int64_t lda, spamm_dty
 spamm_status spamm_build_view(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf,
                               void* stream, spamm_matrix** out);
 
+/* spamm_build_view for operands of products with leaf precision `prec`: no
+ * copy of the FP32 tiles, but for the 16-bit precisions the handle owns
+ * split hi/lo tiles of the array, written as in spamm_build_ex (4 bytes per
+ * element, tile-major).  The leaf products read the split tiles instead of
+ * the array, so the build costs one pass that reads the array and writes the
+ * split tiles, and every product of the handle skips the split.  Products
+ * are the same bits as those of spamm_build_view operands.  For the FP32 and
+ * FP64 precisions it is spamm_build_view.
+ *   out  : in/out as for spamm_build_view (a rebuild refreshes the split)
+ * Errors: as spamm_build_view; EINVAL for an unknown prec; EUNSUPPORTED for
+ * a 16-bit prec with FP64 input. */
+spamm_status spamm_build_view_ex(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf,
+                                 spamm_leaf_prec prec, void* stream, spamm_matrix** out);
+
 /* spamm_build_view of count matrices, one launch for all leaf norms and one
  * per upper tier, as spamm_build_batched.  Arguments, errors and the
  * no-change-on-error rule as spamm_build_batched, with the view conditions

@@ -126,6 +126,7 @@ def lib():
         "spamm_build_ex": ([_VP, i64, i64, i32, i32, i32, _VP, PP], i32),
         "spamm_build_batched": ([i32, _VP, _VP, _VP, i32, i32, _VP, _VP], i32),
         "spamm_build_view": ([_VP, i64, i64, i32, i32, _VP, PP], i32),
+        "spamm_build_view_ex": ([_VP, i64, i64, i32, i32, i32, _VP, PP], i32),
         "spamm_build_view_batched": ([i32, _VP, _VP, _VP, i32, i32, _VP, _VP], i32),
         "spamm_multiply": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Stats)], i32),
         "spamm_multiply_ex": ([_VP, _VP, dbl, i32, i32, _VP, PP, ctypes.POINTER(Stats)], i32),
@@ -299,7 +300,8 @@ def build(a, leaf: int, out: Matrix | None = None, stream=None, prec: str | None
     prec naming a 16-bit leaf precision the same pass also writes the split
     hi/lo tiles those products read (spamm_build_ex).  With view=True the
     handle reads its tiles from `a` itself (spamm_build_view: norms only, no
-    copy); it keeps a reference to `a`, which must not change while in use."""
+    copy; with prec, spamm_build_view_ex also writes the split tiles); it
+    keeps a reference to `a`, which must not change while in use."""
     import torch
     if not (a.is_cuda and a.dim() == 2 and a.shape[0] == a.shape[1]):
         raise ValueError("build expects a square CUDA tensor")
@@ -310,10 +312,12 @@ def build(a, leaf: int, out: Matrix | None = None, stream=None, prec: str | None
     h = ctypes.c_void_p(out.handle.value if out is not None else None)
     dt = 0 if a.dtype == torch.float64 else 1
     if view:
-        if prec is not None:
-            raise ValueError("a view has no split tiles (prec applies to packed builds)")
-        _check(lib().spamm_build_view(ctypes.c_void_p(a.data_ptr()), a.shape[0], a.stride(0), dt, leaf,
-                                      _stream(stream), ctypes.byref(h)))
+        if prec is None:
+            _check(lib().spamm_build_view(ctypes.c_void_p(a.data_ptr()), a.shape[0], a.stride(0), dt, leaf,
+                                          _stream(stream), ctypes.byref(h)))
+        else:
+            _check(lib().spamm_build_view_ex(ctypes.c_void_p(a.data_ptr()), a.shape[0], a.stride(0), dt, leaf,
+                                             LEAF[prec], _stream(stream), ctypes.byref(h)))
         if out is not None:
             out.source = a
             return out

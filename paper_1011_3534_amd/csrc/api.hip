@@ -448,7 +448,7 @@ spamm_status build_single(const void* dev_a, int64_t n, int64_t lda, spamm_dtype
         spamm_status v = check_view(dev_a, n, lda, dt, leaf);
         if (v != SPAMM_OK) return v;
     }
-    const int kind = view ? -1 : split_kind(prec);
+    const int kind = split_kind(prec);
     if (kind >= 0 && dt != SPAMM_F32)
         return set_error(SPAMM_EUNSUPPORTED, "16-bit leaf precisions take FP32 tiles");
     hipStream_t s = (hipStream_t)stream;
@@ -597,6 +597,11 @@ spamm_status spamm_build_view(const void* dev_a, int64_t n, int64_t lda, spamm_d
                               void* stream, spamm_matrix** out) {
     return build_single(dev_a, n, lda, dt, leaf, dt == SPAMM_F64 ? SPAMM_LEAF_F64 : SPAMM_LEAF_F32, true, stream,
                         out);
+}
+
+spamm_status spamm_build_view_ex(const void* dev_a, int64_t n, int64_t lda, spamm_dtype dt, int32_t leaf,
+                                 spamm_leaf_prec prec, void* stream, spamm_matrix** out) {
+    return build_single(dev_a, n, lda, dt, leaf, prec, true, stream, out);
 }
 
 spamm_status spamm_build_batched(int32_t count, const void* const* dev_a, const int64_t* n, const int64_t* lda,

@@ -375,6 +375,180 @@ __device__ inline void chunk_mma(const char* buf, Acc (&acc)[Geo<B, P>::R][Geo<B
     }
 }
 
+// Split 16-bit operands at leaf 64 go from memory straight into LDS
+// (buffer loads with an LDS destination: no registers, no arithmetic) through
+// a ring of NS stages, each holding one 32-wide k-chunk of A_IK (64 rows x 32
+// k) and of B_KJ (32 k-rows x 64 columns) for hi and lo.  Each wave issues the
+// PW 1 KiB loads of one array of a stage; the ring keeps NS - 1 stages in
+// flight.  Two stages and four blocks per CU measured best (more stages cost
+// blocks per CU, which hide more of each tile's latency chain).  B stays row-major in LDS: its MFMA fragments (8 consecutive k of
+// one column per lane) come from the transposing 16-bit LDS read, which hands
+// lane j of each 16-lane group element j % 4 of what lane 4e + j / 4 read, so
+// lane i of a group reads row i / 4 of a 4-row slab at columns 4 (i % 4).
+template <int B, int P, bool PS>
+struct Dma {
+    static constexpr bool ON = PS && B == 64 && is16(P);
+    static constexpr int NARR = isx3(P) ? 2 : 1;
+    static constexpr int ARR = 4096;                 // bytes of one array's chunk
+    static constexpr int STAGE = 2 * NARR * ARR;     // A arrays, then B arrays
+    static constexpr int NS = 2;
+    static constexpr int PW = STAGE / 1024 / 4;      // 1 KiB loads per wave per stage
+    static constexpr int SMEM = NS * STAGE;
+};
+
+template <int B, int P, bool PS>
+constexpr int leaf_smem() {
+    return Dma<B, P, PS>::ON ? (Dma<B, P, PS>::SMEM > Geo<B, P>::C_BYTES ? Dma<B, P, PS>::SMEM : Geo<B, P>::C_BYTES)
+                             : Geo<B, P>::SMEM;
+}
+
+// LDS slots (16 bytes) of a stage.  A rows hold 4 slots (32 k); slot s of
+// row r sits at s ^ dqa(r), so the 16 rows of an A fragment read spread over
+// all banks.  B rows hold 8 slots (64 columns); slot s of row k sits at
+// s ^ dfb(k), so the 8 rows of one 32-lane half of a transposing read (rows
+// k..k+3 and k+8..k+11) hit disjoint banks.
+__device__ inline int dqa(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & 1); }
+__device__ inline int dfb(int k) { return (((k >> 1) & 1) | (((k >> 3) & 1) << 1)) << 1; }
+
+// Byte offset, inside a tile chunk, of the 16 bytes that land at position p
+// of the array's LDS chunk (p = 64 * load + lane).
+template <bool IS_A>
+__device__ inline uint32_t dma_src(int p) {
+    if constexpr (IS_A) {
+        const int r = p >> 2, sl = (p & 3) ^ dqa(r);
+        return (uint32_t)((r * 64 + sl * 8) * 2);
+    } else {
+        const int k = p >> 3, sl = (p & 7) ^ dfb(k);
+        return (uint32_t)((k * 64 + sl * 8) * 2);
+    }
+}
+
+// MFMA accumulation of one stage (the same products in the same order as
+// chunk_mma, so the results are the same bits).
+template <int P, typename Acc>
+__device__ inline void stage_mma(const char* __restrict__ st, Acc (&acc)[2][2], int lane, int wr, int wc) {
+    constexpr int NARR = isx3(P) ? 2 : 1, ARR = 4096;
+    using V8 = typename std::conditional<P == kBF16 || P == kBF16X3, bf16x8, f16x8>::type;
+    typedef short s16x4 __attribute__((ext_vector_type(4)));
+    const int g = lane >> 4, i16 = lane & 15;
+    V8 ah[2], bh[2], al[2], bl[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int r = wr * 32 + 16 * i + i16;
+        const int off = (r * 4 + (g ^ dqa(r))) * 16;
+        ah[i] = *reinterpret_cast<const V8*>(st + off);
+        if constexpr (NARR == 2) al[i] = *reinterpret_cast<const V8*>(st + ARR + off);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int n = wc * 32 + 16 * j + 4 * (i16 & 3);
+        s16x4 h2[2], l2[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = 8 * g + 4 * h + (i16 >> 2);
+            const int off = (k * 8 + ((n >> 3) ^ dfb(k))) * 16 + (n & 7) * 2;
+            h2[h] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((LDSP s16x4*)(st + NARR * ARR + off));
+            if constexpr (NARR == 2)
+                l2[h] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((LDSP s16x4*)(st + (NARR + 1) * ARR + off));
+        }
+        bh[j] = __builtin_bit_cast(V8, __builtin_shufflevector(h2[0], h2[1], 0, 1, 2, 3, 4, 5, 6, 7));
+        if constexpr (NARR == 2)
+            bl[j] = __builtin_bit_cast(V8, __builtin_shufflevector(l2[0], l2[1], 0, 1, 2, 3, 4, 5, 6, 7));
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if constexpr (P == kBF16 || P == kBF16X3) {
+                if constexpr (NARR == 2) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                }
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            } else {
+                if constexpr (NARR == 2) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                }
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            }
+        }
+}
+
+// s_waitcnt with vmcnt = v (lgkmcnt = 0, expcnt untouched): the wave's own
+// LDS reads are done and at most v of its memory loads are outstanding.
+template <int V>
+__device__ inline void wait_vm_lgkm0() {
+    static_assert(V >= 0 && V < 64, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt((V & 15) | ((V >> 4) << 14) | (0x7 << 4));
+}
+
+// Undo the FP16 scales of the product ending at step t (when t is its last
+// chunk) and add its fresh sum to the tile sum: the finish of leaf_tile.
+template <int P, int NCH, typename Acc>
+__device__ __forceinline__ void finish_product(const KList* __restrict__ kl, int t, Acc (&part)[2][2],
+                                               Acc (&acc)[2][2]) {
+    if (t % NCH != NCH - 1) return;
+    if constexpr (isf16(P)) {
+        const int un = __builtin_amdgcn_readfirstlane(-((int)kl->sa[t / NCH] + (int)kl->sb[t / NCH]));
+        if (un >= -126 && un <= 127) {
+            const float f = ldexpf(1.0f, un);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[i][j][q] = __builtin_fmaf(part[i][j][q], f, acc[i][j][q]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[i][j][q] += ldexpf(part[i][j][q], un);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] += part[i][j];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) part[i][j] = Acc{0, 0, 0, 0};
+}
+
+// One step of the direct-to-LDS pipeline: issue this wave's loads of step
+// t + NS - 1 into stage `nxt` (past the last step: empty resources, which
+// load nothing), then, for t >= 0, the MFMA of stage `cur` and the finish of
+// a product.  The restrict qualifiers tell the compiler that the stage being
+// read, the stage being loaded and the K list are disjoint, so it adds no
+// wait of its own for the loads in flight; the caller's wait and barrier
+// order each stage's loads before its reads.
+template <int P, int NCH, int PW, typename Acc>
+__device__ __forceinline__ void dma_step(const char* __restrict__ cur, char* __restrict__ nxt,
+                                         const KList* __restrict__ kl, int t, int T, int NS,
+                                         const uint16_t* __restrict__ base16, bool isA, int64_t I, int64_t J, int64_t nb,
+                                         const uint32_t (&voff)[PW], Acc (&part)[2][2], Acc (&acc)[2][2],
+                                         int lane, int wr, int wc) {
+    const int ti = t + NS - 1;
+    const bool live = ti < T;
+    const int tt = live ? ti : T - 1;
+    const int k = __builtin_amdgcn_readfirstlane(kl->k[tt / NCH]);
+    const int ch = tt % NCH;
+    const int64_t tile = isA ? I * nb + k : (int64_t)k * nb + J;
+    const uint32_t coff = isA ? (uint32_t)ch * 64u : (uint32_t)ch * 4096u;
+    const __amdgpu_buffer_rsrc_t r = rsrc((const char*)(base16 + tile * 4096) + coff, live ? 8192u - coff : 0u);
+#pragma unroll
+    for (int q = 0; q < PW; ++q)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (LDSP void*)(nxt + q * 1024), 16, voff[q], 0, 0, 0);
+    if (t >= 0) {
+        stage_mma<P, Acc>(cur, part, lane, wr, wc);
+        finish_product<P, NCH, Acc>(kl, t, part, acc);
+    }
+}
+
 // One C tile from its kept K to its stored values and norm.  t is a global
 // schedule position (blocked = true: panel/block order inside each product)
 // or a global tile index (blocked = false: row-major).
@@ -437,6 +611,16 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             pre[j] = nk;
             nk += __popcll(wd[j]);
         }
+        // the FP16 scale exponents of every candidate K of this wave's word,
+        // loaded with the mask words (one round trip instead of two)
+        const int kc = (w0 + w) * 64 + lane;
+        int ea = 0, eb = 0;
+        if constexpr (isf16(P)) {
+            if (kc < nb) {
+                ea = d.eA[(int64_t)I * nb + kc];
+                eb = d.eB[(int64_t)kc * nb + J];
+            }
+        }
         if (nk == 0) continue;
         if (!counted) {
             counted = true;
@@ -448,11 +632,10 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             const int base = w == 0 ? pre[0] : w == 1 ? pre[1] : w == 2 ? pre[2] : pre[3];
             if ((mine >> lane) & 1ull) {
                 const int pos = base + __popcll(mine & ((1ull << lane) - 1ull));
-                const int k = (w0 + w) * 64 + lane;
-                kl->k[pos] = k;
+                kl->k[pos] = kc;
                 if constexpr (isf16(P)) {
-                    kl->sa[pos] = (int16_t)f16_shift(d.eA[(int64_t)I * nb + k]);
-                    kl->sb[pos] = (int16_t)f16_shift(d.eB[(int64_t)k * nb + J]);
+                    kl->sa[pos] = (int16_t)f16_shift(ea);
+                    kl->sb[pos] = (int16_t)f16_shift(eb);
                 }
             }
         }
@@ -461,6 +644,42 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         // step t = (list entry t / NCH, k-chunk t % NCH); T is uniform, and
         // the loop control stays in scalar registers
         const int T = __builtin_amdgcn_readfirstlane(nk * NCH);
+        if constexpr (Dma<B, P, PRESPLIT>::ON) {
+            using D = Dma<B, P, PRESPLIT>;
+            constexpr int NS = D::NS, PW = D::PW, NARR = D::NARR;
+            // this wave's array (x3: A hi, A lo, B hi, B lo; one half: two
+            // waves per operand) and its first load in it
+            // (the wave index is uniform: readfirstlane keeps everything derived
+            // from it, the load resources and LDS bases, in scalar registers)
+            const int wu = __builtin_amdgcn_readfirstlane(w);
+            const int arr = NARR == 2 ? wu : (wu >> 1);
+            const bool isA = arr < NARR;
+            const int half = isA ? arr : arr - NARR;
+            const int first = NARR == 2 ? 0 : (wu & 1) * PW;
+            uint32_t voff[PW];
+#pragma unroll
+            for (int q = 0; q < PW; ++q) {
+                const int p = 64 * (first + q) + lane;
+                voff[q] = isA ? dma_src<true>(p) : dma_src<false>(p);
+            }
+            const uint16_t* base16 = (isA ? d.A16 : d.B16) + half * lo16;
+            const int lds0 = arr * D::ARR + first * 1024;
+            for (int t = -(NS - 1); t < T; ++t) {
+                if (t >= 0) {
+                    // this wave's loads of stage t have landed; after the
+                    // barrier every wave's have, and every wave is done with
+                    // step t - 1, whose stage the next loads overwrite
+                    wait_vm_lgkm0<PW * (NS - 2)>();
+                    __builtin_amdgcn_sched_barrier(0);
+                    __builtin_amdgcn_s_barrier();
+                    __builtin_amdgcn_sched_barrier(0);
+                    asm volatile("" ::: "memory");
+                }
+                const int cs = ((t % NS) + NS) % NS, ns = (t + NS - 1) % NS;
+                dma_step<P, NCH, PW>(smem + cs * D::STAGE, smem + ns * D::STAGE + lds0, kl, t, T, NS, base16, isA,
+                                     I, J, nb, voff, part, acc, lane, wr, wc);
+            }
+        } else {
         // MFMA on the chunk in LDS buffer bf.  No branches: the scheduler can
         // interleave it with the split and store of the next chunk.
         auto mma = [&](int bf) {
@@ -607,6 +826,7 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             ld(s1, t + 4);
             __builtin_amdgcn_sched_barrier(0);
         }
+        }
         // Drain the memory counters: no load issued in this segment is still
         // pending, so the wait analysis at the top of the next segment's loop
         // need not assume one (it would otherwise wait for every load in flight).
@@ -652,7 +872,9 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
 
     GLOBAL TC* Cg = (GLOBAL TC*)d.C + local * TS;
     constexpr int VC = 16 / (int)sizeof(TC);
-    double mx = 0.0, idem = 0.0;
+    // largest |value| in the stored type (exact: max commutes with widening)
+    TC mx = (TC)0;
+    double idem = 0.0;
     const GLOBAL TC* Xg = SP2 ? (const GLOBAL TC*)d.X + local * TS : nullptr;
     const int br = SP2 ? *branch : 0;
     for (int u = tid; u < B * B / VC; u += 256) {
@@ -672,7 +894,7 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         }
 #pragma unroll
         for (int j = 0; j < VC; ++j) {
-            mx = fmax(mx, fabs((double)v[j]));
+            mx = fmax(mx, fabs(v[j]));
             Cg[r * B + c + j] = v[j];
         }
     }
@@ -699,7 +921,7 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         if constexpr (SP2) idem += __shfl_down(idem, dd, 64);
     }
     if (lane == 0) {
-        red[0][w] = mx;
+        red[0][w] = (double)mx;
         red[1][w] = idem;
     }
     // canonical squared norm of the stored tile: wave 0, one (or two) columns per lane
@@ -717,9 +939,16 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
                 }
                 s = s + s2;  // tree step h = 64
             } else {
-                for (int r = 0; r < B; ++r) {
-                    const double a0 = (double)(TC)Cs[r * G::SC + lane];
-                    s = __fma_rn(a0, a0, s);
+                // rows in ascending order, their loads issued 16 at a time
+                for (int r0 = 0; r0 < B; r0 += 16) {
+                    CT v[16];
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) v[j] = Cs[(r0 + j) * G::SC + lane];
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        const double a0 = (double)(TC)v[j];
+                        s = __fma_rn(a0, a0, s);
+                    }
                 }
             }
         }
@@ -803,7 +1032,7 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
 // variants, and the persistent kernel (whose tile loop needs more registers),
 // keep the compiler's register choice.
 template <int B, int P, bool PS>
-constexpr int leaf_min_waves() { return (is16(P) && !PS && B <= 64) ? 4 : 1; }
+constexpr int leaf_min_waves() { return (is16(P) && B <= 64 && (!PS || Dma<B, P, PS>::ON)) ? 4 : 1; }
 
 // Static schedule: one block per tile; block x runs on XCD x mod 8 and takes
 // tile (x mod 8) * chunk + x / 8, so each XCD walks a contiguous tile range.
@@ -811,7 +1040,7 @@ template <int B, int P, typename TA, typename TC, bool SP2, bool PS>
 __global__ void __launch_bounds__(256, (leaf_min_waves<B, P, PS>())) k_leaf(const ProdDesc* __restrict__ desc, int nprod, int64_t total,
                                               int64_t chunk, const int* __restrict__ branch,
                                               const int* __restrict__ active) {
-    __shared__ __attribute__((aligned(16))) char smem[Geo<B, P>::SMEM];
+    __shared__ __attribute__((aligned(16))) char smem[leaf_smem<B, P, PS>()];
     __shared__ KList kl;
     __shared__ double red[2][4];
     if (active && *active == 0) return;
@@ -829,7 +1058,7 @@ __global__ void __launch_bounds__(256) k_leaf_queue(const ProdDesc* __restrict__
                                                     const uint32_t* __restrict__ order,
                                                     unsigned long long* __restrict__ queue,
                                                     const int* __restrict__ branch, const int* __restrict__ active) {
-    __shared__ __attribute__((aligned(16))) char smem[Geo<B, P>::SMEM];
+    __shared__ __attribute__((aligned(16))) char smem[leaf_smem<B, P, PS>()];
     __shared__ KList kl;
     __shared__ double red[2][4];
     __shared__ long long s_pos;
@@ -849,15 +1078,15 @@ __global__ void __launch_bounds__(256) k_leaf_queue(const ProdDesc* __restrict__
 // stride; the list and its count come from a tile-list kernel (SP2 steps,
 // the list schedule).  Leaf 64 is compiled for three blocks per CU (no
 // spills) and launched with that many.
-template <int B>
-constexpr int list_blocks_per_cu() { return B == 32 ? 4 : (B == 64 ? 3 : 1); }
+template <int B, int P, bool PS>
+constexpr int list_blocks_per_cu() { return Dma<B, P, PS>::ON ? 4 : (B == 32 ? 4 : (B == 64 ? 3 : 1)); }
 
 template <int B, int P, typename TA, typename TC, bool SP2, bool PS>
-__global__ void __launch_bounds__(256, (B == 64 ? list_blocks_per_cu<B>() : 1))
+__global__ void __launch_bounds__(256, (B == 64 ? list_blocks_per_cu<B, P, PS>() : 1))
     k_leaf_list(const ProdDesc* __restrict__ desc, int nprod, const uint32_t* __restrict__ list,
                 const unsigned* __restrict__ count, unsigned* __restrict__ queue, const int* __restrict__ branch,
                 const int* __restrict__ active) {
-    __shared__ __attribute__((aligned(16))) char smem[Geo<B, P>::SMEM];
+    __shared__ __attribute__((aligned(16))) char smem[leaf_smem<B, P, PS>()];
     __shared__ KList kl;
     __shared__ double red[2][4];
     __shared__ unsigned s_next;
@@ -889,7 +1118,7 @@ template <int B, int P, typename TA, typename TC, bool SP2, bool PS = false>
 hipError_t go(const ProdDesc* d_desc, const LeafPlan& p, hipStream_t s) {
     if (p.list) {
         // a grid of the resident blocks; the stride loop is correct for any grid
-        int64_t grid = (int64_t)num_cus() * list_blocks_per_cu<B>();
+        int64_t grid = (int64_t)num_cus() * list_blocks_per_cu<B, P, PS>();
         if (grid > p.total_tiles) grid = p.total_tiles < 1 ? 1 : p.total_tiles;
         hipLaunchKernelGGL((k_leaf_list<B, P, TA, TC, SP2, PS>), dim3((unsigned)grid), dim3(256), 0, s, d_desc,
                            p.count, p.list, p.list_count, p.list_queue, p.d_branch, p.d_active);

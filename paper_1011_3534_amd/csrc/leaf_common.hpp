@@ -7,6 +7,7 @@ namespace spamm {
 namespace leafk {
 
 #define GLOBAL __attribute__((address_space(1)))
+#define LDSP __attribute__((address_space(3)))
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));

@@ -24,18 +24,23 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline uint32_t pack2(uint16_t a, uint16_t b) { return (uint32_t)a | ((uint32_t)b << 16); }
 
-// One thread per 8 consecutive elements of the tile storage.
+// One thread per 8 consecutive elements of the split storage (tile-major,
+// row-major inside a tile); the FP32 source is read through the handle's
+// tile layout g (packed tiles, or the caller's array for a view).
 template <int B, int KIND>
-__global__ void __launch_bounds__(256) k_split(const float* __restrict__ tiles, const int8_t* __restrict__ texp,
-                                               int64_t nunits, uint16_t* __restrict__ hi,
-                                               uint16_t* __restrict__ lo, const int* __restrict__ active) {
+__global__ void __launch_bounds__(256) k_split(const float* __restrict__ tiles, TileGeo g, int64_t nb,
+                                               const int8_t* __restrict__ texp, int64_t nunits,
+                                               uint16_t* __restrict__ hi, uint16_t* __restrict__ lo,
+                                               const int* __restrict__ active) {
     if (active && *active == 0) return;
     const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (u >= nunits) return;
-    const GLOBAL f32x4* src = (const GLOBAL f32x4*)tiles + 2 * u;
+    const int64_t t = (u * 8) / (B * B);
+    const int e = (int)((u * 8) % (B * B));
+    const GLOBAL f32x4* src = (const GLOBAL f32x4*)(tiles + g.tile(t / nb, t % nb) + (int64_t)(e / B) * g.ld + e % B);
     const f32x4 x0 = src[0], x1 = src[1];
     int sh = 0;
-    if constexpr (KIND == kSplitF16) sh = f16_shift(texp[(u * 8) / (B * B)]);
+    if constexpr (KIND == kSplitF16) sh = f16_shift(texp[t]);
     float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
     uint16_t h[8], l[8];
 #pragma unroll
@@ -61,11 +66,11 @@ hipError_t split_b(const spamm_matrix* M, int kind, const int* active, hipStream
     uint16_t* hi = M->split;
     uint16_t* lo = M->split + elems;
     if (kind == kSplitF16)
-        hipLaunchKernelGGL((k_split<B, kSplitF16>), dim3(blocks), dim3(256), 0, s, (const float*)M->tiles, M->texp,
-                           nunits, hi, lo, active);
+        hipLaunchKernelGGL((k_split<B, kSplitF16>), dim3(blocks), dim3(256), 0, s, (const float*)M->tiles,
+                           tile_geo(M), M->nb, M->texp, nunits, hi, lo, active);
     else
-        hipLaunchKernelGGL((k_split<B, kSplitBF16>), dim3(blocks), dim3(256), 0, s, (const float*)M->tiles, M->texp,
-                           nunits, hi, lo, active);
+        hipLaunchKernelGGL((k_split<B, kSplitBF16>), dim3(blocks), dim3(256), 0, s, (const float*)M->tiles,
+                           tile_geo(M), M->nb, M->texp, nunits, hi, lo, active);
     return hipGetLastError();
 }
 

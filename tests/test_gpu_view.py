@@ -164,3 +164,61 @@ def test_view_full_size_product_equals_packed():
         assert stv["tasks"] == st["tasks"] == 104137
         d2, _ = sp.diff_norms(CV, C)
         assert d2 == 0.0
+
+
+@pytest.mark.parametrize("leaf,n,extra", [(64, 320, 0), (64, 384, 16), (32, 224, 0), (128, 384, 4)])
+def test_split_view_products_equal_view(leaf, n, extra):
+    # views with split tiles (spamm_build_view_ex): the 16-bit leaves read the
+    # split tiles (at leaf 64 straight into LDS) instead of splitting the
+    # array on the fly; the products are the same bits
+    print(f"[case] split view leaf={leaf} n={n} extra={extra}", flush=True)
+    a = si.algebraic_decay(n, 2.0, 44, np.float32)
+    b = si.exp_decay(n, 0.85, 45, np.float32)
+    da = _padded(a, extra) if extra else to_dev(a)
+    db = _padded(b, extra) if extra else to_dev(b)
+    VA, VB = sp.build(da, leaf, view=True), sp.build(db, leaf, view=True)
+    for prec in ("f16x3", "bf16x3", "f16", "bf16"):
+        SA, SB = sp.build(da, leaf, view=True, prec=prec), sp.build(db, leaf, view=True, prec=prec)
+        assert np.array_equal(SA.norms(0), VA.norms(0))
+        for tau in (0.0, 1e-5):
+            _same_bits(sp.multiply(SA, SB, tau, prec), sp.multiply(VA, VB, tau, prec))
+            _same_bits(sp.multiply(SA, SA, tau, prec), sp.multiply(VA, VA, tau, prec))
+        # one split operand and one without: split on the fly (same bits)
+        _same_bits(sp.multiply(SA, VB, 1e-5, prec), sp.multiply(VA, VB, 1e-5, prec))
+    # a rebuild of a split view on other values refreshes its split tiles
+    S = sp.build(da, leaf, view=True, prec="f16x3")
+    sp.build(db, leaf, out=S, view=True, prec="f16x3")
+    _same_bits(sp.multiply(S, S, 1e-5, "f16x3"), sp.multiply(VB, VB, 1e-5, "f16x3"))
+
+
+@pytest.mark.parametrize("schedule", ["list", "lpt", "static"])
+def test_split_view_batched_equals_view(schedule):
+    print(f"[case] split view batched schedule={schedule}", flush=True)
+    rng = np.random.default_rng(9)
+    sizes = [64, 512, 128, 1024, 320, 64 * 11]
+    mats = [si.exp_decay(n, float(rng.uniform(0.8, 0.97)), 700 + i, np.float32) for i, n in enumerate(sizes)]
+    taus = [float(10 ** rng.uniform(-7, -3)) for _ in sizes]
+    dev = [to_dev(a) for a in mats]
+    V = [sp.build(d, 64, view=True) for d in dev]
+    for prec in ("f16x3", "bf16"):
+        S = [sp.build(d, 64, view=True, prec=prec) for d in dev]
+        CS = sp.multiply_batched(S, S, taus, prec, schedule=schedule)
+        CV = sp.multiply_batched(V, V, taus, prec, schedule=schedule)
+        for cs, cv in zip(CS, CV):
+            _same_bits(cs, cv)
+
+
+@pytest.mark.parametrize("n,tau", [(8192, 1e-6), (16448, 1e-7)])
+def test_split_view_full_size_equals_view(n, tau):
+    """The bench workload (n = 8192, leaf 64, FP16x3) and nb = 257 (tiles whose
+    kept K span two 256-K segments), split view against view."""
+    print(f"[case] split view full size n={n} f16x3 tau={tau}", flush=True)
+    a = si.algebraic_workload(8192) if n == 8192 else None
+    da = to_dev(a) if a is not None else sp.generate_decay(si.algebraic_table(n, 1.5), 61, 0.5, 1.5, False)
+    V = sp.build(da, 64, view=True)
+    S = sp.build(da, 64, view=True, prec="f16x3")
+    CV = sp.multiply(V, V, tau, "f16x3")
+    CS = sp.multiply(S, S, tau, "f16x3")
+    d2, r2 = sp.diff_norms(CS, CV)
+    assert d2 == 0.0 and r2 > 0.0
+    assert np.array_equal(CS.task_list(), CV.task_list())
