@@ -398,6 +398,18 @@ spamm_status spamm_sp2(const spamm_matrix* H, int64_t n_occ, double tau, int32_t
  * exactly symmetric (checked: EINVAL otherwise).  Other arguments, results
  * and errors as spamm_sp2; the per-step task counts are those formed. */
 #define SPAMM_SP2_SYMMETRIC 1
+/* SPAMM_SP2_DROPPING: the block-dropping scheme that section 3 compares
+ * SpAMM with.  tau is then the drop threshold: every squaring is exact over
+ * the tiles present (a tile is absent once dropped, so it takes part in no
+ * product; the per-step task counts are the pairs of present tiles), and
+ * after each step every tile of the new iterate with squared norm
+ * S < fl(tau * tau) is dropped (set to zero, norm 0), so the trace that
+ * decides the next branch is that of the filtered iterate.  X_0 is not
+ * filtered.  Presence is the cull test at threshold 1e-150: a non-zero FP32
+ * tile has S >= 2^-298, so two present tiles always pass it.  Not combined
+ * with SPAMM_SP2_SYMMETRIC (EUNSUPPORTED): the two mirrored tiles' norms are
+ * summed in different orders and could be filtered differently. */
+#define SPAMM_SP2_DROPPING 2
 spamm_status spamm_sp2_ex(const spamm_matrix* H, int64_t n_occ, double tau, int32_t max_iter,
                           double idem_tol, spamm_leaf_prec prec, int32_t flags, void* stream,
                           spamm_matrix** P, spamm_sp2_log* log);

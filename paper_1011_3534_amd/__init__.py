@@ -465,14 +465,17 @@ def autotune_batched(dense, taus, prec: str = "f32", leaves=(32, 64, 128), max_r
 
 
 def sp2(H: Matrix, n_occ: int, tau: float, max_iter: int = 60, idem_tol: float = 1e-6,
-        prec: str = "f32", stream=None, symmetric: bool = False):
+        prec: str = "f32", stream=None, symmetric: bool = False, dropping: bool = False):
     """TC2 purification (section 3) with SpAMM squarings; returns (P, log dict).
 
-    symmetric: symmetric squarings (tiles I <= J formed, the others mirrored)."""
+    symmetric: symmetric squarings (tiles I <= J formed, the others mirrored).
+    dropping: the block-dropping scheme instead (tau is the drop threshold;
+    exact squarings over the tiles present, small tiles of each iterate dropped)."""
     h = ctypes.c_void_p()
     log = Sp2Log()
+    flags = (1 if symmetric else 0) | (2 if dropping else 0)
     code = lib().spamm_sp2_ex(H.handle, int(n_occ), float(tau), int(max_iter), float(idem_tol), LEAF[prec],
-                              1 if symmetric else 0, _stream(stream), ctypes.byref(h), ctypes.byref(log))
+                              flags, _stream(stream), ctypes.byref(h), ctypes.byref(log))
     if code not in (0, 6):
         _check(code)
     d = log.to_dict()

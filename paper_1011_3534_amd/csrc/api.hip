@@ -1080,13 +1080,20 @@ spamm_status spamm_sp2_ex(const spamm_matrix* H, int64_t n_occ, double tau, int3
                           spamm_sp2_log* log) {
     using namespace spamm;
     if (!H || !P) return set_error(SPAMM_EINVAL, "null argument");
-    if (flags & ~SPAMM_SP2_SYMMETRIC) return set_error(SPAMM_EINVAL, "unknown SP2 flags");
+    if (flags & ~(SPAMM_SP2_SYMMETRIC | SPAMM_SP2_DROPPING)) return set_error(SPAMM_EINVAL, "unknown SP2 flags");
     const bool symmetric = (flags & SPAMM_SP2_SYMMETRIC) != 0;
+    const bool dropping = (flags & SPAMM_SP2_DROPPING) != 0;
+    if (symmetric && dropping)
+        return set_error(SPAMM_EUNSUPPORTED, "the dropping scheme is not combined with symmetric squarings");
     if (n_occ < 0 || n_occ > H->n) return set_error(SPAMM_EINVAL, "n_occ outside [0, n]");
     if (max_iter < 1 || max_iter > SPAMM_SP2_MAX_ITER) return set_error(SPAMM_EINVAL, "max_iter outside [1, 256]");
     if (!(idem_tol >= 0.0) || !std::isfinite(idem_tol)) return set_error(SPAMM_EINVAL, "idem_tol must be >= 0");
     spamm_status v = check_operands(H, H, tau, prec);
     if (v != SPAMM_OK) return v;
+    // the dropping scheme's tau is the drop threshold; its squarings keep
+    // every pair of present (non-zero) tiles
+    const double tau_drop = dropping ? tau : 0.0;
+    if (dropping) tau = kPresentTau;
     if (prec == SPAMM_LEAF_F64 || H->dt != SPAMM_F32)
         return set_error(SPAMM_EUNSUPPORTED, "SP2 runs on FP32 tiles with FP32 or split 16-bit leaves");
     if (H->nb * H->nb > (int64_t)UINT32_MAX) return set_error(SPAMM_EUNSUPPORTED, "SP2 needs nb^2 < 2^32 tiles");
@@ -1204,6 +1211,10 @@ spamm_status spamm_sp2_ex(const spamm_matrix* H, int64_t n_occ, double tau, int3
         // written by their mirrors, never by a block of their own)
         r = enqueue_product(src, src, dst, tau, prec, cs, 0, 1, d_branch, d_active, dst->ps->desc,
                             (tau > 0.0 || symmetric) ? tile_list : nullptr, st);
+        if (r == SPAMM_OK && dropping) {
+            e = launch_sp2_drop(dst, part, tau_drop * tau_drop, d_active, cs);
+            if (e != hipSuccess) r = hip_error(e, "sp2 drop launch");
+        }
         if (r == SPAMM_OK) {
             e = launch_sp2_finalize(part, nb, &dst->ps->ctr->survivors[0][0], st, m, cs);
             if (e != hipSuccess) r = hip_error(e, "sp2 finalize launch");

@@ -411,6 +411,59 @@ hipError_t launch_sp2_init(const spamm_matrix* H, spamm_matrix* X, double* part,
     return hipGetLastError();
 }
 
+namespace {
+
+#ifndef GLOBAL
+#define GLOBAL __attribute__((address_space(1)))
+#endif
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Block dropping of the new iterate (section 3, scheme I): one wave per tile.
+// A tile whose squared norm (from the epilogue that wrote it) is below tau2
+// and that is not already known to be zero is zeroed, with its norm, its
+// exponent and, on the diagonal, its trace partial.  Its idempotency partial
+// stays: it measures the step's product, not the filtered iterate.
+template <int B>
+__global__ void __launch_bounds__(256) k_sp2_drop(float* __restrict__ X, double* __restrict__ S,
+                                                  int8_t* __restrict__ ex, double* __restrict__ part, int64_t nb,
+                                                  double tau2, const int* __restrict__ active) {
+    if (active && *active == 0) return;
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= nb * nb) return;
+    const int lane = threadIdx.x & 63;
+    if (!(S[t] < tau2) || ex[t] == -128) return;  // (the same words in every lane of the wave)
+    GLOBAL f32x4* x = (GLOBAL f32x4*)(X + t * (int64_t)B * B);
+    for (int u = lane; u < B * B / 4; u += 64) x[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (lane == 0) {
+        S[t] = 0.0;
+        ex[t] = (int8_t)-128;
+        if (t / nb == t % nb) part[nb * nb + t / nb] = 0.0;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sp2_drop(spamm_matrix* X, double* part, double tau2, const int* active, hipStream_t s) {
+    const int64_t tiles = X->nb * X->nb;
+    const unsigned blocks = (unsigned)((tiles + 3) / 4);
+    switch (X->b) {
+        case 32:
+            hipLaunchKernelGGL(k_sp2_drop<32>, dim3(blocks), dim3(256), 0, s, (float*)X->tiles, X->norms, X->texp,
+                               part, X->nb, tau2, active);
+            break;
+        case 64:
+            hipLaunchKernelGGL(k_sp2_drop<64>, dim3(blocks), dim3(256), 0, s, (float*)X->tiles, X->norms, X->texp,
+                               part, X->nb, tau2, active);
+            break;
+        case 128:
+            hipLaunchKernelGGL(k_sp2_drop<128>, dim3(blocks), dim3(256), 0, s, (float*)X->tiles, X->norms, X->texp,
+                               part, X->nb, tau2, active);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_sp2_finalize(const double* part, int64_t nb, unsigned long long* survivors0, Sp2State* st,
                                int m, hipStream_t s) {
     hipLaunchKernelGGL(k_sp2_finalize, dim3(kFinBlocks), dim3(kFinThreads), 0, s, part, nb, survivors0, st, m,

@@ -26,6 +26,9 @@ __host__ __device__ inline uint32_t key_i(uint64_t k) { return (uint32_t)((k >> 
 __host__ __device__ inline uint32_t key_j(uint64_t k) { return (uint32_t)((k >> 19) & 0x7FFFF); }
 __host__ __device__ inline uint32_t key_k(uint64_t k) { return (uint32_t)(k & 0x7FFFF); }
 constexpr int64_t kMaxNb = (int64_t)1 << 19;
+// Cull threshold that keeps exactly the pairs of non-zero FP32 tiles: a
+// non-zero FP32 tile has S >= (2^-149)^2, so S_A S_B >= 2^-596 > 1e-300.
+constexpr double kPresentTau = 1e-150;
 
 // FP16 leaves: a tile whose largest |x| has binary exponent e (-128 for an
 // all-zero tile) is scaled by 2^f16_shift(e), which puts that largest value in
@@ -328,6 +331,9 @@ hipError_t launch_sp2_finalize(const double* part, int64_t nb, unsigned long lon
                                int m, hipStream_t s);
 hipError_t launch_energy(const spamm_matrix* P, const spamm_matrix* H, double* tile_part, double* out,
                          hipStream_t s);
+// Dropping scheme: zero the tiles of X with S < tau2 (norm 0, exponent -128,
+// diagonal trace partial 0); skipped once the SP2 state is inactive.
+hipError_t launch_sp2_drop(spamm_matrix* X, double* part, double tau2, const int* active, hipStream_t s);
 hipError_t launch_sp2_tiles(const ProdDesc* d_desc, int64_t nb, uint32_t* list, Sp2State* st, const int* active,
                             hipStream_t s);
 hipError_t launch_check_symmetric(const spamm_matrix* H, unsigned* flag, hipStream_t s);

@@ -160,3 +160,59 @@ def test_sp2_symmetric_rejects_unsymmetric_h():
         sp.sp2(H, 128, 1e-6, max_iter=5, symmetric=True)
     P, log = sp.sp2(H, 128, 1e-6, max_iter=5)              # the general squaring still runs
     assert log["iterations"] == 5
+
+
+@pytest.mark.parametrize("tau_d", [1e-3, 1e-5])
+def test_sp2_dropping_step_replay_matches_oracle(tau_d):
+    # the dropping scheme (section 3, scheme I): feed the GPU's stored X_k
+    # into one oracle dropping step; the pairs of present tiles are the same
+    # (exact count), as are the branch, trace and idempotency, and the tiles
+    # dropped from X_{k+1} (those whose norm is not within rounding of tau)
+    n, b, n_occ = 512, 32, 256
+    h = si.sp2_hamiltonian(n, 0.85, 7, np.float32)
+    H = sp.build(to_dev(h), b)
+    for k in (1, 5, 12):
+        print(f"[case] sp2 dropping replay tau_d={tau_d} k={k}", flush=True)
+        Pk, logk = sp.sp2(H, n_occ, tau_d, max_iter=k, idem_tol=0.0, dropping=True)
+        assert logk["status"] == "ENOCONV" and logk["result_step"] == k
+        xk = Pk.to_dense().cpu().numpy().astype(np.float64)
+        Pk1, logk1 = sp.sp2(H, n_occ, tau_d, max_iter=k + 1, idem_tol=0.0, dropping=True)
+        x_next, tr, idem, br, T = osp2.step_dropping(xk, n_occ, b, tau_d)
+        assert logk1["tasks"][k] == T
+        assert logk1["branch"][k] == br
+        assert abs(logk1["trace"][k] - tr) < 1e-9 * n
+        assert abs(logk1["idem"][k] - idem) < 1e-5 * max(idem, 1.0)
+        got = Pk1.to_dense().cpu().numpy().astype(np.float64)
+        S_or = oracle.tile_sqnorms(x_next, b)
+        S_gpu = Pk1.norms(0)
+        clear = np.abs(np.sqrt(oracle.tile_sqnorms(osp2.step(xk, n_occ, b, 0.0)[0], b)) - tau_d) > 1e-3 * tau_d
+        assert np.array_equal((S_gpu == 0.0)[clear], (S_or == 0.0)[clear])
+        assert np.all(S_gpu[S_or == 0.0][clear[S_or == 0.0]] == 0.0)
+        elem_clear = np.kron(clear, np.ones((b, b), dtype=bool))[:n, :n]
+        assert np.max(np.abs(got - x_next)[elem_clear]) < 1e-5
+
+
+def test_sp2_dropping_solve_matches_oracle():
+    # a whole dropping-scheme solve against the oracle's; at tau = 0 no tile
+    # is dropped and every squaring counts all nb^3 pairs, as exact TC2
+    n, b, n_occ = 512, 32, 256
+    h = si.sp2_hamiltonian(n, 0.85, 4, np.float32, gap=2.0, n_occ=n_occ)
+    H = sp.build(to_dev(h), b)
+    h64 = h.astype(np.float64)
+    print("[case] sp2 dropping solve tau_d=0", flush=True)
+    P0, log0 = sp.sp2(H, n_occ, 0.0, max_iter=100, idem_tol=1e-6, dropping=True)
+    assert log0["status"] == "OK"
+    assert all(t == (n // b) ** 3 for t in log0["tasks"][:log0["iterations"]])
+    _, logx = sp.sp2(H, n_occ, 0.0, max_iter=100, idem_tol=1e-6)
+    assert abs(log0["energy"] - logx["energy"]) < 1e-6 * abs(logx["energy"])
+    for tau_d in (1e-2, 1e-4):
+        print(f"[case] sp2 dropping solve tau_d={tau_d}", flush=True)
+        P, log = sp.sp2(H, n_occ, tau_d, max_iter=100, idem_tol=1e-6, dropping=True)
+        _, lo = osp2.sp2_dropping(h64, n_occ, b, tau_d, max_iter=100, tol=1e-6)
+        assert log["status"] == "OK"
+        assert abs(log["energy"] - lo["energy"]) < 1e-5 * abs(lo["energy"])
+        k = min(log["iterations"], lo["iterations"])
+        assert abs(np.mean(log["tasks"][:k]) - np.mean(lo["tasks"][:k])) <= 0.01 * np.mean(lo["tasks"][:k])
+    with pytest.raises(sp.SpammError) as e:
+        sp.sp2(H, n_occ, 1e-4, max_iter=4, symmetric=True, dropping=True)
+    assert e.value.status == "EUNSUPPORTED"
