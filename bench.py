@@ -118,7 +118,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 256 MiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--workload", default="algebraic8192",
-                    choices=["algebraic8192", "exp1024", "batched64", "sp2", "learned-tau", "depth-tau"],
+                    choices=["algebraic8192", "exp1024", "batched64", "sp2", "learned-tau", "depth-tau",
+                             "dropping"],
                     help="algebraic8192 (default): the headline line; the others measure the remaining "
                          "hot-path rows and print their own JSON line")
     ap.add_argument("--sp2-n", type=int, default=16384)
@@ -131,7 +132,7 @@ def main():
         sys.exit(2)
     if args.workload != "algebraic8192":
         {"exp1024": run_exp1024, "batched64": run_batched64, "sp2": run_sp2,
-         "learned-tau": run_learned_tau, "depth-tau": run_depth_tau}[args.workload](args)
+         "learned-tau": run_learned_tau, "depth-tau": run_depth_tau, "dropping": run_dropping}[args.workload](args)
         return
 
     import torch
@@ -460,6 +461,80 @@ def run_sp2(args):
                       "config": {"workload": f"SP2, h_ii~N(0,1), h_ij=-0.85^|i-j|, n={n}, n_occ=n/2, leaf 64, "
                                              f"max 60 steps in one hipGraph; '/sym': symmetric squarings"}}),
           flush=True)
+
+
+def _loglog_interp(x, xs, ys):
+    """y at x on the piecewise log-log line through (xs, ys) (xs ascending), or None outside."""
+    if not xs or x < xs[0] or x > xs[-1]:
+        return None
+    lx, lxs, lys = np.log(x), np.log(xs), np.log(ys)
+    return float(np.exp(np.interp(lx, lxs, lys)))
+
+
+def run_dropping(args):
+    """Section 3's comparison: TC2 with SpAMM squarings (scheme II) against TC2 with block
+    dropping (scheme I: exact squarings over the tiles present, tiles of each iterate below
+    tau dropped), the same 60 steps for every run, leaf 64, FP32 leaves.  Two model
+    Hamiltonians h_ii ~ N(0,1), h_ij = -lam^|i-j|: lam = 0.85 at n = 16384 (its tiles decay
+    by 0.85^64 ~ 3e-5 per tile, so both schemes keep nearly the same tridiagonal tile
+    structure), and lam = 0.99 at n = 8192 (0.99^64 ~ 0.53 per tile, closer to the paper's
+    4 x 4 blocks of slowly decaying matrices).  For each threshold: the relative energy
+    error against the exact (tau = 0) run and the average number of leaf products per step;
+    then dropping's products at SpAMM's energy errors (log-log interpolation of the dropping
+    curve) and the slopes of log dE against log tau."""
+    torch, sp = _setup()
+    import spamm_inputs as si
+    steps = 60
+    out = {"metric": METRIC, "workload": "dropping", "steps": steps, "families": {}}
+    for lam, n in ((0.85, args.sp2_n), (0.99, 8192)):
+        Hd = sp.generate_decay(-si.exp_table(n, lam), 0, 1.0, 1.0, False, "f32", si.sp2_diagonal(n, 4))
+        H = sp.build(Hd, 64)
+
+        def solve(tau, dropping):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P, lg = sp.sp2(H, n // 2, tau, max_iter=steps, idem_tol=0.0, prec="f32", dropping=dropping)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            del P
+            k = lg["iterations"]
+            return {"tau": tau, "ms": ms, "iterations": k, "energy": lg["energy"],
+                    "final_trace": lg["final_trace"], "last_idem": lg["idem"][k - 1],
+                    "tasks_per_step": float(np.mean(lg["tasks"][:k]))}
+
+        ref = solve(0.0, False)
+        log(f"lam={lam} n={n} exact TC2: E={ref['energy']:.12g}, {ref['tasks_per_step']:.0f} leaf products per "
+            f"step, {ref['ms']:.0f} ms")
+        curves = {}
+        for scheme, taus in (("spamm", [10.0 ** -k for k in range(1, 9)]),
+                             ("dropping", [10.0 ** -k for k in range(0, 7)])):
+            pts = []
+            for tau in taus:
+                r = solve(tau, scheme == "dropping")
+                r["dE_rel"] = abs(r["energy"] - ref["energy"]) / abs(ref["energy"])
+                pts.append(r)
+                log(f"lam={lam} {scheme} tau={tau:g}: dE={r['dE_rel']:.3e}, {r['tasks_per_step']:.0f} leaf "
+                    f"products per step, {r['ms']:.0f} ms")
+            curves[scheme] = pts
+        dp = sorted((p["dE_rel"], p["tasks_per_step"]) for p in curves["dropping"] if p["dE_rel"] > 0)
+        matched = []
+        for p in curves["spamm"]:
+            t_drop = _loglog_interp(p["dE_rel"], [a for a, _ in dp], [b for _, b in dp])
+            matched.append({"dE_rel": p["dE_rel"], "tau_spamm": p["tau"],
+                            "spamm_tasks_per_step": p["tasks_per_step"], "dropping_tasks_per_step": t_drop,
+                            "dropping_over_spamm": None if t_drop is None else t_drop / p["tasks_per_step"]})
+        slopes = {}
+        for scheme, pts in curves.items():
+            xy = [(np.log10(p["tau"]), np.log10(p["dE_rel"])) for p in pts if p["dE_rel"] > 1e-9]
+            if len(xy) >= 2:
+                slopes[scheme] = float(np.polyfit([a for a, _ in xy], [b for _, b in xy], 1)[0])
+        out["families"][f"lam{lam}_n{n}"] = {"lam": lam, "n": n, "n_occ": n // 2, "exact": ref, "curves": curves,
+                                             "matched": matched, "dE_vs_tau_slope_above_1e-9": slopes}
+        del H, Hd
+    out["config"] = {"workload": f"TC2 on h_ii~N(0,1), h_ij=-lam^|i-j| (lam=0.85, n={args.sp2_n}; lam=0.99, "
+                                 f"n=8192), n_occ=n/2, leaf 64, FP32 leaves, {steps} steps per solve; SpAMM "
+                                 f"squarings vs block dropping; leaf products are 64x64 MATMULs"}
+    print(json.dumps(out), flush=True)
 
 
 def run_learned_tau(args):
