@@ -71,7 +71,8 @@ def tau_grid(hi=1e-4, lo=1e-9):
 
 
 def cpu_baseline(a64, leaf, tau, seconds):
-    """The FP64 oracle's flat SpAMM timed on a bounded sample of C tile rows."""
+    """The FP64 oracle's flat SpAMM timed on a bounded sample of C tile rows (all host
+    threads), its plain recursion on one core, and the paper's 4 x 4 block count."""
     import oracle
     nb = a64.shape[0] // leaf
 
@@ -89,9 +90,23 @@ def cpu_baseline(a64, leaf, tau, seconds):
     _, T = oracle.spamm_flat(a64, a64, leaf, tau, rows=(r0, r0 + rows))
     dt = time.perf_counter() - t0
     flops = 2.0 * leaf ** 3 * T
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"C tile rows [{r0},{r0 + rows}) of {nb} ({T} leaf products, {dt:.1f} s, FP64, "
-                      f"norms of the whole operand included)"}
+    out = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"C tile rows [{r0},{r0 + rows}) of {nb} ({T} leaf products, {dt:.1f} s, FP64, "
+                     f"norms of the whole operand included)"}
+    # the plain recursion of Eq. (4) on one core (the oracle's recursion has
+    # no threads), over the whole product
+    t0 = time.perf_counter()
+    _, Tr, _, _ = oracle.spamm_recursive(a64, a64, leaf, tau)
+    dt = time.perf_counter() - t0
+    out["single_core_recursive"] = {"value": 2.0 * leaf ** 3 * Tr / dt / 1e12, "unit": "TFLOP/s", "cores": 1,
+                                    "seconds": round(dt, 2), "tasks": Tr, "sample": "the whole product"}
+    # the paper's cost measure as context: kept products of 4 x 4 blocks
+    # (hierarchical count from 4 x 4 block norms), 128 flops each
+    S4 = oracle.tile_sqnorms(a64, 4)
+    T4, _ = oracle.count_hierarchical(S4, S4, tau)
+    out["paper_count_b4"] = {"matmuls_4x4": T4, "flops": 128.0 * T4,
+                             "dense_matmuls_4x4": (a64.shape[0] // 4) ** 3}
+    return out
 
 
 def main():
@@ -122,9 +137,12 @@ def main():
                              "dropping"],
                     help="algebraic8192 (default): the headline line; the others measure the remaining "
                          "hot-path rows and print their own JSON line")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the build/cull rooflines and the learned-tau selection at n = 32768 "
+                         "(profiling runs of the headline step)")
     ap.add_argument("--sp2-n", type=int, default=16384)
     ap.add_argument("--learn-n", type=int, default=32768)
-    ap.add_argument("--train-matrices", type=int, default=500)
+    ap.add_argument("--train-matrices", type=int, default=1200)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library has no "
@@ -265,10 +283,116 @@ def main():
            "missed_target": {p: {"floor_rel_err": d["sweep"][-1][1]} for p, d in precs.items()
                              if d["found"] is None},
            "roofline": roof}
+    if not args.no_extras:
+        del E, precs, results
+        torch.cuda.empty_cache()
+        out["norm_build"], out["cull"] = build_and_cull(torch, sp, A_d, b, r["tau"], best, args.steps)
+        del A_d, A
+        torch.cuda.empty_cache()
+        out["cfg5_n32768"] = cfg5_selection(torch, sp, args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(a.astype(np.float64), b, r["tau"], args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+HBM_PEAK_GBS = 8000.0
+
+
+def build_and_cull(torch, sp, A_d, b, tau, prec, steps):
+    """HBM rate of the quadtree build and the cost of the two culls of one product.
+
+    Build: the view build reads n^2 FP32 values once (leaf norms only); the packed
+    build also writes the tile-major copy.  Cull: the direct leaf pass tests every leaf
+    triple (two FP64 norms per triple, mostly L2 hits, one 64-bit mask word written per
+    64 K of a C tile); the level-synchronous descent tests 8 children of every survivor
+    of the tier above (two norms each) and writes an 8-byte key per survivor, compacted by
+    prefix scans tier by tier.  Both give the same kept triples; bytes are algorithmic."""
+    n = A_d.shape[0]
+    nb = -(-n // b)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    V = sp.build(A_d, b, view=True)
+    P = sp.build(A_d, b)
+    builds = {}
+    for name, fn, nbytes in (("view", lambda: sp.build(A_d, b, out=V, view=True), 4.0 * n * n),
+                             ("packed", lambda: sp.build(A_d, b, out=P), 4.0 * n * n + 4.0 * (nb * b) ** 2)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(steps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        gbs = nbytes / ms / 1e6
+        builds[name] = {"ms": round(ms, 5), "bytes": nbytes, "gbs": round(gbs, 1),
+                        "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"n={n} {name} build {ms * 1e3:.1f} us, {gbs:.0f} GB/s")
+    C, st = sp.multiply(V, V, tau, prec, stats=True)
+    surv = st["survivors"]
+    L = st["levels"]
+    W = -(-nb // 64)
+    cands = sum(8 * surv[l + 1] for l in range(L))
+    culls = {}
+    for name, descent, nbytes, tests in (
+            ("direct_leaf_pass", False, 16.0 * nb ** 3 + 8.0 * nb * nb * W, nb ** 3),
+            ("level_synchronous_descent", True, 16.0 * cands + 8.0 * sum(surv[:L]), cands)):
+        for _ in range(3):
+            sp.multiply_timed(V, V, tau, prec, out=C, descent=descent)
+        ms = float(np.median([sp.multiply_timed(V, V, tau, prec, out=C, descent=descent)[1]["ms_cull"]
+                              for _ in range(steps)]))
+        gbs = nbytes / ms / 1e6
+        culls[name] = {"ms": round(ms, 5), "tests": int(tests), "bytes_alg": nbytes, "gbs": round(gbs, 1),
+                       "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "tests_per_s": tests / (ms * 1e-3)}
+        log(f"n={n} {name}: {ms * 1e3:.1f} us, {tests:.3g} tests, {gbs:.0f} GB/s (algorithmic)")
+    cull = {"n": n, "leaf": b, "tau": tau, "tasks": st["tasks"], "survivors_per_tier": surv[:L + 1], **culls,
+            "note": "norm reads of both culls are mostly L2 hits; frac_hbm relates the algorithmic bytes to 8 TB/s"}
+    return {"n": n, **builds}, cull
+
+
+def cfg5_selection(torch, sp, args):
+    """The learned threshold at n = 32768 (algebraic decay p = 1.5, leaf 64, FP32 leaves,
+    target 1e-6): network trained on samples of the training families (n <= 8192),
+    selection against bisection from scratch, and the build/cull figures at this size."""
+    import spamm_inputs as si
+    from paper_1011_3534_amd import tau_data
+    t0 = time.perf_counter()
+    recipes = si.tau_training_params(args.train_matrices, seed=10000, taus_per_matrix=20)
+    X, y, _ = tau_data.training_set(recipes)
+    data_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    model, losses = tau_data.train_model(X, y, epochs=300, batch=256, lr=1e-3)
+    train_s = time.perf_counter() - t0
+    samples = int(X.shape[0])
+    del X, y
+    log(f"learned tau: {samples} samples ({data_s:.1f} s), training {train_s:.1f} s")
+    n, target = 32768, 1e-6
+    Ad = sp.generate_decay(si.algebraic_table(n, 1.5), 5, 0.5, 1.5, False)
+    A = sp.build(Ad, 64)
+    out = {"n": n, "target": target, "samples": samples, "data_seconds": round(data_s, 2),
+           "train_seconds": round(train_s, 2), "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+    for name, mdl in (("learned", model), ("bisection", None)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        C, info = sp.tau_select(A, A, target, mdl, "f32", 0.05)
+        torch.cuda.synchronize()
+        info["seconds"] = round(time.perf_counter() - t0, 3)
+        info["first_tau_met"] = bool(info["fallback"] == 0)
+        out[name] = info
+        log(f"n={n} {name}: tau={info['tau']:.3e} err={info['rel_err']:.2e} evaluations={info['evaluations']} "
+            f"first tau {'met' if info['first_tau_met'] else 'missed'} ({info['err_pred']:.2e})")
+        del C
+    tau = out["learned"]["tau"]
+    for p in ("f32", "f16x3"):
+        C = sp.multiply(A, A, tau, p)
+        out[f"product_ms_{p}"] = round(_time(torch, lambda: sp.multiply(A, A, tau, p, out=C), 5, 1), 3)
+        del C
+    out["dense_fp32_gemm_ms"] = round(_time(torch, lambda: torch.matmul(Ad, Ad), 2, 1), 3)
+    del A
+    torch.cuda.empty_cache()
+    out["norm_build"], out["cull"] = build_and_cull(torch, sp, Ad, 64, tau, "f32", 5)
+    return out
 
 
 # --------------------------------------------------------------------------- other hot-path rows

@@ -270,6 +270,18 @@ spamm_status spamm_multiply_timed(const spamm_matrix* A, const spamm_matrix* B, 
                                   spamm_leaf_prec prec, void* stream, spamm_matrix** C,
                                   spamm_timing* t);
 
+/* spamm_multiply_timed with options.  SPAMM_TIMED_DESCENT: the cull
+ * descends level-synchronously from the root, tier by tier (each tier's
+ * survivors compacted by prefix scans), as a product with statistics does,
+ * instead of testing every leaf triple in one pass -- the same kept triples
+ * and the same result bits, for timing the descent itself.  flags = 0 is
+ * spamm_multiply_timed.  Errors: as spamm_multiply_timed; EINVAL for unknown
+ * flags. */
+#define SPAMM_TIMED_DESCENT 1
+spamm_status spamm_multiply_timed_ex(const spamm_matrix* A, const spamm_matrix* B, double tau,
+                                     spamm_leaf_prec prec, int32_t flags, void* stream, spamm_matrix** C,
+                                     spamm_timing* t);
+
 /* Leaf-product schedule. */
 typedef enum {
     SPAMM_SCHED_STATIC = 0,  /* one block per C tile, tiles split into 8 contiguous
@@ -474,9 +486,11 @@ spamm_status spamm_tau_predict(const spamm_matrix* A, const spamm_matrix* B, dou
 /* Threshold that meets the target, checked against the exact product (FP64
  * leaves at tau = 0): the starting tau -- the network's prediction for half
  * the target (m non-NULL), else 10 target ||A||_F ||B||_F -- is checked; if
- * its error exceeds the target, tau steps down (a quarter decade at a time
- * from a prediction, a decade at a time otherwise) until the target holds and
- * is then bisected in log10(tau) to resolution_decades.  *C (in/out as for spamm_multiply) holds the product at
+ * its error exceeds the target, tau steps down until the target holds (from
+ * a prediction by log10(err / target) + 0.1 decades, at least 0.1, since the
+ * error grows about in proportion to tau; a decade at a time otherwise) and
+ * is then bisected in log10(tau) to resolution_decades between the tau that
+ * met the target and the last one that missed.  *C (in/out as for spamm_multiply) holds the product at
  * the returned tau.  Syncs.  Errors: EINVAL, ENOMEM, EHIP, ENOCONV (no tau
  * within 12 decades met the target). */
 spamm_status spamm_tau_select(const spamm_matrix* A, const spamm_matrix* B, double target,

@@ -123,7 +123,8 @@ def bisect_tau(err_of_tau, target: float, tau_hi: float, resolution_decades: flo
     """Largest tau (within the resolution) with err_of_tau(tau) <= target.
 
     Starts from tau_hi; steps down a decade at a time to a tau that meets the
-    target, then bisects in log10(tau).  Returns (tau, err, evaluations)."""
+    target, then bisects in log10(tau) between it and the last tau that missed.
+    Returns (tau, err, evaluations)."""
     evals = 0
     e = err_of_tau(tau_hi)
     evals += 1
@@ -133,6 +134,7 @@ def bisect_tau(err_of_tau, target: float, tau_hi: float, resolution_decades: flo
     lo = hi
     e_lo = e
     for _ in range(max_down):
+        hi = lo
         lo -= 1.0
         e_lo = err_of_tau(10 ** lo)
         evals += 1

@@ -131,6 +131,7 @@ def lib():
         "spamm_multiply": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Stats)], i32),
         "spamm_multiply_ex": ([_VP, _VP, dbl, i32, i32, _VP, PP, ctypes.POINTER(Stats)], i32),
         "spamm_multiply_timed": ([_VP, _VP, dbl, i32, _VP, PP, ctypes.POINTER(Timing)], i32),
+        "spamm_multiply_timed_ex": ([_VP, _VP, dbl, i32, i32, _VP, PP, ctypes.POINTER(Timing)], i32),
         "spamm_multiply_batched": ([i32, PP, PP, ctypes.POINTER(dbl), i32, ctypes.POINTER(Tune), _VP, PP,
                                     ctypes.POINTER(Stats)], i32),
         "spamm_multiply_batched_noalloc": ([i32, PP, PP, ctypes.POINTER(dbl), i32, ctypes.POINTER(Tune), _VP,
@@ -380,12 +381,14 @@ def multiply(A: Matrix, B: Matrix, tau: float, prec: str = "f32", out: Matrix | 
 
 
 def multiply_timed(A: Matrix, B: Matrix, tau: float, prec: str = "f32", out: Matrix | None = None,
-                   stream=None):
-    """multiply with HIP-event phase timing; returns (C, timing dict in ms)."""
+                   stream=None, descent: bool = False):
+    """multiply with HIP-event phase timing; returns (C, timing dict in ms).
+
+    descent: the cull descends tier by tier from the root (same result)."""
     h = ctypes.c_void_p(out.handle.value if out is not None else None)
     t = Timing()
-    _check(lib().spamm_multiply_timed(A.handle, B.handle, float(tau), LEAF[prec], _stream(stream), ctypes.byref(h),
-                                      ctypes.byref(t)))
+    _check(lib().spamm_multiply_timed_ex(A.handle, B.handle, float(tau), LEAF[prec], 1 if descent else 0,
+                                         _stream(stream), ctypes.byref(h), ctypes.byref(t)))
     C = out if out is not None else Matrix(h)
     return C, t.to_dict()
 

@@ -620,8 +620,12 @@ spamm_status spamm_build(const void* dev_a, int64_t n, int64_t lda, spamm_dtype 
     return spamm_build_ex(dev_a, n, lda, dt, leaf, dt == SPAMM_F64 ? SPAMM_LEAF_F64 : SPAMM_LEAF_F32, stream, out);
 }
 
-spamm_status spamm_multiply_ex(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,
-                               int32_t tau_schedule, void* stream, spamm_matrix** C, spamm_stats* st) {
+namespace {
+// force_descent: the cull descends tier by tier from the root (the path a
+// product with statistics takes) even without statistics
+spamm_status multiply_impl(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,
+                           int32_t tau_schedule, void* stream, spamm_matrix** C, spamm_stats* st,
+                           bool force_descent) {
     if (!C) return set_error(SPAMM_EINVAL, "C is null");
     if (tau_schedule != SPAMM_TAU_FLAT && tau_schedule != SPAMM_TAU_DEPTH_SCALED)
         return set_error(SPAMM_EINVAL, "unknown tau schedule");
@@ -652,8 +656,8 @@ spamm_status spamm_multiply_ex(const spamm_matrix* A, const spamm_matrix* B, dou
     Cm->last_stream = s;
     spamm_status r = ensure_scratch(Cm, s);
     if (r == SPAMM_OK)
-        r = enqueue_product(A, B, Cm, tau, prec, s, st != nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
-                            tau_schedule == SPAMM_TAU_DEPTH_SCALED);
+        r = enqueue_product(A, B, Cm, tau, prec, s, st != nullptr || force_descent, 0, nullptr, nullptr, nullptr,
+                            nullptr, nullptr, tau_schedule == SPAMM_TAU_DEPTH_SCALED);
     if (r != SPAMM_OK) {
         if (fresh) release(Cm);
         return r;
@@ -670,6 +674,13 @@ spamm_status spamm_multiply_ex(const spamm_matrix* A, const spamm_matrix* B, dou
     return SPAMM_OK;
 }
 
+}  // namespace
+
+spamm_status spamm_multiply_ex(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,
+                               int32_t tau_schedule, void* stream, spamm_matrix** C, spamm_stats* st) {
+    return multiply_impl(A, B, tau, prec, tau_schedule, stream, C, st, false);
+}
+
 spamm_status spamm_multiply(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,
                             void* stream, spamm_matrix** C, spamm_stats* st) {
     return spamm_multiply_ex(A, B, tau, prec, SPAMM_TAU_FLAT, stream, C, st);
@@ -677,12 +688,20 @@ spamm_status spamm_multiply(const spamm_matrix* A, const spamm_matrix* B, double
 
 spamm_status spamm_multiply_timed(const spamm_matrix* A, const spamm_matrix* B, double tau, spamm_leaf_prec prec,
                                   void* stream, spamm_matrix** C, spamm_timing* t) {
+    return spamm_multiply_timed_ex(A, B, tau, prec, 0, stream, C, t);
+}
+
+spamm_status spamm_multiply_timed_ex(const spamm_matrix* A, const spamm_matrix* B, double tau,
+                                     spamm_leaf_prec prec, int32_t flags, void* stream, spamm_matrix** C,
+                                     spamm_timing* t) {
     if (!t) return set_error(SPAMM_EINVAL, "timing output is null");
+    if (flags & ~SPAMM_TIMED_DESCENT) return set_error(SPAMM_EINVAL, "unknown timing flags");
     static thread_local hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (!ev[0])
         for (auto& e : ev) SPAMM_HIP(hipEventCreate(&e));
     t_phase = ev;
-    spamm_status r = spamm_multiply(A, B, tau, prec, stream, C, nullptr);
+    spamm_status r = multiply_impl(A, B, tau, prec, SPAMM_TAU_FLAT, stream, C, nullptr,
+                                   (flags & SPAMM_TIMED_DESCENT) != 0);
     t_phase = nullptr;
     if (r != SPAMM_OK) return r;
     SPAMM_HIP(hipEventSynchronize(ev[3]));

@@ -429,8 +429,8 @@ spamm_status spamm_tau_select(const spamm_matrix* A, const spamm_matrix* B, doub
     spamm_status r;
     double tau0 = 0.0;
     // the network is asked for half the target so that a typical prediction
-    // lands inside it; a miss falls back in quarter-decade steps
-    const double step = m ? 0.25 : 1.0;
+    // lands inside it; a miss steps down towards the target (see below)
+    const double step = 1.0;
     if (m) {
         if ((r = spamm_tau_predict(A, B, 0.5 * target, m, stream, &tau0)) != SPAMM_OK) return r;
     } else {
@@ -466,12 +466,18 @@ spamm_status spamm_tau_select(const spamm_matrix* A, const spamm_matrix* B, doub
     int64_t tasks = t0;
     if (r == SPAMM_OK && e0 > target) {
         info->fallback = 1;
-        // step down a decade at a time, then bisect in log10(tau)
+        // step down until the target holds, then bisect in log10(tau) between
+        // that tau and the last one that missed.  From a prediction each step
+        // aims at the target: the error grows about in proportion to tau (each
+        // culled product adds about its norm product), so the step is
+        // log10(err / target) plus a tenth of a decade (at least 0.1); with no
+        // model the steps are whole decades.
         double hi = std::log10(tau0), lo = hi, elo = e0;
         int64_t tlo = t0;
-        bool met = false;
-        for (int k = 0; k < (int)(12.0 / step) && r == SPAMM_OK; ++k) {
-            lo -= step;
+        bool met = false, last_at_lo = true;
+        for (int k = 0; k < 24 && r == SPAMM_OK && lo > std::log10(tau0) - 12.0; ++k) {
+            hi = lo;
+            lo -= m ? std::max(0.1, std::log10(elo / target) + 0.1) : step;
             r = err_at(std::pow(10.0, lo), &elo, &tlo);
             if (r == SPAMM_OK && elo <= target) {
                 met = true;
@@ -488,15 +494,17 @@ spamm_status spamm_tau_select(const spamm_matrix* A, const spamm_matrix* B, doub
                 lo = mid;
                 elo = em;
                 tlo = tm;
+                last_at_lo = true;
             } else {
                 hi = mid;
+                last_at_lo = false;
             }
         }
         tau = std::pow(10.0, lo);
         err = elo;
         tasks = tlo;
         // leave C holding the product at the returned tau
-        if (r == SPAMM_OK) r = err_at(tau, &err, &tasks);
+        if (r == SPAMM_OK && !last_at_lo) r = err_at(tau, &err, &tasks);
     }
     spamm_free(E);
     if (r != SPAMM_OK) return r;

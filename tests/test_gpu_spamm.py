@@ -459,6 +459,11 @@ def test_flat_start_cull_matches_full_descent(n, b, tau):
     assert np.array_equal(C1.to_dense().cpu().numpy(), C2.to_dense().cpu().numpy())
     for lv in range(C1.levels + 1):
         assert np.array_equal(C1.norms(lv), C2.norms(lv))
+    # the timed descent (no statistics, descent from the root): the same triples and bits
+    C3, t = sp.multiply_timed(A, A, tau, "f32", descent=True)
+    assert t["ms_cull"] > 0.0
+    assert np.array_equal(C3.task_list(), keys)
+    assert np.array_equal(C3.to_dense().cpu().numpy(), C1.to_dense().cpu().numpy())
 
 
 def test_flat_start_enumeration_beyond_direct_leaf_pass():

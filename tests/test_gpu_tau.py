@@ -136,3 +136,44 @@ def test_training_and_gain_over_no_network():
     # queried at half the target, the prediction keeps some products bisection would cull
     assert np.sum(t_l) <= 1.5 * np.sum(t_b)
     assert np.sum(t_l) < np.sum(t_c)
+
+
+def test_learned_tau_meets_1e6_on_held_out_matrices_with_n16384():
+    """Target 1e-6 with a network trained on >= 10k samples of the training
+    families (n <= 8192): held-out matrices of those families and an
+    algebraic p = 1.5 matrix at n = 16384 (beyond the training sizes).  Every
+    selection meets the target; the test reports how often the network's
+    first tau already does (no fallback) and the evaluations against
+    bisection from scratch."""
+    from paper_1011_3534_amd import tau_data
+    target = 1e-6
+    recipes = si.tau_training_params(1200, seed=10000, taus_per_matrix=20)
+    X, y, _ = tau_data.training_set(recipes)
+    print(f"[case] learned tau at 1e-6: {X.shape[0]} training samples", flush=True)
+    assert X.shape[0] >= 10000
+    model, losses = tau_data.train_model(X, y, epochs=300, batch=256, lr=1e-3)
+    del X, y
+    held = [(r, f"{r['family']} n={r['n']} b={r['leaf']}")
+            for r in si.tau_training_params(6, seed=55555, taus_per_matrix=1)]
+    held.append(({"family": "alg", "n": 16384, "leaf": 64, "param": 1.5, "lo": 0.5, "hi": 1.5,
+                  "symmetric": False, "seed": 5}, "alg p=1.5 n=16384 b=64"))
+    first_hits, ev_l, ev_b = 0, [], []
+    for r, name in held:
+        A = sp.generate_decay(si.recipe_table(r), r["seed"], r["lo"], r["hi"], r["symmetric"])
+        h = sp.build(A, r["leaf"])
+        _, il = sp.tau_select(h, h, target, model, "f32", 0.05)
+        _, ib = sp.tau_select(h, h, target, None, "f32", 0.05)
+        assert il["rel_err"] <= target and ib["rel_err"] <= target
+        first_hits += il["fallback"] == 0
+        ev_l.append(il["evaluations"])
+        ev_b.append(ib["evaluations"])
+        print(f"  {name}: first tau err {il['err_pred']:.2e} ({'met' if il['fallback'] == 0 else 'missed'}), "
+              f"evaluations {il['evaluations']} vs bisection {ib['evaluations']}; T {il['tasks']} vs "
+              f"{ib['tasks']}", flush=True)
+        if r["n"] == 16384:
+            assert il["evaluations"] <= 3
+        del A, h
+    print(f"  first tau met the target for {first_hits}/{len(held)}; evaluations {sum(ev_l)} vs {sum(ev_b)}",
+          flush=True)
+    assert first_hits >= len(held) // 2
+    assert sum(ev_l) < 0.5 * sum(ev_b)

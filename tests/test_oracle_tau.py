@@ -98,6 +98,7 @@ def test_bisection_finds_threshold():
     # err(tau) = tau / 7 meets target 1e-6 up to tau* = 7e-6
     tau, err, evals = tm.bisect_tau(lambda t: t / 7.0, 1e-6, 1.0, resolution_decades=0.01)
     assert tau <= 7e-6 and tau >= 7e-6 * 10 ** -0.01 and err <= 1e-6
-    assert evals < 25
+    # the start, six decade steps (1e-6 meets), seven halvings of [1e-6, 1e-5]
+    assert evals == 1 + 6 + 7
     # already met at the start
     assert tm.bisect_tau(lambda t: 0.0, 1e-6, 1e-3)[2] == 1
