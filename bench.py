@@ -134,7 +134,7 @@ def main():
                     help="run a 256 MiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--workload", default="algebraic8192",
                     choices=["algebraic8192", "exp1024", "batched64", "sp2", "learned-tau", "depth-tau",
-                             "dropping"],
+                             "dropping", "cull"],
                     help="algebraic8192 (default): the headline line; the others measure the remaining "
                          "hot-path rows and print their own JSON line")
     ap.add_argument("--no-extras", action="store_true",
@@ -150,7 +150,8 @@ def main():
         sys.exit(2)
     if args.workload != "algebraic8192":
         {"exp1024": run_exp1024, "batched64": run_batched64, "sp2": run_sp2,
-         "learned-tau": run_learned_tau, "depth-tau": run_depth_tau, "dropping": run_dropping}[args.workload](args)
+         "learned-tau": run_learned_tau, "depth-tau": run_depth_tau, "dropping": run_dropping,
+         "cull": run_cull}[args.workload](args)
         return
 
     import torch
@@ -585,6 +586,24 @@ def run_sp2(args):
                       "config": {"workload": f"SP2, h_ii~N(0,1), h_ij=-0.85^|i-j|, n={n}, n_occ=n/2, leaf 64, "
                                              f"max 60 steps in one hipGraph; '/sym': symmetric squarings"}}),
           flush=True)
+
+
+def run_cull(args):
+    """Quadtree build and the two culls (direct leaf pass, level-synchronous descent) at
+    the headline size (algebraic p = 2, n = 8192, tau = 1e-6) and at n = 32768 (algebraic
+    p = 1.5, seed 5, tau = 1.4e-8, the learned selection's threshold there)."""
+    torch, sp = _setup()
+    import spamm_inputs as si
+    out = {"metric": METRIC, "workload": "cull", "cases": []}
+    for n, p, seed, tau in ((8192, 2.0, 2, 1e-6), (32768, 1.5, 5, 1.4e-8)):
+        Ad = sp.generate_decay(si.algebraic_table(n, p), seed, 0.5, 1.5, False)
+        bld, cull = build_and_cull(torch, sp, Ad, 64, tau, "f32", args.steps)
+        out["cases"].append({"n": n, "p": p, "tau": tau, "norm_build": bld, "cull": cull})
+        del Ad
+        torch.cuda.empty_cache()
+    out["config"] = {"workload": "algebraic decay u/(|i-j|^p+1), leaf 64: n=8192 p=2 tau=1e-6; n=32768 p=1.5 "
+                                 "tau=1.4e-8"}
+    print(json.dumps(out), flush=True)
 
 
 def _loglog_interp(x, xs, ys):

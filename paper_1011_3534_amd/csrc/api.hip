@@ -324,6 +324,9 @@ static bool split_current(const spamm_matrix* M, int kind) {
 }
 
 // Shared by multiply and SP2: cull + leaf products + C pyramid, all enqueued.
+// want_bound: 0 = no statistics (a flat product may test its leaf triples in
+// one pass); 1 = statistics (the descent from the root, counts and the
+// culled-node bound); 2 = the descent from the root without the bound.
 spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm_matrix* C, double tau,
                              spamm_leaf_prec prec, hipStream_t s, int want_bound, int sp2, const int* d_branch,
                              const int* d_active, ProdDesc* d_desc_override, uint32_t* sp2_list,
@@ -389,7 +392,8 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
     int64_t items[kMaxLevels];
     tier_items(C, ps->front_cap, items);
     if (t_phase) SPAMM_HIP(hipEventRecord(t_phase[0], s));
-    SPAMM_HIP(launch_cull_ex(d_desc, cp, ps->mask, ps->front[0], ps->front[1], ps->ctr, want_bound, d_active, items, s));
+    SPAMM_HIP(launch_cull_ex(d_desc, cp, ps->mask, ps->front[0], ps->front[1], ps->ctr, want_bound == 1, d_active,
+                             items, s));
     LeafPlan lp;
     lp.count = 1;
     lp.total_tiles = C->nb * C->nb;
@@ -656,8 +660,8 @@ spamm_status multiply_impl(const spamm_matrix* A, const spamm_matrix* B, double 
     Cm->last_stream = s;
     spamm_status r = ensure_scratch(Cm, s);
     if (r == SPAMM_OK)
-        r = enqueue_product(A, B, Cm, tau, prec, s, st != nullptr || force_descent, 0, nullptr, nullptr, nullptr,
-                            nullptr, nullptr, tau_schedule == SPAMM_TAU_DEPTH_SCALED);
+        r = enqueue_product(A, B, Cm, tau, prec, s, st != nullptr ? 1 : (force_descent ? 2 : 0), 0, nullptr,
+                            nullptr, nullptr, nullptr, nullptr, tau_schedule == SPAMM_TAU_DEPTH_SCALED);
     if (r != SPAMM_OK) {
         if (fresh) release(Cm);
         return r;

@@ -122,7 +122,17 @@ __device__ void cull_pass(const ProdDesc* __restrict__ desc, int nprod, int l, c
             } else if (mine) {
                 atomicAdd(&ctr->survivors[m][c], mine);
             }
-            if (want_bound && bound > 0.0) atomicAdd(&ctr->culled_bound[m], bound);
+            // the culled-node bound: one atomic per wave of one product
+            // (per thread, the adds to one address serialise)
+            if (want_bound) {
+                if (uniform) {
+                    double sb = bound;
+                    for (int d = kWave / 2; d >= 1; d /= 2) sb += __shfl_xor(sb, d, kWave);
+                    if (lane == 0 && sb > 0.0) atomicAdd(&ctr->culled_bound[m0], sb);
+                } else if (bound > 0.0) {
+                    atomicAdd(&ctr->culled_bound[m], bound);
+                }
+            }
         }
         if (c == 0) continue;  // leaf tier: nothing to compact
         // block-wide exclusive scan of the per-thread child counts
