@@ -559,7 +559,7 @@ def run_sp2(args):
     res = {}
     for sym in (False, True):
       for tau in (0.0, 1e-4, 1e-5, 1e-6, 1e-7):
-        for prec in ("f32", "f16x3"):
+        for prec in ("f32", "f16x3", "bf16x3"):
             if tau == 0.0 and prec != "f32":
                 continue
             torch.cuda.synchronize()

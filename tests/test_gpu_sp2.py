@@ -20,7 +20,7 @@ def _torch_alloc():
     yield
 
 
-@pytest.mark.parametrize("prec", ["f32", "f16x3"])
+@pytest.mark.parametrize("prec", ["f32", "f16x3", "bf16x3"])
 def test_sp2_projector_matches_eigh(prec):
     print(f"[case] sp2 vs eigh prec={prec}", flush=True)
     n, b, n_occ = 512, 32, 256
@@ -31,8 +31,11 @@ def test_sp2_projector_matches_eigh(prec):
     w, v = np.linalg.eigh(h.astype(np.float64))
     pe = v[:, :n_occ] @ v[:, :n_occ].T
     pd = P.to_dense().cpu().numpy().astype(np.float64)
-    # FP32 purification: the converged projector carries ~10 u sqrt(n) (1.4e-5) elementwise
-    assert np.max(np.abs(pd - pe)) < 5e-5
+    # FP32 purification: the converged projector carries ~10 u sqrt(n) (1.4e-5) elementwise;
+    # BF16x3 leaves add 3 * 2^-16 (4.6e-5) per product term, and the iteration stops
+    # (stagnates) about five of those units from the projector
+    tol = 1e-3 if prec == "bf16x3" else 5e-5
+    assert np.max(np.abs(pd - pe)) < tol
     assert abs(np.trace(pd) - n_occ) < 1e-3
     assert abs(log["final_trace"] - np.trace(pd)) < 1e-6 * n
     assert abs(log["energy"] - w[:n_occ].sum()) < 1e-5 * abs(w[:n_occ].sum())
