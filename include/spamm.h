@@ -298,7 +298,11 @@ typedef enum {
 typedef struct {
     int32_t leaf;            /* leaf size the operands were built with (autotuner output) */
     int32_t schedule;        /* spamm_schedule                                           */
-    int32_t reserved[6];
+    int32_t split;           /* autotuner output: 1 = build the operands with split
+                                16-bit tiles (spamm_build_ex with the leaf precision),
+                                0 = plain builds (split while staging); ignored by
+                                spamm_multiply_batched, whose operands decide        */
+    int32_t reserved[5];
 } spamm_tune;
 
 /* count independent products C_m ~= A_m B_m in one pass: one cull over every
@@ -347,12 +351,13 @@ spamm_status spamm_multiply_batched_noalloc(int32_t count, const spamm_matrix* c
 /* ------------------------------------------------------------------ autotuner */
 
 #define SPAMM_TUNE_MAX_LEAVES 3
-#define SPAMM_TUNE_MAX_TRIALS 12
+#define SPAMM_TUNE_MAX_TRIALS 18
 typedef struct {
     int32_t trials;                              /* candidates timed (0 if from cache)     */
     int32_t from_cache;                          /* 1: answer read from the cache file     */
     int32_t leaf[SPAMM_TUNE_MAX_TRIALS];
     int32_t schedule[SPAMM_TUNE_MAX_TRIALS];
+    int32_t split[SPAMM_TUNE_MAX_TRIALS];        /* operands built with split tiles        */
     int32_t qualified[SPAMM_TUNE_MAX_TRIALS];    /* met max_rel_err                        */
     double ms[SPAMM_TUNE_MAX_TRIALS];            /* median of reps batched products        */
     double max_rel_err[SPAMM_TUNE_MAX_TRIALS];   /* worst product of the batch             */
@@ -363,16 +368,21 @@ typedef struct {
  * caller's dense operands (dev_a[m]: n[m] x n[m] row-major, leading
  * dimension n[m], element type dt).  For every leaf size in leaves[] (each
  * 32, 64 or 128; at most 3) the operands are built and the three schedules
- * are timed (median of reps products, HIP events on `stream`).  Because the leaf
- * size changes which block products are kept, a candidate qualifies only if
- * every product stays within max_rel_err (relative Frobenius error) of the
- * exact product, formed once with FP64 leaves at tau = 0.  The fastest
- * qualifying candidate is returned in *best and, if cache_path is non-NULL,
- * appended to that text file (one line per key: batch sizes, types, tau
- * range, target, candidates); a later call with the same key returns the
- * cached answer without trials.  report (optional) lists every trial.
- * Synchronises.  Errors: EINVAL (bad arguments, no candidate qualifies),
- * ENOMEM, EHIP. */
+ * are timed (median of reps products, HIP events on `stream`); with a 16-bit
+ * leaf precision and FP32 operands every leaf size is tried twice, with plain
+ * builds and with split tiles (spamm_build_ex), so up to 18 candidates.
+ * Because the leaf size changes which block products are kept, a candidate
+ * qualifies only if every product stays within max_rel_err (relative
+ * Frobenius error) of the exact product, formed once with FP64 leaves at
+ * tau = 0.  The fastest qualifying candidate is returned in *best and, if
+ * cache_path is non-NULL, appended to that text file, one line per key.  The
+ * key describes the batch by buckets: the count in octaves, the mean n in
+ * half-octaves and the kept fraction of the leaf triples at leaves[0] (one
+ * product with statistics, in octaves), with dt, prec, max_rel_err and the
+ * candidate leaves; a later call whose batch falls in the same buckets
+ * returns the cached answer after that one product, without trials.
+ * report (optional) lists every trial.  Synchronises.  Errors: EINVAL (bad
+ * arguments, no candidate qualifies), ENOMEM, EHIP. */
 spamm_status spamm_autotune_batched(int32_t count, const void* const* dev_a, const int64_t* n,
                                     spamm_dtype dt, const double* tau, spamm_leaf_prec prec,
                                     const int32_t* leaves, int32_t n_leaves, double max_rel_err,

@@ -47,19 +47,26 @@ SCHEDULE = {"static": 0, "lpt": 1, "list": 2}
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("leaf", ctypes.c_int32), ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+    _fields_ = [("leaf", ctypes.c_int32), ("schedule", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+TUNE_MAX_TRIALS = 18
 
 
 class TuneReport(ctypes.Structure):
-    _fields_ = [("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("leaf", ctypes.c_int32 * 12),
-                ("schedule", ctypes.c_int32 * 12), ("qualified", ctypes.c_int32 * 12), ("ms", ctypes.c_double * 12),
-                ("max_rel_err", ctypes.c_double * 12), ("best_ms", ctypes.c_double)]
+    _fields_ = [("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("leaf", ctypes.c_int32 * TUNE_MAX_TRIALS), ("schedule", ctypes.c_int32 * TUNE_MAX_TRIALS),
+                ("split", ctypes.c_int32 * TUNE_MAX_TRIALS), ("qualified", ctypes.c_int32 * TUNE_MAX_TRIALS),
+                ("ms", ctypes.c_double * TUNE_MAX_TRIALS), ("max_rel_err", ctypes.c_double * TUNE_MAX_TRIALS),
+                ("best_ms", ctypes.c_double)]
 
     def to_dict(self):
         sched = {v: k for k, v in SCHEDULE.items()}
         return {"from_cache": bool(self.from_cache), "best_ms": self.best_ms,
-                "trials": [{"leaf": self.leaf[i], "schedule": sched[self.schedule[i]], "ms": self.ms[i],
-                            "max_rel_err": self.max_rel_err[i], "qualified": bool(self.qualified[i])}
+                "trials": [{"leaf": self.leaf[i], "schedule": sched[self.schedule[i]], "split": bool(self.split[i]),
+                            "ms": self.ms[i], "max_rel_err": self.max_rel_err[i],
+                            "qualified": bool(self.qualified[i])}
                            for i in range(self.trials)]}
 
 
@@ -446,9 +453,10 @@ def multiply_batched_noalloc(As, Bs, taus, outs, prec: str = "f32", schedule: st
 
 def autotune_batched(dense, taus, prec: str = "f32", leaves=(32, 64, 128), max_rel_err: float = 1e-5,
                      reps: int = 3, cache_path: str | None = None, stream=None):
-    """Pick leaf size and schedule for the products A_m A_m of dense CUDA tensors.
+    """Pick leaf size, operand staging and schedule for the products A_m A_m of dense CUDA tensors.
 
-    Returns (tune dict {"leaf", "schedule"}, report dict)."""
+    Returns (tune dict {"leaf", "schedule", "split"}, report dict); split: build the
+    operands with split tiles (build(..., prec=prec))."""
     import torch
     count = len(dense)
     for a in dense:
@@ -464,7 +472,7 @@ def autotune_batched(dense, taus, prec: str = "f32", leaves=(32, 64, 128), max_r
                                         int(reps), cache_path.encode() if cache_path else None, _stream(stream),
                                         ctypes.byref(best), ctypes.byref(rep)))
     sched = {v: k for k, v in SCHEDULE.items()}
-    return {"leaf": best.leaf, "schedule": sched[best.schedule]}, rep.to_dict()
+    return {"leaf": best.leaf, "schedule": sched[best.schedule], "split": bool(best.split)}, rep.to_dict()
 
 
 def sp2(H: Matrix, n_occ: int, tau: float, max_iter: int = 60, idem_tol: float = 1e-6,
