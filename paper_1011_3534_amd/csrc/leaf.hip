@@ -221,9 +221,20 @@ __device__ inline void stage16_store(const Stage16<B, P>& st, char* buf, int tid
     }
 }
 
+// LDS slots (16 bytes) of a stage.  A rows hold 4 slots (32 k); slot s of
+// row r sits at s ^ dqa(r), so the 16 rows of an A fragment read spread over
+// all banks.  B rows hold 8 slots (64 columns); slot s of row k sits at
+// s ^ dfb(k), so the 8 rows of one 32-lane half of a transposing read (rows
+// k..k+3 and k+8..k+11) hit disjoint banks.
+__device__ inline int dqa(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & 1); }
+__device__ inline int dfb(int k) { return (((k >> 1) & 1) | (((k >> 3) & 1) << 1)) << 1; }
+
 // Register stage of one k-chunk, 16-bit leaves split on the fly from FP32
 // tiles (operands without split tiles): A units are 8 consecutive k of one
-// row, B units 8 consecutive k of one column (8 loads, coalesced over c).
+// row.  B units are 8 consecutive columns of one k-row at leaf 64 (two
+// 16-byte loads; B stays row-major in LDS in the layout of the split-operand
+// stages, and the MFMA fragments come from the transposing LDS read), and 8
+// consecutive k of one column at leaf 32 and 128 (8 loads, coalesced over c).
 template <int B, int P>
 struct Stage16c {
     using G = Geo<B, P>;
@@ -255,14 +266,28 @@ __device__ inline void stage16c_load(Stage16c<B, P>& st, __amdgpu_buffer_rsrc_t 
             st.a[u][4 + j] = v1[j];
         }
     }
+    if constexpr (B == 64) {
+        // leaf 64: B units are 8 consecutive columns of one k-row (two 16-byte
+        // loads), kept row-major in LDS (the MFMA reads transpose them)
+        const int k = tid >> 3, c = (tid & 7) * 8;
+        const int vo = (k * ldb + c) * 4;
+        const f32x4 v0 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rb, vo, 0, 0));
+        const f32x4 v1 = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rb, vo, 16, 0));
 #pragma unroll
-    for (int u = 0; u < S::U; ++u) {
-        const int unit = tid + u * 256;
-        if (S::PARTIAL && unit >= S::NU) break;
-        const int c = unit % B, k = (unit / B) * 8;
+        for (int j = 0; j < 4; ++j) {
+            st.b[0][j] = v0[j];
+            st.b[0][4 + j] = v1[j];
+        }
+    } else {
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            st.b[u][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, (k * ldb + c) * 4, j * ldb * 4, 0));
+        for (int u = 0; u < S::U; ++u) {
+            const int unit = tid + u * 256;
+            if (S::PARTIAL && unit >= S::NU) break;
+            const int c = unit % B, k = (unit / B) * 8;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                st.b[u][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, (k * ldb + c) * 4, j * ldb * 4, 0));
+        }
     }
 }
 
@@ -295,13 +320,21 @@ __device__ inline void stage16c_store(const Stage16c<B, P>& st, char* buf, int t
         const int ka = sw16(r, k);
         put(st.a[u], sa, As + r * G::SA + ka, As + G::A_ELEMS + r * G::SA + ka);
     }
+    if constexpr (B == 64) {
+        // row k of B, columns c..c+7 at slot (c / 8) ^ dfb(k) of the row (the
+        // layout the transposing fragment reads of stage_mma expect)
+        const int k = tid >> 3, cg = tid & 7;
+        const int ob = (k * 8 + (cg ^ dfb(k))) * 8;
+        put(st.b[0], sb, Bs + ob, Bs + G::B_ELEMS + ob);
+    } else {
 #pragma unroll
-    for (int u = 0; u < S::U; ++u) {
-        const int unit = tid + u * 256;
-        if (S::PARTIAL && unit >= S::NU) break;
-        const int c = unit % B, k = (unit / B) * 8;
-        const int kb = sw16(c, k);
-        put(st.b[u], sb, Bs + c * G::SB + kb, Bs + G::B_ELEMS + c * G::SB + kb);
+        for (int u = 0; u < S::U; ++u) {
+            const int unit = tid + u * 256;
+            if (S::PARTIAL && unit >= S::NU) break;
+            const int c = unit % B, k = (unit / B) * 8;
+            const int kb = sw16(c, k);
+            put(st.b[u], sb, Bs + c * G::SB + kb, Bs + G::B_ELEMS + c * G::SB + kb);
+        }
     }
 }
 
@@ -401,14 +434,6 @@ constexpr int leaf_smem() {
     return Dma<B, P, PS>::ON ? (Dma<B, P, PS>::SMEM > Geo<B, P>::C_BYTES ? Dma<B, P, PS>::SMEM : Geo<B, P>::C_BYTES)
                              : Geo<B, P>::SMEM;
 }
-
-// LDS slots (16 bytes) of a stage.  A rows hold 4 slots (32 k); slot s of
-// row r sits at s ^ dqa(r), so the 16 rows of an A fragment read spread over
-// all banks.  B rows hold 8 slots (64 columns); slot s of row k sits at
-// s ^ dfb(k), so the 8 rows of one 32-lane half of a transposing read (rows
-// k..k+3 and k+8..k+11) hit disjoint banks.
-__device__ inline int dqa(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & 1); }
-__device__ inline int dfb(int k) { return (((k >> 1) & 1) | (((k >> 3) & 1) << 1)) << 1; }
 
 // Byte offset, inside a tile chunk, of the 16 bytes that land at position p
 // of the array's LDS chunk (p = 64 * load + lane).
@@ -683,7 +708,9 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         // MFMA on the chunk in LDS buffer bf.  No branches: the scheduler can
         // interleave it with the split and store of the next chunk.
         auto mma = [&](int bf) {
-            if constexpr (P != kF64)
+            if constexpr (is16(P) && !PRESPLIT && B == 64)
+                stage_mma<P, Acc>(smem + bf * G::BUF_BYTES, part, lane, wr, wc);
+            else if constexpr (P != kF64)
                 chunk_mma<B, P, Acc>(smem + bf * G::BUF_BYTES, part, lane, wr, wc);
             else
                 chunk_mma<B, P, Acc>(smem + bf * G::BUF_BYTES, acc, lane, wr, wc);
