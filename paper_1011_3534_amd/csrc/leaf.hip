@@ -1141,6 +1141,367 @@ __global__ void __launch_bounds__(256, (B == 64 ? list_blocks_per_cu<B, P, PS>()
     }
 }
 
+// ---------------------------------------------------------------------------
+// 2 x 2 super-tiles of 16-bit leaf-64 products of operands with split tiles.
+//
+// One 256-thread block owns the C tiles (I0 + qi, J0 + qj), qi, qj in {0, 1},
+// and walks the union of their kept K in ascending order.  For each K the
+// split hi (+ lo) tiles of A_(I0+qi)K and B_K(J0+qj) that a kept product needs
+// go from memory straight into LDS (buffer loads with an LDS destination, no
+// registers), each once for the two products that share it, and wave
+// q = 2 qi + qj runs the MFMA of product (I0 + qi, K, J0 + qj), a whole 64 x 64
+// C tile, if that product is kept.  The stage layout is that of the one-tile
+// kernel per operand tile, so every 16 x 16 block sees the same MFMA sequence
+// (stage_mma), the same scale undo and the same epilogue arithmetic as in
+// leaf_tile: the results are the same bits.  Per kept product the operand
+// bytes halve when all four products of a K are kept.
+
+// Kept K of one mask segment of a super-tile: bit q of f marks product
+// (I0 + (q >> 1), K, J0 + (q & 1)) as kept; sa[i] / sb[j] are the FP16 scale
+// exponents of A_(I0+i)K and B_K(J0+j).
+struct QList {
+    int k[256];
+    uint8_t f[256];
+    int16_t sa[2][256];
+    int16_t sb[2][256];
+};
+
+template <int P>
+struct QDma {
+    static constexpr int NARR = isx3(P) ? 2 : 1;
+    static constexpr int PANEL = 4096;                // one operand tile's array of a chunk (bytes)
+    static constexpr int STAGE = 2 * NARR * 2 * PANEL;  // (A, B) x (hi, lo) x two tiles
+    static constexpr int NS = 2;
+    static constexpr int PW = STAGE / 1024 / 4;       // 1 KiB loads per wave per stage
+    static constexpr int SC = 68;                     // C staging stride (floats)
+    static constexpr int C_BYTES = 4 * 64 * SC * 4;
+    static constexpr int SMEM = NS * STAGE > C_BYTES ? NS * STAGE : C_BYTES;
+};
+
+// MFMA of one stage for the 64 x 64 tile of wave (qi, qj): panels of A tile qi
+// and B tile qj (per 16 x 16 block the products and order of stage_mma).
+template <int P, typename Acc>
+__device__ inline void qdma_mma(const char* __restrict__ st, Acc (&acc)[4][4], int lane, int qi, int qj) {
+    using D = QDma<P>;
+    constexpr int NARR = D::NARR, PN = D::PANEL;
+    using V8 = typename std::conditional<P == kBF16 || P == kBF16X3, bf16x8, f16x8>::type;
+    typedef short s16x4 __attribute__((ext_vector_type(4)));
+    const int g = lane >> 4, i16 = lane & 15;
+    // panels: A hi (two tiles), [A lo], B hi, [B lo]
+    const char* ah_p = st + qi * PN;
+    const char* al_p = st + (2 + qi) * PN;
+    const char* bh_p = st + (2 * NARR + qj) * PN;
+    const char* bl_p = st + (2 * NARR + 2 + qj) * PN;
+    V8 bh[4], bl[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int n = 16 * j + 4 * (i16 & 3);
+        s16x4 h2[2], l2[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = 8 * g + 4 * h + (i16 >> 2);
+            const int off = (k * 8 + ((n >> 3) ^ dfb(k))) * 16 + (n & 7) * 2;
+            h2[h] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((LDSP s16x4*)(bh_p + off));
+            if constexpr (NARR == 2) l2[h] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((LDSP s16x4*)(bl_p + off));
+        }
+        bh[j] = __builtin_bit_cast(V8, __builtin_shufflevector(h2[0], h2[1], 0, 1, 2, 3, 4, 5, 6, 7));
+        if constexpr (NARR == 2)
+            bl[j] = __builtin_bit_cast(V8, __builtin_shufflevector(l2[0], l2[1], 0, 1, 2, 3, 4, 5, 6, 7));
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = 16 * i + i16;
+        const int off = (r * 4 + (g ^ dqa(r))) * 16;
+        const V8 ah = *reinterpret_cast<const V8*>(ah_p + off);
+        V8 al;
+        if constexpr (NARR == 2) al = *reinterpret_cast<const V8*>(al_p + off);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if constexpr (P == kBF16 || P == kBF16X3) {
+                if constexpr (NARR == 2) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+                }
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+            } else {
+                if constexpr (NARR == 2) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[j], acc[i][j], 0, 0, 0);
+                }
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[j], acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// One step of the super-tile pipeline: this wave's loads of step t + 1 into
+// stage `nxt` (past the last step, or for operand tiles no kept product of
+// that step reads: empty resources, which load nothing), then for t >= 0 the
+// MFMA of stage `cur` if the wave's product is kept, and after a product's
+// last chunk the undo of its scales.  The restrict qualifiers tell the
+// compiler that the stage being read, the stage being loaded and the list
+// are disjoint, so it adds no wait of its own for the loads in flight.
+template <int P>
+__device__ __forceinline__ void qdma_step(const char* __restrict__ cur, char* __restrict__ nxt,
+                                          const QList* __restrict__ kl, int t, int T,
+                                          const uint16_t* __restrict__ base16, bool isA, int arr, int u0, int nu,
+                                          int I0, int J0, bool hasI1, bool hasJ1, int nb, const uint32_t (&voff)[4],
+                                          f32x4 (&part)[4][4], f32x4 (&acc)[4][4], int lane, int q, int qi, int qj) {
+    using D = QDma<P>;
+    constexpr int NCH = 2;
+    {
+        const int ti = t + 1;
+        const bool live = ti < T;
+        const int tt = live ? ti : T - 1;
+        const int e = tt / NCH, ch = tt % NCH;
+        const int k = __builtin_amdgcn_readfirstlane(kl->k[e]);
+        const unsigned f = live ? (unsigned)__builtin_amdgcn_readfirstlane((int)kl->f[e]) : 0u;
+        const uint32_t coff = isA ? (uint32_t)ch * 64u : (uint32_t)ch * 4096u;
+#pragma unroll
+        for (int uu = 0; uu < 2; ++uu) {
+            if (uu >= nu) break;
+            const int u = u0 + uu;
+            const bool need = isA ? (f & (u ? 0xCu : 0x3u)) != 0 : (f & (u ? 0xAu : 0x5u)) != 0;
+            const int It = isA ? ((u && hasI1) ? I0 + 1 : I0) : k;
+            const int Jt = isA ? k : ((u && hasJ1) ? J0 + 1 : J0);
+            const int64_t tile = (int64_t)It * nb + Jt;
+            const __amdgpu_buffer_rsrc_t r = rsrc((const char*)(base16 + tile * 4096) + coff, need ? 8192u - coff : 0u);
+            char* dst = nxt + (arr * 2 + u) * D::PANEL;
+#pragma unroll
+            for (int l = 0; l < 4; ++l)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (LDSP void*)(dst + l * 1024), 16, voff[l], 0, 0, 0);
+        }
+    }
+    if (t < 0) return;
+    const unsigned fl = (unsigned)__builtin_amdgcn_readfirstlane((int)kl->f[t / NCH]);
+    if ((fl >> q) & 1u) qdma_mma<P>(cur, part, lane, qi, qj);
+    if (t % NCH != NCH - 1) return;
+    const int e = t / NCH;
+    if constexpr (isf16(P)) {
+        const int un = __builtin_amdgcn_readfirstlane(-((int)kl->sa[qi][e] + (int)kl->sb[qj][e]));
+        if (un >= -126 && un <= 127) {
+            const float fs = ldexpf(1.0f, un);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[i][j][c] = __builtin_fmaf(part[i][j][c], fs, acc[i][j][c]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[i][j][c] += ldexpf(part[i][j][c], un);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] += part[i][j];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part[i][j] = f32x4{0, 0, 0, 0};
+}
+
+// One super-tile per block; block x runs on XCD x mod 8 and takes position
+// (x mod 8) * chunk + x / 8 of the super-tile grid (panel order inside).
+template <int P>
+__global__ void __launch_bounds__(256, 2) k_leaf_quad(const ProdDesc* __restrict__ desc, int64_t total, int64_t chunk) {
+    using D = QDma<P>;
+    constexpr int NCH = 2, NS = D::NS, PW = D::PW, NARR = D::NARR;
+    static_assert(NS == 2, "a step issues the loads of the next step");
+    __shared__ __attribute__((aligned(16))) char smem[D::SMEM];
+    __shared__ QList kl;
+    const int64_t x = blockIdx.x;
+    const int64_t pos = (x & 7) * chunk + (x >> 3);
+    if (pos >= total) return;
+    const ProdDesc& d = desc[0];
+    const int nb = d.nb, nq = (nb + 1) >> 1;
+    int QI, QJ;
+    block_order<4>(pos, nq, QI, QJ);
+    const int I0 = 2 * QI, J0 = 2 * QJ;
+    const bool hasI1 = I0 + 1 < nb, hasJ1 = J0 + 1 < nb;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int q = __builtin_amdgcn_readfirstlane(tid >> 6), qi = q >> 1, qj = q & 1;
+    const int I = I0 + qi, J = J0 + qj;
+    const bool mine = I < nb && J < nb;  // this wave's tile exists
+
+    // this wave's loads: panels of one array (x3: A hi, A lo, B hi, B lo; one
+    // half: A hi and B hi, two waves each) for both operand tiles u = 0, 1
+    const int arr = NARR == 2 ? q : (q >> 1);
+    const bool isA = arr < NARR;
+    const int half = isA ? arr : arr - NARR;  // hi or lo
+    const int u0 = NARR == 2 ? 0 : (q & 1), nu = NARR == 2 ? 2 : 1;
+    const int64_t lo16 = (int64_t)nb * nb * 4096;  // hi tiles -> lo tiles (elements)
+    const uint16_t* __restrict__ base16 = (isA ? d.A16 : d.B16) + half * lo16;
+    uint32_t voff[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const int p = 64 * l + lane;
+        voff[l] = isA ? dma_src<true>(p) : dma_src<false>(p);
+    }
+    static_assert(PW == 4 * (NARR == 2 ? 2 : 1), "one or two panels of four loads per wave");
+
+    f32x4 acc[4][4], part[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc[i][j] = f32x4{0, 0, 0, 0};
+            part[i][j] = f32x4{0, 0, 0, 0};
+        }
+
+    // mask rows of the four tiles (a missing tile reads the first tile's
+    // words and drops them: the loads stay unconditional scalar loads)
+    const int64_t loc[4] = {(int64_t)I0 * nb + J0, (int64_t)I0 * nb + (hasJ1 ? J0 + 1 : J0),
+                            (int64_t)(hasI1 ? I0 + 1 : I0) * nb + J0,
+                            (int64_t)(hasI1 ? I0 + 1 : I0) * nb + (hasJ1 ? J0 + 1 : J0)};
+    const bool has[4] = {true, hasJ1, hasI1, hasI1 && hasJ1};
+    const int W = d.W;
+    unsigned cnt = 0;  // bit t: tile t has a kept product
+    for (int w0 = 0; w0 < W; w0 += 4) {
+        // words w0..w0+3 of every tile; m[t]: word w0 + q of tile t
+        uint64_t uw[4], m[4];
+        int pre[4], nk = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int wi = w0 + j < W ? w0 + j : W - 1;
+            uw[j] = 0ull;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint64_t v = (has[t] && w0 + j < W) ? d.mask[loc[t] * W + wi] : 0ull;
+                uw[j] |= v;
+                cnt |= v != 0ull ? 1u << t : 0u;
+                if (j == 0) m[t] = v;
+                else if (j == q) m[t] = v;
+            }
+            pre[j] = nk;
+            nk += __popcll(uw[j]);
+        }
+        // the FP16 scale exponents of every candidate K of this wave's word,
+        // loaded with the mask words
+        const int kc = (w0 + q) * 64 + lane;
+        int ea0 = 0, ea1 = 0, eb0 = 0, eb1 = 0;
+        if constexpr (isf16(P)) {
+            if (kc < nb) {
+                ea0 = d.eA[(int64_t)I0 * nb + kc];
+                eb0 = d.eB[(int64_t)kc * nb + J0];
+                if (hasI1) ea1 = d.eA[(int64_t)(I0 + 1) * nb + kc];
+                if (hasJ1) eb1 = d.eB[(int64_t)kc * nb + J0 + 1];
+            }
+        }
+        if (nk == 0) continue;
+        {
+            // wave q lists the K of word w0 + q in ascending order
+            const uint64_t uu = q == 0 ? uw[0] : q == 1 ? uw[1] : q == 2 ? uw[2] : uw[3];
+            const int base = q == 0 ? pre[0] : q == 1 ? pre[1] : q == 2 ? pre[2] : pre[3];
+            if ((uu >> lane) & 1ull) {
+                const int p = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(uu >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)uu, 0u));
+                unsigned f = 0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) f |= (unsigned)((m[t] >> lane) & 1ull) << t;
+                kl.k[p] = kc;
+                kl.f[p] = (uint8_t)f;
+                if constexpr (isf16(P)) {
+                    kl.sa[0][p] = (int16_t)f16_shift(ea0);
+                    kl.sa[1][p] = (int16_t)f16_shift(ea1);
+                    kl.sb[0][p] = (int16_t)f16_shift(eb0);
+                    kl.sb[1][p] = (int16_t)f16_shift(eb1);
+                }
+            }
+        }
+        __syncthreads();
+
+        const int T = __builtin_amdgcn_readfirstlane(nk * NCH);
+        // step t = (list entry t / NCH, k-chunk t % NCH).  Each step waits for
+        // its own stage, then issues the loads of step t + 1 into the other
+        // stage (past the end: empty resources, which load nothing) and runs
+        // the MFMA of its product if kept; after a product's last chunk its
+        // fresh sum joins the tile sum with the scales undone (a product that
+        // is not kept left part at +0, and adding it changes nothing).
+        for (int t = -(NS - 1); t < T; ++t) {
+            if (t >= 0) {
+                wait_vm_lgkm0<PW * (NS - 2)>();
+                __builtin_amdgcn_sched_barrier(0);
+                __builtin_amdgcn_s_barrier();
+                __builtin_amdgcn_sched_barrier(0);
+                asm volatile("" ::: "memory");
+            }
+            const int cs = ((t % NS) + NS) % NS, ns = (t + NS - 1) % NS;
+            qdma_step<P>(smem + cs * D::STAGE, smem + ns * D::STAGE, &kl, t, T, base16, isA, arr, u0, nu, I0, J0,
+                         hasI1, hasJ1, nb, voff, part, acc, lane, q, qi, qj);
+        }
+        // no load of this segment is still in flight, every wave is done with
+        // the stages and the list
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+
+    // ---------------------------------------------------------------- epilogue
+    // (per wave, its own tile; the barriers are block-wide and unconditional)
+    const bool kept = (cnt >> q) & 1u;
+    const int64_t local = (int64_t)I * nb + J;
+    const bool zero_kept = mine && !kept && d.eC[local] == -128;
+    const bool write = mine && !zero_kept;
+    float* Cs = reinterpret_cast<float*>(smem) + q * 64 * D::SC;
+    if (write) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    Cs[(16 * i + 4 * (lane >> 4) + c) * D::SC + 16 * j + (lane & 15)] = acc[i][j][c];
+    }
+    __syncthreads();
+    if (write) {
+        GLOBAL float* Cg = (GLOBAL float*)d.C + local * 4096;
+        for (int v = lane; v < 1024; v += 64) {
+            const int r = v >> 4, c = (v & 15) * 4;
+            *reinterpret_cast<GLOBAL f32x4*>(Cg + r * 64 + c) = *reinterpret_cast<const f32x4*>(Cs + r * D::SC + c);
+        }
+        // canonical squared norm (lane = column, rows ascending, then the
+        // pairwise column tree) and the largest |value|
+        double s = 0.0;
+        float mx = 0.0f;
+        for (int r0 = 0; r0 < 64; r0 += 16) {
+            float v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = Cs[(r0 + j) * D::SC + lane];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const double a0 = (double)v[j];
+                s = __fma_rn(a0, a0, s);
+                mx = fmaxf(mx, fabsf(v[j]));
+            }
+        }
+        for (int dd = 32; dd >= 1; dd >>= 1) {
+            mx = fmaxf(mx, __shfl_xor(mx, dd, 64));
+            const double o = __shfl_down(s, dd, 64);
+            if (lane < dd) s = s + o;
+        }
+        if (lane == 0) {
+            d.SC[local] = s;
+            const double m2 = (double)mx;
+            int e = -128;
+            if (m2 > 0.0) {
+                e = ilogb(m2);
+                e = e < -127 ? -127 : (e > 127 ? 127 : e);
+            }
+            if (s != s) e = 127;
+            d.eC[local] = (int8_t)e;
+        }
+    } else if (mine && lane == 0) {
+        d.SC[local] = 0.0;
+    }
+    if (tid == 0 && cnt) atomicAdd(d.nonempty, (unsigned long long)__popc(cnt));
+}
+
 template <int B, int P, typename TA, typename TC, bool SP2, bool PS = false>
 hipError_t go(const ProdDesc* d_desc, const LeafPlan& p, hipStream_t s) {
     if (p.list) {
@@ -1160,6 +1521,19 @@ hipError_t go(const ProdDesc* d_desc, const LeafPlan& p, hipStream_t s) {
         hipLaunchKernelGGL((k_leaf_queue<B, P, TA, TC, SP2, PS>), dim3((unsigned)grid), dim3(256), 0, s, d_desc, p.count,
                            p.total_tiles, p.order, p.queue, p.d_branch, p.d_active);
         return hipGetLastError();
+    }
+    if constexpr (B == 64 && is16(P) && !SP2 && PS) {
+        if (p.count == 1) {
+            // a single product of split operands: 2 x 2 super-tiles
+            int64_t nb = (int64_t)llround(sqrt((double)p.total_tiles));
+            while (nb * nb > p.total_tiles) --nb;
+            while ((nb + 1) * (nb + 1) <= p.total_tiles) ++nb;
+            const int64_t nq = (nb + 1) / 2, quads = nq * nq;
+            if (quads == 0) return hipSuccess;
+            const int64_t chunk = (quads + 7) / 8;
+            hipLaunchKernelGGL((k_leaf_quad<P>), dim3((unsigned)(chunk * 8)), dim3(256), 0, s, d_desc, quads, chunk);
+            return hipGetLastError();
+        }
     }
     const int64_t chunk = (p.total_tiles + 7) / 8;
     const int64_t grid = chunk * 8;
