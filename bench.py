@@ -582,9 +582,36 @@ def run_sp2(args):
     e0 = res["f32@0"]["energy"]
     for k, v in res.items():
         v["dE_rel"] = abs(v["energy"] - e0) / abs(e0)
+    # the same H with its diagonal shifted by -10 / +10 on the two halves: a
+    # spectral gap of about 3.5 opens at N_occ and TC2 converges
+    del H
+    Hd = sp.generate_decay(-si.exp_table(n, 0.85), 0, 1.0, 1.0, False, "f32",
+                           si.sp2_diagonal(n, 4, gap=20.0, n_occ=n // 2))
+    H = sp.build(Hd, 64)
+    gapped = {}
+    for tau, prec in ((0.0, "f32"), (1e-6, "f32"), (1e-6, "f16x3"), (1e-6, "bf16x3")):
+        torch.cuda.synchronize()
+        e0e, e1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0e.record()
+        P, lg = sp.sp2(H, n // 2, tau, max_iter=60, idem_tol=1e-5, prec=prec)
+        e1e.record()
+        torch.cuda.synchronize()
+        gapped[f"{prec}@{tau:g}"] = {"ms": e0e.elapsed_time(e1e), "iterations": lg["iterations"],
+                                     "status": lg["status"], "converged": lg["converged"],
+                                     "final_trace": lg["final_trace"], "energy": lg["energy"],
+                                     "last_idem": lg["idem"][-1] if lg["idem"] else None,
+                                     "products_per_step": float(np.mean(lg["tasks"]))}
+        log(f"sp2 gapped {prec} tau={tau:g}: {gapped[f'{prec}@{tau:g}']['ms']:.1f} ms, {lg['iterations']} steps, "
+            f"converged {lg['converged']}, idem {lg['idem'][-1]:.2e}")
+        del P
+    eg = gapped["f32@0"]["energy"]
+    for v in gapped.values():
+        v["dE_rel"] = abs(v["energy"] - eg) / abs(eg)
     print(json.dumps({"metric": METRIC, "workload": "sp2", "n": n, "n_occ": n // 2, "results": res,
+                      "gapped": gapped,
                       "config": {"workload": f"SP2, h_ii~N(0,1), h_ij=-0.85^|i-j|, n={n}, n_occ=n/2, leaf 64, "
-                                             f"max 60 steps in one hipGraph; '/sym': symmetric squarings"}}),
+                                             f"max 60 steps in one hipGraph; '/sym': symmetric squarings; "
+                                             f"'gapped': h_ii shifted by -10 (i < n/2) / +10"}}),
           flush=True)
 
 

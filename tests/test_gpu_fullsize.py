@@ -118,6 +118,34 @@ def test_sp2_full_size_first_step():
         print(f"  symmetric={sym} T={T} branch={br}", flush=True)
 
 
+def test_sp2_full_size_gapped_converges():
+    # the SP2 workload's H with its diagonal shifted by -10 on the first n/2
+    # indices and +10 on the rest: the two halves' spectra (each about 13
+    # wide) separate, a gap of about 3.5 opens at N_occ, and TC2 must drive
+    # ||X^2 - X||_F below the tolerance at full size (n = 16384, leaf 64) with
+    # trace N_occ; the energy at tau = 1e-6 matches the tau = 0 solve
+    n, b, n_occ = 16384, 64, 8192
+    print(f"[case] sp2 n={n} gapped convergence", flush=True)
+    Hd = sp.generate_decay(-si.exp_table(n, 0.85), 0, 1.0, 1.0, False, "f32",
+                           si.sp2_diagonal(n, 4, gap=20.0, n_occ=n_occ))
+    H = sp.build(Hd, b)
+    del Hd
+    _, ref = sp.sp2(H, n_occ, 0.0, max_iter=60, idem_tol=1e-5, prec="f32")
+    assert ref["converged"] and ref["status"] == "OK"
+    for prec in ("f32", "f16x3"):
+        P, lg = sp.sp2(H, n_occ, 1e-6, max_iter=60, idem_tol=1e-5, prec=prec)
+        print(f"  {prec}: {lg['iterations']} steps, idem {lg['idem'][-1]:.3e}, trace {lg['final_trace']:.6f}, "
+              f"E {lg['energy']:.10g} (tau = 0: {ref['energy']:.10g}), products/step {np.mean(lg['tasks']):.0f}",
+              flush=True)
+        assert lg["converged"] and not lg["stagnated"] and lg["status"] == "OK"
+        assert lg["iterations"] < 60
+        assert lg["idem"][-1] <= 1e-5
+        assert abs(lg["final_trace"] - n_occ) < 1e-3
+        assert abs(lg["energy"] - ref["energy"]) < 1e-7 * abs(ref["energy"])
+        assert max(lg["tasks"]) < 0.01 * (n // b) ** 3
+        del P
+
+
 def test_batched_full_64_task_lists():
     # the 64-matrix batch (n ~ U{512..8192}, exponential decay, tau = 1e-6): one
     # batched build and one batched product with the list schedule; every
