@@ -125,9 +125,10 @@ def main():
     ap.add_argument("--presplit", action="store_true",
                     help="16-bit leaves: build the operand with its split hi/lo tiles (spamm_build_ex) "
                          "instead of splitting on the fly in the leaf kernel")
-    ap.add_argument("--build", default="view", choices=["view", "packed"],
+    ap.add_argument("--build", default="view", choices=["view", "packed", "view-split"],
                     help="how a step builds the operand: view (spamm_build_view: leaf norms only, the leaf "
-                         "kernels read the dense array) or packed (spamm_build: copy into tile-major storage)")
+                         "kernels read the dense array), packed (spamm_build: copy into tile-major storage) or "
+                         "view-split (spamm_build_view_ex: a view plus split 16-bit tiles, for 16-bit leaves)")
     ap.add_argument("--no-build-compare", action="store_true",
                     help="time only the --build mode (profiling runs: every leaf dispatch reads one layout)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -220,20 +221,21 @@ def main():
         # packed (with --presplit the packed build also writes the split
         # hi/lo tiles the 16-bit leaves then read); both give the same bits
         bp = p if args.presplit else None
-        Av = sp.build(A_d, b, view=True)
+        vsplit = args.build == "view-split" and p in ("f16x3", "bf16x3", "f16", "bf16")
+        Av = sp.build(A_d, b, view=True, prec=p if vsplit else None)
 
         def step(mode):
-            if mode == "view":
-                sp.build(A_d, b, out=Av, view=True)
+            if mode in ("view", "view-split"):
+                sp.build(A_d, b, out=Av, view=True, prec=p if vsplit else None)
                 sp.multiply(Av, Av, tau, p, out=C)
             else:
                 sp.build(A_d, b, out=A, prec=bp)
                 sp.multiply(A, A, tau, p, out=C)
 
         modes = {}
-        mode = "packed" if args.presplit else args.build
+        mode = "packed" if args.presplit else ("view-split" if vsplit else ("view" if args.build != "packed" else "packed"))
         other = "view" if mode == "packed" else "packed"
-        for mode_t in ((mode,) if args.no_build_compare else ("packed", "view")):
+        for mode_t in ((mode,) if args.no_build_compare else (other, mode)):
             for _ in range(args.warmup):
                 step(mode_t)
             torch.cuda.synchronize()
@@ -245,7 +247,7 @@ def main():
             modes[mode_t] = ev0.elapsed_time(ev1) / args.steps
         step_ms = modes[mode]
         modes.setdefault(other, None)
-        Ah = Av if mode == "view" else A
+        Ah = Av if mode in ("view", "view-split") else A
         phases = [sp.multiply_timed(Ah, Ah, tau, p, out=C)[1] for _ in range(args.steps)]
         leaf_ms = float(np.mean([ph["ms_leaf"] for ph in phases]))
         cull_ms = float(np.mean([ph["ms_cull"] for ph in phases]))
