@@ -191,6 +191,24 @@ def test_split_view_products_equal_view(leaf, n, extra):
     _same_bits(sp.multiply(S, S, 1e-5, "f16x3"), sp.multiply(VB, VB, 1e-5, "f16x3"))
 
 
+@pytest.mark.parametrize("n", [64, 100, 130, 190])
+def test_split_packed_small_and_ragged_equal_on_the_fly(n):
+    # packed builds with split tiles (spamm_build_ex) at one tile (nb = 1) and
+    # ragged sizes (zero-padded tiles, odd nb): a single product of split
+    # operands (leaf 64: 2 x 2 super-tiles, some of them cut by the edge) is
+    # the same bits as the product that splits the packed tiles on the fly
+    print(f"[case] split packed leaf=64 n={n}", flush=True)
+    a = si.algebraic_decay(n, 2.0, 46, np.float32)
+    b = si.exp_decay(n, 0.8, 47, np.float32)
+    da, db = to_dev(a), to_dev(b)
+    PA, PB = sp.build(da, 64), sp.build(db, 64)
+    for prec in ("f16x3", "bf16x3", "f16", "bf16"):
+        SA, SB = sp.build(da, 64, prec=prec), sp.build(db, 64, prec=prec)
+        for tau in (0.0, 1e-4):
+            _same_bits(sp.multiply(SA, SB, tau, prec), sp.multiply(PA, PB, tau, prec))
+            _same_bits(sp.multiply(SB, SA, tau, prec), sp.multiply(PB, PA, tau, prec))
+
+
 @pytest.mark.parametrize("schedule", ["list", "lpt", "static"])
 def test_split_view_batched_equals_view(schedule):
     print(f"[case] split view batched schedule={schedule}", flush=True)
