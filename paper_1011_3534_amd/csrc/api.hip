@@ -338,10 +338,18 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
     // the FP32 tiles on the fly
     const int kind = split_kind(prec);
     const bool presplit = split_current(A, kind) && split_current(B, kind);
+    // a flat threshold without per-tier statistics starts below the root
+    // (L >= 2); up to 2^27 leaf triples it tests every one in a single pass.
+    // Outside SP2 and without statistics, nothing reads that pass's counters
+    // or the count of non-empty C tiles, and no kernel updates them.
+    const bool flat = !depth_tau && !want_bound && C->L >= 2;
+    const bool direct = flat && C->nb * C->nb * C->nb <= ((int64_t)1 << 27);
+    const bool uncounted = direct && !sp2_list && !sp2 && !count_tasks;
     C->gen++;
     if (!d_desc) {
         ProdDesc d = make_desc(A, B, C, tau);
         d.depth_tau = depth_tau;
+        if (uncounted) d.nonempty = nullptr;
         if (!ps->desc_valid || std::memcmp(&d, &ps->host_desc, sizeof d) != 0) {
             ps->host_desc = d;
             SPAMM_HIP(hipMemcpyAsync(ps->desc, &ps->host_desc, sizeof(ProdDesc), hipMemcpyHostToDevice, s));
@@ -355,7 +363,7 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
     cp.front_cap = ps->front_cap;
     cp.mask_words = C->nb * C->nb * ceil_div(C->nb, 64);
     cp.nonempty = nonempty_ctr(ps->ctr);
-    if (!depth_tau && !want_bound && C->L >= 2) {
+    if (flat) {
         // flat threshold, no per-tier statistics: start at the first tier of
         // at most 64^3 nodes (the tiers above are implied by the flat rule);
         // with L >= 2 that tier lies below the root, which the tier passes
@@ -366,7 +374,7 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
         cp.flat_m = C->lvl_m[fs];
         // up to 2^27 leaf triples, testing every one in a single pass (no
         // frontier, no atomics per triple) beats the descent
-        if (C->nb * C->nb * C->nb <= ((int64_t)1 << 27)) {
+        if (direct) {
             cp.leaf_direct = 1;
             cp.leaf_nb = C->nb;
             if (sp2_list) {
@@ -375,7 +383,7 @@ spamm_status enqueue_product(const spamm_matrix* A, const spamm_matrix* B, spamm
                 cp.sp2_list = sp2_list;
                 cp.sp2_state = sp2_state;
                 cp.skip_prep = true;
-            } else if (!sp2 && !count_tasks) {
+            } else if (uncounted) {
                 // a product without statistics: its counters are read by
                 // nothing (statistics take the full descent, which zeroes them)
                 cp.skip_prep = true;
@@ -967,7 +975,8 @@ spamm_status multiply_batched_impl(int32_t count, const spamm_matrix* const* A, 
     ProdDesc* d_desc = (ProdDesc*)(ws + o_desc);
     DevCounters* ctr = (DevCounters*)(ws + o_ctr);
     for (int m = 0; m < count; ++m) {
-        hd[m].nonempty = nonempty_ctr(ctr) + m;
+        // the non-empty tile counts are read only with statistics
+        hd[m].nonempty = st ? nonempty_ctr(ctr) + m : nullptr;
         out[m]->ps->desc_valid = false;
         out[m]->gen++;
     }
@@ -1200,6 +1209,7 @@ spamm_status spamm_sp2_ex(const spamm_matrix* H, int64_t n_occ, double tau, int3
         spamm_matrix* src = X[i];
         spamm_matrix* dst = X[1 - i];
         ProdDesc d = make_desc(src, src, dst, tau);
+        d.nonempty = nullptr;  // SP2 reports no per-product tile counts
         d.sym_upper = symmetric;
         d.sp2_part = part;
         d.X = src->tiles;

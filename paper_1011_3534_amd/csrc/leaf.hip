@@ -32,8 +32,11 @@ struct Geo {
     static constexpr int NCH = B / KC;                                 // chunks per task
     // operand element in LDS
     using E = typename std::conditional<P == kF64, double, typename std::conditional<is16(P), uint16_t, float>::type>::type;
-    // row strides (elements); 16-bit rows are unpadded and swizzled (sw16)
-    static constexpr int SA = (P == kF64) ? KC + 2 : (is16(P) ? KC : KC + 4);
+    // row strides (elements); 16-bit rows are unpadded and swizzled (sw16).
+    // FP32 A rows are 34 words apart: the 16 rows of an MFMA fragment read
+    // at one k fall on 16 distinct banks (34 r mod 32 = 2 r), which a 36-word
+    // stride would map pairwise (r and r + 8) onto the same bank.
+    static constexpr int SA = is16(P) ? KC : KC + 2;
     static constexpr int SB = (P == kF64) ? B + 8 : (is16(P) ? KC : B + 16);
     static constexpr int ROWS_B = is16(P) ? B : KC;                                // B^T rows for 16-bit
     static constexpr int NARR = isx3(P) ? 2 : 1;                                   // hi (+ lo)
@@ -649,7 +652,7 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         if (nk == 0) continue;
         if (!counted) {
             counted = true;
-            if (tid == 0) atomicAdd(d.nonempty, 1ull);
+            if (tid == 0 && d.nonempty) atomicAdd(d.nonempty, 1ull);
         }
         {
             // wave w lists the K of word w0 + w in ascending order
@@ -1499,7 +1502,7 @@ __global__ void __launch_bounds__(256, 2) k_leaf_quad(const ProdDesc* __restrict
     } else if (mine && lane == 0) {
         d.SC[local] = 0.0;
     }
-    if (tid == 0 && cnt) atomicAdd(d.nonempty, (unsigned long long)__popc(cnt));
+    if (tid == 0 && cnt && d.nonempty) atomicAdd(d.nonempty, (unsigned long long)__popc(cnt));
 }
 
 template <int B, int P, typename TA, typename TC, bool SP2, bool PS = false>

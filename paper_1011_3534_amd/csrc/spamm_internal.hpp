@@ -105,7 +105,7 @@ struct ProdDesc {
     const void* X;            // SP2: the operand tiles X_m (== A == B)
     const uint16_t* A16;      // split 16-bit tiles of A and B: hi tiles, then lo
     const uint16_t* B16;      //   tiles at +nb^2 b^2 elements (16-bit leaves only)
-    unsigned long long* nonempty;  // count of C tiles with at least one kept product
+    unsigned long long* nonempty;  // count of C tiles with at least one kept product (null: not counted)
     int64_t lvl_off[kMaxLevels];
     int32_t lvl_m[kMaxLevels];
     int64_t tile_base;        // first global C-tile index of this product
