@@ -659,7 +659,10 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
             const uint64_t mine = w == 0 ? wd[0] : w == 1 ? wd[1] : w == 2 ? wd[2] : wd[3];
             const int base = w == 0 ? pre[0] : w == 1 ? pre[1] : w == 2 ? pre[2] : pre[3];
             if ((mine >> lane) & 1ull) {
-                const int pos = base + __popcll(mine & ((1ull << lane) - 1ull));
+                // set bits of the word below this lane (mbcnt: no 64-bit lane
+                // mask held in registers across the tile)
+                const int pos = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mine >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mine, 0u));
                 kl->k[pos] = kc;
                 if constexpr (isf16(P)) {
                     kl->sa[pos] = (int16_t)f16_shift(ea);
@@ -1058,11 +1061,14 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
 }
 
 // Static 16-bit leaves that split their operands while staging fit in 128
-// VGPRs, so four blocks share a CU (one wave per SIMD each); the other
-// variants, and the persistent kernel (whose tile loop needs more registers),
+// VGPRs, so four blocks share a CU (one wave per SIMD each).  So do static
+// FP32 leaves up to leaf 64 (40000 bytes of LDS at leaf 64).  The other
+// variants, and the persistent kernels (whose tile loop needs more registers),
 // keep the compiler's register choice.
 template <int B, int P, bool PS>
-constexpr int leaf_min_waves() { return (is16(P) && B <= 64 && (!PS || Dma<B, P, PS>::ON)) ? 4 : 1; }
+constexpr int leaf_min_waves() {
+    return ((is16(P) || P == kF32) && B <= 64 && (!PS || Dma<B, P, PS>::ON)) ? 4 : 1;
+}
 
 // Static schedule: one block per tile; block x runs on XCD x mod 8 and takes
 // tile (x mod 8) * chunk + x / 8, so each XCD walks a contiguous tile range.
