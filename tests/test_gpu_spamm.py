@@ -78,6 +78,12 @@ CASES = [
 ]
 
 
+def _nonempty(keys):
+    # C tiles with at least one kept leaf triple
+    I, J, _ = oracle.unpack_keys(keys)
+    return len(set(zip(I.tolist(), J.tolist())))
+
+
 def _operands(n, fam, f64):
     dt = np.float64 if f64 else np.float32
     if fam == "exp":
@@ -97,6 +103,7 @@ def test_multiply_matches_oracle(n, b, tau, prec, fam):
     got = C.task_list()
     assert np.array_equal(got, keys)
     assert st["tasks"] == len(keys)
+    assert st["nonempty_tiles"] == _nonempty(keys)
     T, kept = oracle.count_hierarchical(oracle.tile_sqnorms(a64, b), oracle.tile_sqnorms(b64, b), tau)
     assert st["survivors"] == kept.tolist()
     ref, _ = oracle.spamm_flat(a64, b64, b, tau)
@@ -137,6 +144,31 @@ def test_presplit_operands_match_split_on_the_fly(n, leaf, prec):
     sp.build(to_dev(a), leaf, out=A2)
     C5 = sp.multiply(A2, A2, 1e-6, prec)
     assert np.array_equal(C5.to_dense().cpu().numpy(), C1.to_dense().cpu().numpy())
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16x3"])
+def test_nonempty_count_after_products_without_statistics(prec):
+    # products without statistics skip the count of non-empty C tiles; a
+    # later product with statistics into the same handle (single or batched)
+    # still reports the oracle's count
+    _case(f"non-empty tile count after uncounted products, {prec}")
+    n, b = 1500, 64
+    a, bm = si.algebraic_decay(n, 2.0, 2, np.float32), si.algebraic_decay(n, 2.0, 5, np.float32)
+    A, B = sp.build(to_dev(a), b), sp.build(to_dev(bm), b)
+    SA, SB = oracle.tile_sqnorms(a.astype(np.float64), b), oracle.tile_sqnorms(bm.astype(np.float64), b)
+    C = sp.multiply(A, B, 1e-6, prec)
+    sp.multiply(A, B, 1e-3, prec, out=C)
+    _, st = sp.multiply(A, B, 1e-5, prec, out=C, stats=True)
+    assert st["nonempty_tiles"] == _nonempty(oracle.tasks_flat(SA, SB, 1e-5)[0])
+    sp.multiply(A, B, 1e-6, prec, out=C)
+    _, st = sp.multiply(A, B, 1e-2, prec, out=C, stats=True)
+    assert st["nonempty_tiles"] == _nonempty(oracle.tasks_flat(SA, SB, 1e-2)[0])
+    for schedule in ("static", "list", "lpt"):
+        Cs = sp.multiply_batched([A, B], [B, A], [1e-6, 1e-4], prec, schedule=schedule)
+        sp.multiply_batched([A, B], [B, A], [1e-3, 1e-7], prec, outs=Cs, schedule=schedule)
+        _, sts = sp.multiply_batched([A, B], [B, A], [1e-5, 1e-6], prec, outs=Cs, stats=True, schedule=schedule)
+        assert sts[0]["nonempty_tiles"] == _nonempty(oracle.tasks_flat(SA, SB, 1e-5)[0])
+        assert sts[1]["nonempty_tiles"] == _nonempty(oracle.tasks_flat(SB, SA, 1e-6)[0])
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16x3"])
