@@ -577,13 +577,23 @@ __device__ __forceinline__ void dma_step(const char* __restrict__ cur, char* __r
     }
 }
 
+// The thread index as a value the compiler cannot see through.  A persistent
+// loop over tiles then derives the per-thread offsets of each tile afresh
+// instead of holding them in registers across the loop, which made the leaf
+// 64 list kernel spill at four blocks per CU.
+__device__ inline int opaque_tid() {
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // One C tile from its kept K to its stored values and norm.  t is a global
 // schedule position (blocked = true: panel/block order inside each product)
-// or a global tile index (blocked = false: row-major).
+// or a global tile index (blocked = false: row-major); tid is threadIdx.x.
 template <int B, int P, typename TA, typename TC, bool SP2, bool PRESPLIT>
 __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int nprod, int64_t t, char* smem,
                                           KList* kl, double (*red)[4], const int* __restrict__ branch,
-                                          bool blocked) {
+                                          bool blocked, int tid) {
     using G = Geo<B, P>;
     using CT = typename G::CT;
     using Acc = typename std::conditional<P == kF64, f64x4, f32x4>::type;
@@ -599,7 +609,7 @@ __device__ __forceinline__ void leaf_tile(const ProdDesc* __restrict__ desc, int
         J = (int)((t - d.tile_base) % nb);
     }
     const int64_t local = (int64_t)I * nb + J;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+    const int lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
     const int64_t lo16 = (int64_t)nb * nb * B * B;  // hi tiles -> lo tiles
     constexpr int64_t TS = (int64_t)B * B;
     // Operand tiles, in bytes: A tile (I, k) at a_row + k*a_sk and B tile
@@ -1083,7 +1093,7 @@ __global__ void __launch_bounds__(256, (leaf_min_waves<B, P, PS>())) k_leaf(cons
     const int64_t x = blockIdx.x;
     const int64_t t = (x & 7) * chunk + (x >> 3);
     if (t >= total) return;
-    leaf_tile<B, P, TA, TC, SP2, PS>(desc, nprod, t, smem, &kl, red, branch, true);
+    leaf_tile<B, P, TA, TC, SP2, PS>(desc, nprod, t, smem, &kl, red, branch, true, (int)threadIdx.x);
 }
 
 // Persistent schedule: resident blocks pull positions from a queue counter
@@ -1106,16 +1116,18 @@ __global__ void __launch_bounds__(256) k_leaf_queue(const ProdDesc* __restrict__
         __syncthreads();
         if (pos >= total) break;
         leaf_tile<B, P, TA, TC, SP2, PS>(desc, nprod, order ? (int64_t)order[pos] : (int64_t)pos, smem, &kl, red,
-                                         branch, false);
+                                         branch, false, opaque_tid());
     }
 }
 
 // Resident blocks take the listed C tiles (global tile indices) in a static
 // stride; the list and its count come from a tile-list kernel (SP2 steps,
-// the list schedule).  Leaf 64 is compiled for three blocks per CU (no
-// spills) and launched with that many.
+// the list schedule).  Leaf 64 below FP64 is compiled for four blocks per CU
+// (no spills) and launched with that many (FP64: three).
 template <int B, int P, bool PS>
-constexpr int list_blocks_per_cu() { return Dma<B, P, PS>::ON ? 4 : (B == 32 ? 4 : (B == 64 ? 3 : 1)); }
+constexpr int list_blocks_per_cu() {
+    return Dma<B, P, PS>::ON ? 4 : (B == 32 ? 4 : (B == 64 ? (P == kF64 ? 3 : 4) : 1));
+}
 
 template <int B, int P, typename TA, typename TC, bool SP2, bool PS>
 __global__ void __launch_bounds__(256, (B == 64 ? list_blocks_per_cu<B, P, PS>() : 1))
@@ -1130,7 +1142,8 @@ __global__ void __launch_bounds__(256, (B == 64 ? list_blocks_per_cu<B, P, PS>()
     const int64_t n = (int64_t)*count;
     if (!queue) {
         for (int64_t i = blockIdx.x; i < n; i += gridDim.x)
-            leaf_tile<B, P, TA, TC, SP2, PS>(desc, nprod, (int64_t)list[i], smem, &kl, red, branch, false);
+            leaf_tile<B, P, TA, TC, SP2, PS>(desc, nprod, (int64_t)list[i], smem, &kl, red, branch, false,
+                                             opaque_tid());
         return;
     }
     // dynamic: each block pulls its next list position from the queue while
@@ -1143,7 +1156,7 @@ __global__ void __launch_bounds__(256, (B == 64 ? list_blocks_per_cu<B, P, PS>()
     __syncthreads();
     while (i < n) {
         if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
-        leaf_tile<B, P, TA, TC, SP2, PS>(desc, nprod, (int64_t)list[i], smem, &kl, red, branch, false);
+        leaf_tile<B, P, TA, TC, SP2, PS>(desc, nprod, (int64_t)list[i], smem, &kl, red, branch, false, opaque_tid());
         __syncthreads();
         i = s_next;
         __syncthreads();
