@@ -271,6 +271,13 @@ def main():
             "frac": round(achieved / PEAK_TFLOPS[best], 4), "traffic": leaf_traffic(best, b, n, r["tau"], r["build"]),
             "kernel": f"k_leaf<{b},{best}>", "hw_flop_mult": HW_MULT[best],
             "hw_frac": round(achieved * HW_MULT[best] / PEAK_TFLOPS[best], 4)}
+    # every leaf precision that met the target, each against its own MFMA peak
+    # (`roofline` above is the fastest one's)
+    leaf_roofs = {p: {"kernel": f"k_leaf<{b},{p}>", "achieved": round(res["leaf_tflops"], 3),
+                      "peak": PEAK_TFLOPS[p], "unit": "TFLOP/s", "frac": round(res["leaf_tflops"] / PEAK_TFLOPS[p], 4),
+                      "hw_frac": round(res["leaf_tflops"] * HW_MULT[p] / PEAK_TFLOPS[p], 4),
+                      "traffic": leaf_traffic(p, b, n, res["tau"], res["build"])}
+                  for p, res in results.items()}
     out = {"metric": METRIC, "value": round(r["step_tflops"], 3), "unit": "TFLOP/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["step_ms"], 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": best,
@@ -285,7 +292,7 @@ def main():
                           for p, res in results.items()},
            "missed_target": {p: {"floor_rel_err": d["sweep"][-1][1]} for p, d in precs.items()
                              if d["found"] is None},
-           "roofline": roof}
+           "roofline": roof, "leaf_rooflines": leaf_roofs}
     if not args.no_extras:
         del E, precs, results
         torch.cuda.empty_cache()
