@@ -1123,10 +1123,11 @@ __global__ void __launch_bounds__(256) k_leaf_queue(const ProdDesc* __restrict__
 // Resident blocks take the listed C tiles (global tile indices) in a static
 // stride; the list and its count come from a tile-list kernel (SP2 steps,
 // the list schedule).  Leaf 64 below FP64 is compiled for four blocks per CU
-// (no spills) and launched with that many (FP64: three).
+// (no spills) and launched with that many; FP64 for the two its 71.7 KB of
+// LDS allow.
 template <int B, int P, bool PS>
 constexpr int list_blocks_per_cu() {
-    return Dma<B, P, PS>::ON ? 4 : (B == 32 ? 4 : (B == 64 ? (P == kF64 ? 3 : 4) : 1));
+    return Dma<B, P, PS>::ON ? 4 : (B == 32 ? 4 : (B == 64 ? (P == kF64 ? 2 : 4) : 1));
 }
 
 template <int B, int P, typename TA, typename TC, bool SP2, bool PS>
